@@ -1,0 +1,135 @@
+"""Random turbulence phase screens (Eq. (9) eps_t, Eq. (10)), FP64 on the CPU.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The paper builds its turbulent screen by the spectral method: complex white
+noise is shaped by the square root of a phase spectrum and inverse Fourier
+transformed.  Eq. (10) models the spectrum as a step; the workloads use the
+Kolmogorov phase spectrum with the plane-wave Fried parameter of a slab of
+thickness dz_s, r0 = (0.423 k0^2 Cn^2 dz_s)^(-3/5) (textbook FFT phase-screen
+method); the step spectrum is available as an option.
+
+Normalisation: with spatial frequency f in cycles/m the phase spectrum is
+Phi(f) = 0.023 r0^(-5/3) f^(-11/3) and each FFT sample carries
+sqrt(Phi(f)) df, df = 1/L.  (Written with angular frequency kappa = 2 pi f
+and dkappa = 2 pi / L the constant is 0.023 (2 pi)^(5/3) = 0.49; using 0.023
+with kappa would make the structure function 25 times too small.)  This is
+what reproduces D(r) = 6.88 (r/r0)^(5/3).
+
+Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
+numbers: as easy as 1, 2, 3", SC'11), written here from its definition:
+ten rounds of two 32x32->64 multiplies with a Weyl-sequence key schedule.
+Counter = (column, row, pair index, 0), key = (seed low word, seed high word).
+Two uniforms (u + 1/2) 2^-32 from output words 0 and 1 feed one Box-Muller
+transform, giving c = z0 + i z1 for that spectral sample.  One complex draw
+gives two screens: the real part (even screen index) and the imaginary part
+(odd screen index) of sum_k c_k sqrt(Phi(f_k)) df e^{2 pi i f_k.x}.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Tuple
+
+import numpy as np
+
+PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+PHILOX_W = (0x9E3779B9, 0xBB67AE85)
+_MASK = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(ctr, key) -> Tuple[np.ndarray, ...]:
+    """Vectorised Philox4x32-10; ``ctr`` is 4 uint32 arrays, ``key`` 2 ints."""
+    c = [np.asarray(v, dtype=np.uint64) & _MASK for v in ctr]
+    k0 = np.uint64(key[0] & 0xFFFFFFFF)
+    k1 = np.uint64(key[1] & 0xFFFFFFFF)
+    m0 = np.uint64(PHILOX_M[0])
+    m1 = np.uint64(PHILOX_M[1])
+    for rnd in range(10):
+        if rnd > 0:
+            k0 = (k0 + np.uint64(PHILOX_W[0])) & _MASK
+            k1 = (k1 + np.uint64(PHILOX_W[1])) & _MASK
+        p0 = m0 * c[0]
+        p1 = m1 * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & _MASK
+        hi1, lo1 = p1 >> np.uint64(32), p1 & _MASK
+        c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+    return tuple(v.astype(np.uint32) for v in c)
+
+
+def uniform_open(u32: np.ndarray) -> np.ndarray:
+    """Map a 32-bit word to (0, 1): (u + 1/2) / 2^32."""
+    return (u32.astype(np.float64) + 0.5) * 2.0 ** -32
+
+
+def box_muller(u1: np.ndarray, u2: np.ndarray):
+    r = np.sqrt(-2.0 * np.log(u1))
+    return r * np.cos(2.0 * math.pi * u2), r * np.sin(2.0 * math.pi * u2)
+
+
+def white_noise(n: int, seed: int, pair: int) -> np.ndarray:
+    """Complex unit-variance-per-component noise c[row, col] of one draw."""
+    col = np.tile(np.arange(n, dtype=np.uint64), n)
+    row = np.repeat(np.arange(n, dtype=np.uint64), n)
+    zero = np.zeros(n * n, dtype=np.uint64)
+    pr = np.full(n * n, pair, dtype=np.uint64)
+    o = philox4x32_10((col, row, pr, zero), (seed & 0xFFFFFFFF, seed >> 32))
+    z0, z1 = box_muller(uniform_open(o[0]), uniform_open(o[1]))
+    return (z0 + 1j * z1).reshape(n, n)
+
+
+def fried_parameter(k0: float, cn2: float, dz_s: float) -> float:
+    return (0.423 * k0 ** 2 * cn2 * dz_s) ** (-3.0 / 5.0)
+
+
+def kolmogorov_amplitude(n: int, length: float, r0: float) -> np.ndarray:
+    """sqrt(Phi(f)) df on the FFT grid [row, col]; zero at f = 0."""
+    f = np.fft.fftfreq(n, d=length / n)
+    fr = np.sqrt(f[None, :] ** 2 + f[:, None] ** 2)
+    psd = np.zeros_like(fr)
+    nz = fr > 0
+    psd[nz] = 0.023 * r0 ** (-5.0 / 3.0) * fr[nz] ** (-11.0 / 3.0)
+    return np.sqrt(psd) / length
+
+
+def step_amplitude(n: int, length: float, tau: float, k_h: float) -> np.ndarray:
+    """Eq. (10) read as a low-pass step: sqrt(tau) for 0 < kappa <= k_h."""
+    k = 2.0 * math.pi * np.fft.fftfreq(n, d=length / n)
+    kap = np.sqrt(k[None, :] ** 2 + k[:, None] ** 2)
+    return np.where((kap > 0) & (kap <= k_h), math.sqrt(tau), 0.0)
+
+
+def screen_pair(n: int, length: float, amp: np.ndarray, seed: int,
+                pair: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Two phase screens [rad] from one draw: phi = N^2 IFFT2(c amp)."""
+    spec = white_noise(n, seed, pair) * amp
+    phi = np.fft.ifft2(spec) * (n * n)
+    return phi.real.copy(), phi.imag.copy()
+
+
+def instance_screens(inst) -> Dict[int, np.ndarray]:
+    """Kolmogorov screens of an instance keyed by the step they follow."""
+    if inst.n_screens <= 0:
+        return {}
+    k0 = 2.0 * math.pi / inst.medium.wavelength
+    r0 = fried_parameter(k0, inst.cn2, inst.screen_dz)
+    amp = kolmogorov_amplitude(inst.n, inst.length, r0)
+    steps = []
+    for s in range(1, inst.n_screens + 1):
+        steps.append(int(round((s - 0.5) * inst.screen_dz / inst.dz)) - 1)
+    out = {}
+    for p in range((inst.n_screens + 1) // 2):
+        re, im = screen_pair(inst.n, inst.length, amp, inst.seed, p)
+        out[steps[2 * p]] = re
+        if 2 * p + 1 < inst.n_screens:
+            out[steps[2 * p + 1]] = im
+    return out
+
+
+def structure_function(phi: np.ndarray, max_lag: int) -> np.ndarray:
+    """<(phi(x+r) - phi(x))^2> along both axes for lags 1..max_lag (periodic)."""
+    out = np.empty(max_lag)
+    for lag in range(1, max_lag + 1):
+        dx = np.roll(phi, -lag, axis=1) - phi
+        dy = np.roll(phi, -lag, axis=0) - phi
+        out[lag - 1] = 0.5 * (np.mean(dx ** 2) + np.mean(dy ** 2))
+    return out

@@ -1,0 +1,148 @@
+"""Pins of the oracle's hand-written discrete adjoint.
+
+The adjoint is checked three independent ways: dot-product identities of each
+sub-map, central finite differences of the loss in FP64, and reverse-mode
+autodiff (torch on the CPU, float64) of a separately written forward map.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import march as M
+from oracle import turbulence as T
+
+
+def _ip(a, b):
+    """Real inner product <a, b> = Re sum conj(a) b."""
+    return float(np.real(np.vdot(a, b)))
+
+
+def _small(terms, n=32, theta=None, sigma=0.1, power=60 * W.P_CR, dz=0.02):
+    return W.Instance(n=n, length=4e-3, dz=dz, n_steps=6,
+                      medium=W.Medium(terms=terms), w0=0.7e-3, power=power,
+                      sigma=sigma, seed=11, theta=theta)
+
+
+def test_diffraction_adjoint_dot_product():
+    n = 24
+    rng = np.random.default_rng(0)
+    u = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    v = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    p = M.propagator(n, 3e-3, 0.4, W.K0)
+    lhs = _ip(M.diffract(u, p), v)
+    rhs = _ip(u, M.diffract_adjoint(v, p))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("terms", [W.KPM, W.TERM_KERR | W.TERM_ANSATZ | W.TERM_MPA])
+def test_screen_adjoint_matches_linearisation(terms):
+    """<J d, lam> = <d, J^T lam> with J d from central differences of the
+    forward screen map, J^T the adjoint formula used by ``gradient``."""
+    inst = _small(terms, theta=tuple(W.THETA0))
+    scr = M.Screen.of(inst)
+    rng = np.random.default_rng(1)
+    n = 16
+    v = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) \
+        * math.sqrt(0.4 * W.I_A)
+    d = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    lam = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    h = 1e-6 * math.sqrt(W.I_A)
+    jd = (M.apply_screen(v + h * d, scr) - M.apply_screen(v - h * d, scr)) / (2 * h)
+    i = np.abs(v) ** 2
+    e, de = scr.dfactor(i)
+    jt = lam * np.conj(e + i * de) + np.conj(lam) * v * v * de
+    lhs, rhs = _ip(jd, lam), _ip(d, jt)
+    assert abs(lhs - rhs) < 1e-7 * (abs(lhs) + abs(rhs))
+
+
+def _loss_fn(target):
+    return lambda u: M.fluence_loss(u, target)
+
+
+def _case(terms, with_turb=False):
+    theta = tuple(np.array(W.THETA0) + W.random_theta(5, 0.1))
+    kw = {}
+    if with_turb:
+        terms |= W.TERM_TURB
+        kw = dict(cn2=3e-13, screen_dz=0.04, n_screens=3)
+    inst = dataclasses.replace(_small(terms, theta=theta), **kw)
+    u0 = W.initial_field(inst)
+    target = W.synthetic_target(inst, 3)
+    screens = T.instance_screens(inst) if with_turb else None
+    return inst, u0, target, screens
+
+
+@pytest.mark.parametrize("with_turb", [False, True])
+def test_gradient_matches_finite_differences(with_turb):
+    terms = W.KPM | W.TERM_ANSATZ
+    inst, u0, target, screens = _case(terms, with_turb)
+    loss, g_u0, g_th = M.gradient(u0, inst, screens=screens,
+                                  cotangent=_loss_fn(target))
+
+    def f(u, th):
+        r = M.march(u, inst, theta=th, screens=screens)
+        return M.fluence_loss(r.field, target)[0]
+
+    th0 = np.array(inst.theta)
+    for p in range(8):
+        h = 1e-6 * max(1.0, abs(th0[p]))
+        e = np.zeros(8)
+        e[p] = h
+        fd = (f(u0, th0 + e) - f(u0, th0 - e)) / (2 * h)
+        assert abs(fd - g_th[p]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g_th).max())
+    rng = np.random.default_rng(9)
+    for _ in range(3):
+        d = rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape)
+        h = 1e-6 * np.abs(u0).max() / np.abs(d).max()
+        fd = (f(u0 + h * d, th0) - f(u0 - h * d, th0)) / (2 * h)
+        an = _ip(g_u0, d)
+        assert abs(fd - an) <= 1e-6 * abs(fd)
+
+
+def _torch_forward(u0, inst, theta, screens, target):
+    """Independent float64 torch version of the same discrete map."""
+    n = inst.n
+    k = 2 * math.pi * torch.fft.fftfreq(n, d=inst.length / n, dtype=torch.float64)
+    k0 = 2 * math.pi / inst.medium.wavelength
+    prop = torch.exp(-1j * (k[None, :] ** 2 + k[:, None] ** 2) * inst.dz / (2 * k0))
+    m = inst.medium
+    kn = k0 * m.n2 * inst.dz
+    K = m.mpa_order
+    u = u0
+    for step in range(inst.n_steps):
+        v = torch.fft.ifft2(prop * torch.fft.fft2(u))
+        i = (v * v.conj()).real
+        x = i / m.i_ref
+        ph = kn * i - kn * m.i_ref * x ** K / (1 + x ** (K - 1))
+        den = 1 + x ** 4
+        re = sum(theta[p - 1] * x ** p for p in range(1, 5)) / den
+        im = sum(theta[3 + p] * x ** p for p in range(1, 5)) / den
+        ph = ph + kn * m.i_ref * re
+        la = -torch.log(1 + (K - 1) * m.beta_k * i ** (K - 1) * inst.dz) / (2 * (K - 1))
+        la = la - kn * m.i_ref * im
+        if screens and step in screens:
+            ph = ph + torch.from_numpy(screens[step])
+        u = v * torch.exp(la + 1j * ph)
+    inten = (u * u.conj()).real
+    tgt = torch.from_numpy(target)
+    return ((inten - tgt) ** 2).sum() / (tgt ** 2).sum()
+
+
+@pytest.mark.parametrize("with_turb", [False, True])
+def test_gradient_matches_independent_autodiff(with_turb):
+    terms = W.KPM | W.TERM_ANSATZ
+    inst, u0, target, screens = _case(terms, with_turb)
+    loss, g_u0, g_th = M.gradient(u0, inst, screens=screens,
+                                  cotangent=_loss_fn(target))
+    tu = torch.from_numpy(u0.copy()).requires_grad_(True)
+    tth = torch.tensor(np.array(inst.theta), dtype=torch.float64,
+                       requires_grad=True)
+    tl = _torch_forward(tu, inst, tth, screens, target)
+    tl.backward()
+    assert abs(tl.item() - loss) < 1e-12 * loss
+    assert M.rel_l2(g_u0, tu.grad.numpy()) < 1e-10
+    assert np.max(np.abs(g_th - tth.grad.numpy())) < 1e-10 * np.abs(g_th).max()

@@ -1,0 +1,250 @@
+"""Seeded synthetic inputs for the split-step march of the stationary NLSE.
+
+This module defines the medium constants, the grids, beams, step sizes and
+turbulence settings of the five workloads, and synthesises the initial
+Gaussian field of Eq. (7).  It holds none of the march's arithmetic: both the
+FP64 CPU oracle and the GPU library take what it produces as input, and
+neither is imported here.
+
+Readings of the paper that fix the numbers below (Math and Equations, Eq. (1),
+(3), (7); EL benchmarking):
+
+* Eq. (7) writes the beam as ``A exp(-(r/r_n)^2)`` and its power as
+  ``pi A r_n^2``.  With ``A`` a field amplitude the power of that profile is
+  ``pi A^2 r_n^2 / 2``; we take ``U = sqrt(I0) exp(-r^2/w0^2)`` with
+  ``I0 = 2P/(pi w0^2)`` and ``w0 = r_n``.
+* The critical power is the Marburger value for a Gaussian beam,
+  ``P_cr = 3.77 lambda^2 / (8 pi n0 n2)``, with ``n2 = 3.2e-19 cm^2/W``
+  (the paper quotes 4-7 GW for air without stating n2).
+* The multiphoton coefficient is chosen so that the MPA rate equals the Kerr
+  phase rate at the reference intensity ``I_a = 5e13 W/cm^2``:
+  ``beta_K I_a^(K-1) = k0 n2 I_a``.
+* Amplitude noise is multiplicative, ``(1 + sigma eta)`` with ``eta`` a unit
+  complex normal, after which the field is rescaled to the exact power.
+* Turbulence screens sit at slab mid-planes ``z_s = (s - 1/2) dz_s`` and are
+  applied at the end of the step that reaches ``z_s``.
+
+All lengths are in metres, powers in W, intensities in W/m^2.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+# ---------------------------------------------------------------- constants
+LAMBDA = 800e-9            # carrier wavelength [m]
+N0 = 1.0                   # linear refractive index of air
+N2 = 3.2e-23               # Kerr index [m^2/W]  (3.2e-19 cm^2/W)
+I_A = 5e17                 # reference intensity [W/m^2] (5e13 W/cm^2)
+K_MPA = 8                  # multiphoton order
+K0 = 2.0 * math.pi / LAMBDA
+P_CR = 3.77 * LAMBDA ** 2 / (8.0 * math.pi * N0 * N2)   # ~3.000 GW
+BETA_K = K0 * N2 * I_A ** (1 - (K_MPA - 1))              # ~1.6085e-122 SI
+
+# screen-term bit mask (same values as the C header)
+TERM_KERR = 1
+TERM_MPA = 2
+TERM_PLASMA = 4
+TERM_ANSATZ = 8
+TERM_TURB = 16
+
+SEED_BASE = 2306156780
+
+# Least-squares fit of the 8-parameter ansatz f_theta(x) = [sum_p th_p x^p +
+# i sum_p th_{4+p} x^p] / (1 + x^4) to the saturating-plasma index
+# -x^8/(1+x^7) (real part) and to the small-step MPA attenuation x^7/2
+# (imaginary part) on x in [0, 1]; written by tests/golden/make_theta0.py,
+# which a CPU test re-runs and compares with these values.
+THETA0 = (
+    0.26709402, -2.3841864, 6.2538822, -5.1148255,
+    -0.37834535, 3.1562125, -7.6877035, 5.8110478,
+)
+
+
+@dataclasses.dataclass
+class Medium:
+    """Medium and screen-term selection (Eq. (1), (3), (9))."""
+
+    wavelength: float = LAMBDA
+    n0: float = N0
+    n2: float = N2
+    mpa_order: int = K_MPA
+    beta_k: float = BETA_K
+    i_ref: float = I_A
+    terms: int = TERM_KERR
+
+
+@dataclasses.dataclass
+class Instance:
+    """One beam on one grid: everything needed to start a march."""
+
+    n: int                       # grid points per side (square grid)
+    length: float                # window side [m]
+    dz: float                    # z step [m]
+    n_steps: int
+    medium: Medium
+    w0: float                    # 1/e field radius [m]
+    power: float                 # beam power [W]
+    sigma: float                 # multiplicative noise level
+    seed: int
+    cn2: float = 0.0             # C_n^2 [m^-2/3]
+    screen_dz: float = 0.0       # spacing of turbulence screens [m]
+    n_screens: int = 0
+    theta: Optional[Sequence[float]] = None
+
+    @property
+    def dx(self) -> float:
+        return self.length / self.n
+
+    def screen_steps(self) -> List[int]:
+        """Step index after which each turbulence screen is applied."""
+        out = []
+        for s in range(1, self.n_screens + 1):
+            z_s = (s - 0.5) * self.screen_dz
+            out.append(int(round(z_s / self.dz)) - 1)
+        return out
+
+
+def grid_axis(n: int, length: float) -> np.ndarray:
+    """Cell-centred coordinates x_j = (j + 1/2 - n/2) dx."""
+    dx = length / n
+    return (np.arange(n) + 0.5 - n / 2) * dx
+
+
+def gaussian_beam(n: int, length: float, w0: float, power: float,
+                  sigma: float, seed: int) -> np.ndarray:
+    """Initial field U0 [sqrt(W/m^2)], complex128 [y, x] (Eq. (7)).
+
+    U0 = sqrt(I0) exp(-r^2/w0^2) (1 + sigma eta), eta ~ CN(0, 1), then scaled
+    so that sum |U0|^2 dx^2 equals ``power`` exactly.
+    """
+    x = grid_axis(n, length)
+    r2 = x[None, :] ** 2 + x[:, None] ** 2
+    i0 = 2.0 * power / (math.pi * w0 ** 2)
+    u = np.sqrt(i0) * np.exp(-r2 / w0 ** 2)
+    if sigma > 0.0:
+        rng = np.random.default_rng(seed)
+        xi = rng.standard_normal((2, n, n))
+        eta = (xi[0] + 1j * xi[1]) / math.sqrt(2.0)
+        u = u * (1.0 + sigma * eta)
+    u = u.astype(np.complex128)
+    dx = length / n
+    p_now = float(np.sum(np.abs(u) ** 2) * dx * dx)
+    return u * math.sqrt(power / p_now)
+
+
+def initial_field(inst: Instance) -> np.ndarray:
+    return gaussian_beam(inst.n, inst.length, inst.w0, inst.power,
+                         inst.sigma, inst.seed)
+
+
+def rayleigh_length(w0: float, wavelength: float = LAMBDA) -> float:
+    return math.pi * w0 ** 2 / wavelength
+
+
+# ----------------------------------------------------------------- configs
+def config1() -> List[Instance]:
+    """Plain SSFM, single 1 mm beam at 5 P_cr on 128^2, Kerr only."""
+    w0 = 1e-3
+    lz = 0.5 * rayleigh_length(w0)
+    n_steps = 200
+    return [Instance(n=128, length=8e-3, dz=lz / n_steps, n_steps=n_steps,
+                     medium=Medium(terms=TERM_KERR), w0=w0, power=5 * P_CR,
+                     sigma=0.05, seed=SEED_BASE + 1)]
+
+
+KPM = TERM_KERR | TERM_MPA | TERM_PLASMA
+
+
+def config2() -> List[Instance]:
+    """Multifilamentation: 1 cm beam at 100 P_cr on 1024^2, 2000 steps."""
+    return [Instance(n=1024, length=6e-2, dz=1e-2, n_steps=2000,
+                     medium=Medium(terms=KPM), w0=1e-2, power=100 * P_CR,
+                     sigma=0.10, seed=SEED_BASE + 2)]
+
+
+def config3(n_inst: int = 64) -> List[Instance]:
+    """Batched uneven instances with Kolmogorov turbulence screens."""
+    rng = np.random.default_rng(SEED_BASE + 3)
+    sizes = rng.choice(np.array([256, 512, 768, 1024]), size=n_inst)
+    powers = rng.uniform(20.0, 200.0, size=n_inst) * P_CR
+    cn2 = 10.0 ** rng.uniform(-15.0, -14.0, size=n_inst)
+    out = []
+    for i in range(n_inst):
+        out.append(Instance(
+            n=int(sizes[i]), length=6e-2, dz=0.1, n_steps=2000,
+            medium=Medium(terms=KPM | TERM_TURB), w0=1e-2,
+            power=float(powers[i]), sigma=0.0,
+            seed=SEED_BASE + 3 + 1000 * (i + 1), cn2=float(cn2[i]),
+            screen_dz=10.0, n_screens=20))
+    return out
+
+
+def config4_sparse() -> Instance:
+    """Sparse 256^2 grid with the 8-parameter ansatz, 500 steps over 3 m."""
+    return Instance(n=256, length=8e-3, dz=6e-3, n_steps=500,
+                    medium=Medium(terms=TERM_KERR | TERM_ANSATZ), w0=1e-3,
+                    power=5 * P_CR, sigma=0.0, seed=SEED_BASE + 4,
+                    theta=THETA0)
+
+
+def config4_dense() -> Instance:
+    """Dense 2048^2 reference (dx = 3.9 um) over the same 3 m."""
+    return Instance(n=2048, length=8e-3, dz=5e-4, n_steps=6000,
+                    medium=Medium(terms=KPM), w0=1e-3, power=5 * P_CR,
+                    sigma=0.0, seed=SEED_BASE + 4)
+
+
+def config4() -> List[Instance]:
+    return [config4_sparse()]
+
+
+def config5() -> List[Instance]:
+    """Large aperture: 2.5 cm beam at 1000 P_cr on 4096^2 over 1 km."""
+    return [Instance(n=4096, length=0.12, dz=0.2, n_steps=5000,
+                     medium=Medium(terms=KPM | TERM_ANSATZ | TERM_TURB),
+                     w0=2.5e-2, power=1000 * P_CR, sigma=0.05,
+                     seed=SEED_BASE + 5, cn2=5e-15, screen_dz=20.0,
+                     n_screens=50, theta=(0.0,) * 8)]
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
+
+
+def scaled(inst: Instance, n: int, n_steps: int) -> Instance:
+    """Same beam and medium on a smaller window-preserving grid (tests)."""
+    return dataclasses.replace(inst, n=n, n_steps=n_steps)
+
+
+def random_theta(seed: int, scale: float = 0.3) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return scale * rng.standard_normal(8)
+
+
+def random_field_like(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """Complex Gaussian array (directions, loss cotangents) [y, x]."""
+    rng = np.random.default_rng(seed)
+    xi = rng.standard_normal((2, n, n))
+    return scale * (xi[0] + 1j * xi[1])
+
+
+def synthetic_target(inst: Instance, seed: int) -> np.ndarray:
+    """A smooth positive fluence target [W/m^2] for loss tests.
+
+    A wider Gaussian of the same power, modulated by a seeded low-order
+    ripple; it stands in for a dense-grid reference fluence.
+    """
+    x = grid_axis(inst.n, inst.length)
+    r2 = x[None, :] ** 2 + x[:, None] ** 2
+    w = 1.3 * inst.w0
+    i0 = 2.0 * inst.power / (math.pi * w ** 2)
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-0.2, 0.2, size=4)
+    kx = 2 * math.pi / inst.length
+    ripple = (1 + a[0] * np.cos(3 * kx * x)[None, :]
+              + a[1] * np.cos(2 * kx * x)[:, None]
+              + a[2] * np.sin(5 * kx * x)[None, :] * np.sin(4 * kx * x)[:, None])
+    return i0 * np.exp(-2 * r2 / w ** 2) * np.clip(ripple, 0.2, None)
