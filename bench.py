@@ -1,0 +1,226 @@
+"""Throughput of the split-step march on one MI355X (grid-point . steps / s).
+
+Workload (default): the 1024 x 1024 multifilamentation beam (1 cm, 100 P_cr,
+Kerr + multiphoton absorption + saturating plasma, 10 % seeded noise),
+2000 z steps of 1 cm, complex64 with FP64 reductions.  One bench step is
+the whole differentiable march: forward with a checkpoint every 50 steps,
+the fluence-mismatch loss against a synthetic target, and the exact adjoint
+back to the input field (segment recompute included).  Grid-point . steps
+count each z step once.
+
+The JSON line also carries: the roofline of the dominant pass kernel
+(HIP-event timing of that kernel's launches on the library's stream), the
+same march with the complex128 instantiation of the kernels, forward-only
+throughput, parity against the oracle's stored samples of this workload,
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "grid-point·steps/s SSFM fwd+adjoint, FP32 vs FP64, at stated L2 error"
+
+
+def _desc_list(insts):
+    from paper_2306_15678_amd.march import desc_of
+    return [desc_of(i) for i in insts]
+
+
+def _timed(fn, steps, warmup, sync):
+    for _ in range(warmup):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) / steps
+
+
+def run_gpu(args):
+    import torch
+
+    import workloads as W
+    from paper_2306_15678_amd.march import Propagator
+
+    torch.cuda.set_device(0)
+    inst = W.config2()[0]
+    n, z_steps = inst.n, inst.n_steps
+    ckpt = args.ckpt_every
+    u0 = W.initial_field(inst)
+    target = W.synthetic_target(inst, 2)
+    dev = torch.device("cuda", 0)
+    u0_d = torch.from_numpy(u0).to(dev)
+    tgt_d = torch.from_numpy(target).to(dev)
+    gp_steps = float(n) * n * z_steps
+    out = {}
+
+    def make(precision):
+        p = Propagator(_desc_list([inst]), precision=precision, max_steps=z_steps,
+                       ckpt_every=ckpt, device=dev)
+        return p
+
+    def fwd_adj(p):
+        p.set_field(0, u0_d)
+        p.forward_record(z_steps)
+        p.fluence_loss(0, tgt_d)
+        p.backward()
+
+    for precision in (32, 64):
+        p = make(precision)
+        t = _timed(lambda: fwd_adj(p), args.steps if precision == 32 else max(1, args.steps // 2),
+                   args.warmup, p.synchronize)
+        out[precision] = {"s_per_step": t, "value": gp_steps / t}
+        if precision == 32:
+            # forward only (plain propagate) on the same context
+            def fwd():
+                p.set_field(0, u0_d)
+                p.propagate(z_steps)
+            tf = _timed(fwd, args.steps, 1, p.synchronize)
+            out["fwd"] = {"s_per_step": tf, "value": gp_steps / tf}
+            # parity of the timed march: loss, diagnostics and fluence
+            p.set_field(0, u0_d)
+            p.propagate(z_steps)
+            pw, pk = p.diag(0, z_steps)
+            fl = p.intensity(0)
+            out["parity"] = parity_vs_stored(inst, pw, pk, fl, p.field(0))
+            # dominant-kernel timing, HIP events on the library's stream
+            p.set_field(0, u0_d)
+            p.propagate(50)
+            ms_row, ms_col, b_row, b_col = p.time_passes(reps=200)
+            out["passes"] = {"ms_row": ms_row, "ms_col": ms_col,
+                             "bytes_row": b_row, "bytes_col": b_col}
+        p.close()
+        del p
+        torch.cuda.empty_cache()
+    return out
+
+
+def parity_vs_stored(inst, power, peak, fluence, field):
+    """Compare with the oracle's samples of this workload (written by
+    tests/golden/calibrate_floor.py c2); None if the fixture is absent."""
+    path = os.path.join(ROOT, "tests", "golden", "floor_c2.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    ref = d["reference"]
+    last = str(d["steps"][-1])
+    bf = np.array(ref["block_fluence"][last])
+    b = inst.n // bf.shape[0]
+    got = fluence.reshape(bf.shape[0], b, bf.shape[0], b).mean(axis=(1, 3))
+    k = d["steps"].index(int(last))
+    return {
+        "z_steps": int(last),
+        "block_fluence_rel_l2": float(np.linalg.norm(got - bf) / np.linalg.norm(bf)),
+        "power_max_rel_err": float(np.max(np.abs(np.array(power) / np.array(ref["power"]) - 1))),
+        "peak_final_rel_err": float(abs(peak[-1] / ref["peak"][-1] - 1)),
+        "floor_step32_fluence": d["step32"]["fluence"][k],
+        "floor_step32_field": d["step32"]["field"][k],
+    }
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 oracle (numpy) on a bounded sample: forward + adjoint of the
+    first z steps of the same 1024^2 beam."""
+    import workloads as W
+    from oracle import march as M
+
+    inst = W.config2()[0]
+    u0 = W.initial_field(inst)
+    target = W.synthetic_target(inst, 2)
+    steps = 4
+    t0 = time.perf_counter()
+    M.gradient(u0, inst, n_steps=steps, cotangent=lambda u: M.fluence_loss(u, target))
+    dt = time.perf_counter() - t0
+    steps = max(steps, int(steps * seconds_target / max(dt, 1e-3)))
+    steps = min(steps, 60)
+    t0 = time.perf_counter()
+    M.gradient(u0, inst, n_steps=steps, cotangent=lambda u: M.fluence_loss(u, target))
+    dt = time.perf_counter() - t0
+    return {
+        "value": float(inst.n) ** 2 * steps / dt,
+        "unit": "grid-point·steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"FP64 numpy oracle, forward + adjoint of the first {steps} z steps of the "
+                  f"1024x1024 workload ({dt:.1f} s, single-threaded pocketfft)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--ckpt-every", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the march of one beam or a "
+              "batch lives on one device; no multi-GPU path is built)", file=sys.stderr)
+        sys.exit(2)
+    import workloads as W
+    inst = W.config2()[0]
+    g = run_gpu(args)
+    t32, t64 = g[32]["s_per_step"], g[64]["s_per_step"]
+    ps = g["passes"]
+    dom = "col" if ps["ms_col"] >= ps["ms_row"] else "row"
+    ms = ps["ms_" + dom]
+    achieved = ps["bytes_" + dom] / (ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": g[32]["value"],
+        "unit": "grid-point·steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "multifilamentation beam, 1024x1024 complex64 (FP64 reductions), "
+                        "Kerr+MPA+plasma, 2000 z steps, forward+adjoint, checkpoint every "
+                        f"{args.ckpt_every} steps",
+            "grid": inst.n, "z_steps": inst.n_steps, "ckpt_every": args.ckpt_every,
+            "beam": "w0=1 cm, 100 P_cr, 10% seeded noise, window 6 cm, dz=1 cm",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"{dom} pass (forward, complex64)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "ms_per_launch": ms,
+            "bytes_per_launch": ps["bytes_" + dom],
+        },
+        "fp64": {"value": g[64]["value"], "ms_per_step": t64 * 1e3,
+                 "speedup_fp32_over_fp64": t64 / t32},
+        "forward_only": {"value": g["fwd"]["value"], "ms_per_step": g["fwd"]["s_per_step"] * 1e3},
+        "passes_ms": {"row": ps["ms_row"], "col": ps["ms_col"]},
+        "parity": g["parity"],
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * ssfm.h -- C ABI of the MI355X split-step (phase-screen) NLSE march.
+ *
+ * The library integrates the stationary (2D+1) nonlinear Schroedinger
+ * equation of Bulygin & Geints (arXiv 2306.15678; Math and Equations,
+ * Eq. (1), (3), (9)) by the split-step method: every z step applies the
+ * paraxial diffraction operator exactly in Fourier space,
+ *   V = F^-1[ exp(-i (kx^2 + ky^2) dz / 2k0) F U ],
+ * and then a pointwise nonlinear screen U' = V A(I) exp(i Phi(I)) built from
+ * the Kerr term (Eq. (1)), saturating plasma refraction and multiphoton
+ * absorption (Eq. (3)), an 8-parameter ansatz f_theta(I) standing in for the
+ * effective lens (Eq. (6), (9)), and optional random turbulence phase
+ * screens (Eq. (9) eps_t, Eq. (10)).  Conventions: dU/dz = (i/2k0) Lap U +
+ * i k0 dn U - alpha/2 U (the complex conjugate of the paper's e^{i w t}
+ * form; intensities are identical), cell-centred periodic grid, Lie
+ * splitting with diffraction first.
+ *
+ * Units at this boundary are SI: lengths in m, fields in sqrt(W/m^2),
+ * intensities in W/m^2.  Fields cross the boundary as interleaved complex128
+ * (re, im doubles), row-major [y][x] with x contiguous, n*n elements.
+ *
+ * Ownership: the caller allocates every device buffer, including the
+ * workspace sized by ssfm_workspace_bytes(); the library never calls
+ * hipMalloc and never frees caller memory.  A context owns only host
+ * objects (plans, captured graphs) and is released by ssfm_destroy().
+ *
+ * Streams: all device work is enqueued on the stream given to ssfm_create()
+ * (a hipStream_t passed as void*; NULL is the default stream).  Functions
+ * that return data to the host synchronise that stream; the others are
+ * asynchronous.
+ *
+ * Errors: every function returns an ssfm_status; ssfm_last_error() gives a
+ * thread-local detail string for the last failure.  No C++ exception crosses
+ * this boundary.  A context is not thread-safe; distinct contexts are
+ * independent.
+ */
+#ifndef SSFM_H
+#define SSFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSFM_VERSION 10000 /* major*10000 + minor*100 + patch */
+
+typedef struct ssfm_ctx ssfm_ctx;
+
+typedef enum {
+  SSFM_OK = 0,
+  SSFM_EINVAL = -1,       /* bad argument (null pointer, range, size)      */
+  SSFM_EUNSUPPORTED = -2, /* grid size or option not built into the library */
+  SSFM_EHIP = -3,         /* HIP runtime error (detail in ssfm_last_error) */
+  SSFM_ESTATE = -4,       /* call out of order (e.g. backward before forward) */
+  SSFM_ENONFINITE = -5,   /* non-finite power detected in the diagnostics  */
+  SSFM_EWORKSPACE = -6    /* workspace missing, misaligned or too small    */
+} ssfm_status;
+
+/* Screen terms (bit mask). */
+enum {
+  SSFM_KERR = 1,   /* phase k0 n2 I dz                               (Eq. 1) */
+  SSFM_MPA = 2,    /* exact pointwise solution of dI/dz = -beta_K I^K (Eq. 3) */
+  SSFM_PLASMA = 4, /* phase -k0 n2 I_a dz x^K/(1+x^(K-1)), x = I/I_a (Eq. 3) */
+  SSFM_ANSATZ = 8, /* exp(i k0 n2 I_a dz f_theta(x))            (Eq. 6, 9) */
+  SSFM_TURB = 16   /* Kolmogorov phase screens after scheduled steps (Eq. 9) */
+};
+
+/* Precision of the march. */
+enum { SSFM_FP32 = 32, SSFM_FP64 = 64 };
+
+/* Where a caller buffer lives. */
+enum { SSFM_HOST = 0, SSFM_DEVICE = 1 };
+
+/* One beam on one grid (Math and Equations; Eq. (7) gives the beams the
+ * workloads start from).  Supported n: 128, 256, 512, 768, 1024, 2048, 4096. */
+typedef struct {
+  int32_t n;           /* grid points per side (square grid)                */
+  int32_t mpa_order;   /* K >= 2 (multiphoton order; plasma exponent)        */
+  uint32_t terms;      /* SSFM_KERR | SSFM_MPA | ...                         */
+  int32_t n_screens;   /* turbulence screens, used when SSFM_TURB is set     */
+  double length;       /* window side [m]                                    */
+  double dz;           /* z step [m]                                         */
+  double wavelength;   /* [m]; k0 = 2 pi / wavelength (air, n0 = 1)          */
+  double n2;           /* Kerr index [m^2/W]                                 */
+  double beta_k;       /* MPA coefficient [m^(2K-3) W^(1-K)]                 */
+  double i_ref;        /* reference intensity I_a [W/m^2] (> 0)              */
+  double cn2;          /* refractive structure constant [m^(-2/3)]           */
+  double screen_dz;    /* spacing of turbulence screens [m]; screen s (1-based)
+                          sits at (s - 1/2) screen_dz and is applied after the
+                          step that reaches it                               */
+  uint64_t seed;       /* Philox4x32-10 key of this beam's screens           */
+} ssfm_instance_desc;
+
+/* Version number (SSFM_VERSION of the built library). */
+int ssfm_version(void);
+
+/* Static description of a status code. */
+const char* ssfm_strerror(int status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char* ssfm_last_error(void);
+
+/* Device workspace a context needs.
+ *   desc, n_inst : the instances (n_inst >= 1)
+ *   precision    : SSFM_FP32 (complex64 march) or SSFM_FP64 (complex128)
+ *   max_steps    : longest march that will be recorded for the adjoint
+ *                  (0 if ssfm_forward_record() will not be used)
+ *   ckpt_every   : M, steps per adjoint checkpoint segment (M >= 1; M >=
+ *                  max_steps stores every step and needs no recompute)
+ * Writes the byte count to *bytes.  Pure host computation. */
+int ssfm_workspace_bytes(const ssfm_instance_desc* desc, int32_t n_inst,
+                         int32_t precision, int64_t max_steps,
+                         int32_t ckpt_every, size_t* bytes);
+
+/* Create a context over a caller-owned device workspace of ws_bytes bytes
+ * (256-byte aligned, at least ssfm_workspace_bytes()).  Builds the
+ * propagator and twiddle tables (FP64 on the host, rounded once) and the
+ * work lists; fields start at zero.  stream: hipStream_t or NULL. */
+int ssfm_create(const ssfm_instance_desc* desc, int32_t n_inst,
+                int32_t precision, int64_t max_steps, int32_t ckpt_every,
+                void* workspace, size_t ws_bytes, void* stream,
+                ssfm_ctx** out);
+
+/* Release the context's host objects (not the workspace).  Synchronises. */
+int ssfm_destroy(ssfm_ctx* ctx);
+
+/* Load instance inst's field U [sqrt(W/m^2)], complex128 n*n from host or
+ * device memory; resets that instance's step counter to 0. */
+int ssfm_set_field(ssfm_ctx* ctx, int32_t inst, const void* src, int32_t where);
+
+/* Ansatz parameters theta[8] of instance inst (Eq. (6)/(9) stand-in):
+ * f_theta(x) = [sum_p theta_p x^p + i sum_p theta_{4+p} x^p] / (1 + x^4). */
+int ssfm_set_theta(ssfm_ctx* ctx, int32_t inst, const double* theta);
+
+/* Generate every instance's turbulence phase screens on the device
+ * (Philox4x32-10 white noise, Kolmogorov spectrum, inverse FFT). */
+int ssfm_gen_screens(ssfm_ctx* ctx);
+
+/* Copy screen s of instance inst [rad], float64 n*n, to host or device. */
+int ssfm_get_screen(ssfm_ctx* ctx, int32_t inst, int32_t s, void* dst,
+                    int32_t where);
+
+/* March every instance n_steps further (asynchronous).  Per-step power and
+ * peak intensity are accumulated in FP64 for ssfm_get_diag(). */
+int ssfm_propagate(ssfm_ctx* ctx, int64_t n_steps);
+
+/* Current field of instance inst, complex128 SI, to host or device. */
+int ssfm_get_field(ssfm_ctx* ctx, int32_t inst, void* dst, int32_t where);
+
+/* Current intensity (fluence proxy, w = U U*) of instance inst [W/m^2],
+ * float64 n*n, to host or device. */
+int ssfm_get_intensity(ssfm_ctx* ctx, int32_t inst, void* dst, int32_t where);
+
+/* Power sum |U|^2 dx^2 [W] and peak intensity [W/m^2] after each of the
+ * last n steps of the most recent propagate/record call (FP64, host arrays
+ * of length n).  Synchronises.  Returns SSFM_ENONFINITE if a power is not
+ * finite. */
+int ssfm_get_diag(ssfm_ctx* ctx, int32_t inst, double* power, double* peak,
+                  int64_t n);
+
+/* Forward march of n_steps (<= max_steps) from the current fields that keeps
+ * what the adjoint needs: the field at the start of every segment of M steps
+ * (or every pre-screen field when M >= n_steps). */
+int ssfm_forward_record(ssfm_ctx* ctx, int64_t n_steps);
+
+/* Cotangent of the final field of instance inst,
+ * G = dL/dRe U_N + i dL/dIm U_N [1/sqrt(W/m^2)], complex128 from host or
+ * device. */
+int ssfm_set_cotangent(ssfm_ctx* ctx, int32_t inst, const void* g, int32_t where);
+
+/* Fluence-mismatch loss of instance inst against a target w [W/m^2]
+ * (float64 n*n, host or device):
+ *   L = sum (|U_N|^2 - w)^2 / sum w^2,
+ * which also sets the cotangent of U_N.  Writes L to *loss (synchronises). */
+int ssfm_fluence_loss(ssfm_ctx* ctx, int32_t inst, const void* target,
+                      int32_t where, double* loss);
+
+/* Exact discrete adjoint of the recorded march back to its first step
+ * (recomputing each segment from its checkpoint when M < n_steps). */
+int ssfm_backward(ssfm_ctx* ctx);
+
+/* Gradient of L w.r.t. instance inst's initial field (complex128 SI, same
+ * convention as the cotangent), to host or device. */
+int ssfm_get_grad_field(ssfm_ctx* ctx, int32_t inst, void* dst, int32_t where);
+
+/* Gradient of L w.r.t. theta of instance inst (FP64, host double[8]). */
+int ssfm_get_grad_theta(ssfm_ctx* ctx, int32_t inst, double* g);
+
+/* Block mean of a float64 n*n device array into (n/b)*(n/b) (device to
+ * device), used to average a dense reference fluence onto a sparse grid. */
+int ssfm_block_mean(ssfm_ctx* ctx, const double* src, int32_t n, int32_t b,
+                    double* dst);
+
+/* Run march steps through captured HIP graphs (1, default) or plain
+ * launches (0). */
+int ssfm_use_graphs(ssfm_ctx* ctx, int32_t enable);
+
+/* Number of compiled FFT tile variants for grid size n, and selection of
+ * the variant used by this context for that n (autotuner hook). */
+int ssfm_plan_variants(int32_t n, int32_t precision, int32_t* count);
+int ssfm_select_plan(ssfm_ctx* ctx, int32_t n, int32_t variant);
+
+/* Time each pass kernel of one step in isolation with HIP events on the
+ * context's stream: reps launches of the forward row pass and of the
+ * forward column pass over all instances.  Writes the mean milliseconds per
+ * launch and the bytes each launch moves (algorithmic: read + write of the
+ * field).  Leaves the fields unchanged only in the sense that they are
+ * advanced by whole steps; call it on scratch state. */
+int ssfm_time_passes(ssfm_ctx* ctx, int32_t reps, double* ms_row,
+                     double* ms_col, double* bytes_row, double* bytes_col);
+
+/* Wait for all work of the context's stream. */
+int ssfm_synchronize(ssfm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSFM_H */

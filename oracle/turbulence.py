@@ -115,7 +115,8 @@ def instance_screens(inst) -> Dict[int, np.ndarray]:
     amp = kolmogorov_amplitude(inst.n, inst.length, r0)
     steps = []
     for s in range(1, inst.n_screens + 1):
-        steps.append(int(round((s - 0.5) * inst.screen_dz / inst.dz)) - 1)
+        # the step that reaches the slab mid-plane z_s (ties round up)
+        steps.append(int(math.floor((s - 0.5) * inst.screen_dz / inst.dz + 0.5)) - 1)
     out = {}
     for p in range((inst.n_screens + 1) // 2):
         re, im = screen_pair(inst.n, inst.length, amp, inst.seed, p)

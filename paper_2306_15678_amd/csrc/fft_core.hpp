@@ -1,0 +1,313 @@
+// fft_core.hpp -- register/LDS Stockham FFT building blocks for gfx950.
+//
+// A "line" is one row or one column of the transverse grid (the split-step
+// diffraction operator of Eq. (1) factorises exactly into a row operator and
+// a column operator, each diagonal in its own 1-D Fourier basis).  T threads
+// cooperate on a line of N points; thread t holds the E = N/T points
+// t + T*e (e = 0..E-1) in registers.  Each radix stage of the
+// self-sorting (Stockham, decimation-in-time) FFT computes N/R butterflies
+// of radix R; thread t owns butterflies j = t + T*b (b < E/R).
+//
+//   stage with span Ns (1, R0, R0*R1, ...):
+//     inputs    x[j + r*N/R]                       r = 0..R-1
+//     twiddle   w^(r * (j mod Ns) * N/(Ns*R)),     w = exp(dir 2 pi i / N)
+//     DFT_R
+//     outputs   y[(j div Ns)*Ns*R + (j mod Ns) + r*Ns]
+//
+// The inputs of the first stage and the outputs of the last stage are
+// exactly the thread's own register points, so an FFT needs LDS only
+// between stages, and FFT -> pointwise multiply -> inverse FFT needs no LDS
+// traffic at the junction.  Twiddles come from a table
+// tw[m] = exp(-2 pi i m / N) computed in FP64 on the host and rounded once.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ssfm {
+
+template <typename R>
+struct cx {
+  R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) {
+  return {a.re - b.re, a.im - b.im};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * conj(b)
+template <typename R>
+__device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b) {
+  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> conjg(cx<R> a) {
+  return {a.re, -a.im};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> scale(cx<R> a, R s) {
+  return {a.re * s, a.im * s};
+}
+// multiply by (dir * i): dir = -1 gives -i, dir = +1 gives +i
+template <int DIR, typename R>
+__device__ __forceinline__ cx<R> rot_q(cx<R> a) {
+  if constexpr (DIR < 0) {
+    return {a.im, -a.re};
+  } else {
+    return {-a.im, a.re};
+  }
+}
+// multiply by exp(dir i pi/4) = (1 + dir i)/sqrt(2)
+template <int DIR, typename R>
+__device__ __forceinline__ cx<R> rot_8(cx<R> a) {
+  const R h = R(0.70710678118654752440);
+  if constexpr (DIR < 0) {
+    return {(a.re + a.im) * h, (a.im - a.re) * h};
+  } else {
+    return {(a.re - a.im) * h, (a.im + a.re) * h};
+  }
+}
+// multiply by exp(dir 3 i pi/4) = (-1 + dir i)/sqrt(2)
+template <int DIR, typename R>
+__device__ __forceinline__ cx<R> rot_38(cx<R> a) {
+  const R h = R(0.70710678118654752440);
+  if constexpr (DIR < 0) {
+    return {(a.im - a.re) * h, -(a.re + a.im) * h};
+  } else {
+    return {-(a.re + a.im) * h, (a.re - a.im) * h};
+  }
+}
+// multiply by exp(dir 2 pi i e / 16) for e = 1, 3, 9
+template <int DIR, int EXP, typename R>
+__device__ __forceinline__ cx<R> rot_16(cx<R> a) {
+  constexpr double c1 = 0.92387953251128675613;  // cos(pi/8)
+  constexpr double s1 = 0.38268343236508977173;  // sin(pi/8)
+  double cr, ci;
+  if constexpr (EXP == 1) {
+    cr = c1;
+    ci = DIR * s1;
+  } else if constexpr (EXP == 3) {
+    cr = s1;
+    ci = DIR * c1;
+  } else {  // EXP == 9
+    cr = -c1;
+    ci = -DIR * s1;
+  }
+  return cmul(a, cx<R>{R(cr), R(ci)});
+}
+
+// ---------------------------------------------------------------- DFTs
+// In-place DFT of R points in natural order: y_k = sum_n x_n w^(nk),
+// w = exp(dir 2 pi i / R).
+
+template <int DIR, typename R>
+__device__ __forceinline__ void dft2(cx<R>* v) {
+  cx<R> a = v[0];
+  v[0] = a + v[1];
+  v[1] = a - v[1];
+}
+
+template <int DIR, typename R>
+__device__ __forceinline__ void dft3(cx<R>* v) {
+  const R h = R(0.86602540378443864676);  // sqrt(3)/2
+  cx<R> t = v[1] + v[2];
+  cx<R> u = v[1] - v[2];
+  cx<R> m = {v[0].re - R(0.5) * t.re, v[0].im - R(0.5) * t.im};
+  cx<R> w = scale(rot_q<DIR>(u), h);
+  v[0] = v[0] + t;
+  v[1] = m + w;
+  v[2] = m - w;
+}
+
+template <int DIR, typename R>
+__device__ __forceinline__ void dft4_(cx<R>& a0, cx<R>& a1, cx<R>& a2,
+                                      cx<R>& a3) {
+  cx<R> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3;
+  cx<R> t3 = rot_q<DIR>(a1 - a3);
+  a0 = t0 + t2;
+  a2 = t0 - t2;
+  a1 = t1 + t3;
+  a3 = t1 - t3;
+}
+
+template <int DIR, typename R>
+__device__ __forceinline__ void dft4(cx<R>* v) {
+  dft4_<DIR>(v[0], v[1], v[2], v[3]);
+}
+
+template <int DIR, typename R>
+__device__ __forceinline__ void dft8(cx<R>* v) {
+  cx<R> b0 = v[0] + v[4], c0 = v[0] - v[4];
+  cx<R> b1 = v[1] + v[5], c1 = v[1] - v[5];
+  cx<R> b2 = v[2] + v[6], c2 = v[2] - v[6];
+  cx<R> b3 = v[3] + v[7], c3 = v[3] - v[7];
+  c1 = rot_8<DIR>(c1);
+  c2 = rot_q<DIR>(c2);
+  c3 = rot_38<DIR>(c3);
+  dft4_<DIR>(b0, b1, b2, b3);  // even outputs
+  dft4_<DIR>(c0, c1, c2, c3);  // odd outputs
+  v[0] = b0; v[2] = b1; v[4] = b2; v[6] = b3;
+  v[1] = c0; v[3] = c1; v[5] = c2; v[7] = c3;
+}
+
+// 16 = 4 x 4: inner DFT4 over n2 (stride 4), twiddle w16^(n1 k2), outer
+// DFT4 over n1; output index k2 + 4 k1.
+template <int DIR, typename R>
+__device__ __forceinline__ void dft16(cx<R>* v) {
+  dft4_<DIR>(v[0], v[4], v[8], v[12]);
+  dft4_<DIR>(v[1], v[5], v[9], v[13]);
+  dft4_<DIR>(v[2], v[6], v[10], v[14]);
+  dft4_<DIR>(v[3], v[7], v[11], v[15]);
+  // v[n1 + 4 k2] *= w16^(n1 k2)
+  v[5] = rot_16<DIR, 1>(v[5]);
+  v[9] = rot_8<DIR>(v[9]);
+  v[13] = rot_16<DIR, 3>(v[13]);
+  v[6] = rot_8<DIR>(v[6]);
+  v[10] = rot_q<DIR>(v[10]);
+  v[14] = rot_38<DIR>(v[14]);
+  v[7] = rot_16<DIR, 3>(v[7]);
+  v[11] = rot_38<DIR>(v[11]);
+  v[15] = rot_16<DIR, 9>(v[15]);
+  dft4_<DIR>(v[0], v[1], v[2], v[3]);
+  dft4_<DIR>(v[4], v[5], v[6], v[7]);
+  dft4_<DIR>(v[8], v[9], v[10], v[11]);
+  dft4_<DIR>(v[12], v[13], v[14], v[15]);
+  // now v[4 k2 + k1] holds y[k2 + 4 k1]: transpose the 4x4 index
+  cx<R> t;
+#define SSFM_SWAP(a, b) t = v[a]; v[a] = v[b]; v[b] = t;
+  SSFM_SWAP(1, 4) SSFM_SWAP(2, 8) SSFM_SWAP(3, 12)
+  SSFM_SWAP(6, 9) SSFM_SWAP(7, 13) SSFM_SWAP(11, 14)
+#undef SSFM_SWAP
+}
+
+template <int RAD, int DIR, typename R>
+__device__ __forceinline__ void dft(cx<R>* v) {
+  if constexpr (RAD == 2) dft2<DIR>(v);
+  else if constexpr (RAD == 3) dft3<DIR>(v);
+  else if constexpr (RAD == 4) dft4<DIR>(v);
+  else if constexpr (RAD == 8) dft8<DIR>(v);
+  else if constexpr (RAD == 16) dft16<DIR>(v);
+  else static_assert(RAD == 2, "unsupported radix");
+}
+
+// ------------------------------------------------------------ plans
+template <int... Rs>
+struct Radices {};
+
+// N points per line, T threads per line, LINES lines per workgroup.
+template <int N_, int T_, int LINES_, class Rad>
+struct Plan {
+  static constexpr int N = N_;
+  static constexpr int T = T_;
+  static constexpr int LINES = LINES_;
+  static constexpr int E = N_ / T_;
+  static constexpr int THREADS = T_ * LINES_;
+  using radices = Rad;
+  static_assert(N_ % T_ == 0, "T must divide N");
+};
+
+// --------------------------------------------------------- LDS layouts
+// Row lines: line-major with one pad slot per 32 points.
+template <typename R, int N>
+struct LdsLineMajor {
+  static constexpr int LINE = N + N / 32;
+  static constexpr int SIZE_PER_LINE = LINE;
+  cx<R>* base;
+  __device__ __forceinline__ cx<R> get(int p) const { return base[p + (p >> 5)]; }
+  __device__ __forceinline__ void put(int p, cx<R> v) const { base[p + (p >> 5)] = v; }
+};
+
+// Column tiles: point-major, the W columns of a point adjacent.
+template <typename R, int W>
+struct LdsPointMajor {
+  cx<R>* base;  // already offset by the column index
+  __device__ __forceinline__ cx<R> get(int p) const { return base[p * W]; }
+  __device__ __forceinline__ void put(int p, cx<R> v) const { base[p * W] = v; }
+};
+
+// ---------------------------------------------------------- one stage
+template <typename R, int N, int T, int RAD, int NS, int DIR, bool FIRST,
+          bool LAST, class Lds>
+__device__ __forceinline__ void fft_stage(cx<R>* v, int t, const Lds& lds,
+                                          const cx<R>* __restrict__ tw) {
+  constexpr int E = N / T;
+  constexpr int NB = E / RAD;
+  constexpr int STRIDE = N / RAD;
+  constexpr int TWS = N / (NS * RAD);
+  static_assert(E % RAD == 0, "radix must divide points per thread");
+  cx<R> a[NB][RAD];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) {
+      if constexpr (FIRST) {
+        a[b][r] = v[b + r * NB];
+      } else {
+        a[b][r] = lds.get(t + T * b + r * STRIDE);
+      }
+    }
+  }
+  if constexpr (!FIRST) {
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = t + T * b;
+    const int k = j % NS;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        cx<R> w = tw[r * k * TWS];
+        if constexpr (DIR > 0) w.im = -w.im;
+        a[b][r] = cmul(a[b][r], w);
+      }
+    }
+    dft<RAD, DIR>(a[b]);
+    if constexpr (!LAST) {
+      const int base = (j / NS) * NS * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) lds.put(base + r * NS, a[b][r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[b + r * NB] = a[b][r];
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+  }
+}
+
+template <typename R, int N, int T, int DIR, int NS, bool FIRST, class Lds,
+          int R0, int... Rest>
+__device__ __forceinline__ void fft_stages(cx<R>* v, int t, const Lds& lds,
+                                           const cx<R>* __restrict__ tw) {
+  constexpr bool LAST = sizeof...(Rest) == 0;
+  fft_stage<R, N, T, R0, NS, DIR, FIRST, LAST>(v, t, lds, tw);
+  if constexpr (!LAST) {
+    fft_stages<R, N, T, DIR, NS * R0, false, Lds, Rest...>(v, t, lds, tw);
+  }
+}
+
+template <typename R, int N, int T, int DIR, class Lds, int... Rs>
+__device__ __forceinline__ void fft_line_impl(cx<R>* v, int t, const Lds& lds,
+                                              const cx<R>* __restrict__ tw,
+                                              Radices<Rs...>) {
+  fft_stages<R, N, T, DIR, 1, true, Lds, Rs...>(v, t, lds, tw);
+}
+
+// In-register FFT of one line (DIR = -1 forward, +1 inverse, unscaled).
+// On entry and exit v[e] holds point t + T*e.
+template <typename R, class P, int DIR, class Lds>
+__device__ __forceinline__ void fft_line(cx<R>* v, int t, const Lds& lds,
+                                         const cx<R>* __restrict__ tw) {
+  fft_line_impl<R, P::N, P::T, DIR>(v, t, lds, tw, typename P::radices{});
+}
+
+}  // namespace ssfm

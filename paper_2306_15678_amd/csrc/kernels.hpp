@@ -1,0 +1,119 @@
+// kernels.hpp -- host-visible interface of the HIP kernels (launch wrappers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace ssfm {
+
+template <typename R>
+struct cx;
+
+// Pass kinds.  A forward step is ROW_FWD (pending screen applied on load,
+// then row diffraction) followed by COL_FWD (column diffraction, FP64 power
+// partials, store of the pre-screen field).  An adjoint step is COL_ADJ
+// followed by ROW_ADJ (adjoint screen of the previous step fused into the
+// epilogue).  ROW_INV / COL_INV are plain inverse DFTs for screen synthesis.
+enum PassKind { ROW_FWD = 0, ROW_ADJ = 1, ROW_INV = 2, COL_FWD = 3, COL_ADJ = 4, COL_INV = 5 };
+
+template <typename R>
+struct PassArgs {
+  const void* src;            // cx<R> field buffer read
+  void* dst;                  // cx<R> field buffer written
+  const void* aux;            // ROW_ADJ: pre-screen field s_n (cx<R>)
+  const WorkItem* work;       // one entry per workgroup
+  const InstDev* inst;        // beam table
+  const void* tables;         // cx<R> twiddle and propagator tables
+  const R* screens;           // turbulence planes (read)
+  R* planes_out;              // COL_INV: screen planes (write)
+  const int64_t* screen_steps;  // per-beam sorted step lists
+  double* part;               // COL_FWD: [n_work][2] (sum x A^2, max x A^2)
+                              // ROW_ADJ: [n_work][8] theta accumulators
+  int64_t step;               // step whose screen is pending (-1: none)
+  int32_t pair;               // COL_INV: screen pair index
+  int32_t pad;
+};
+
+struct PlanInfo {
+  int threads;   // workgroup size
+  int lines;     // lines per workgroup
+  int t;         // threads per line
+  size_t lds;    // static LDS bytes
+};
+
+// Number of variants and their shape for (kind is column?, n, precision).
+int plan_count(bool column, int n);
+bool plan_info(bool column, int n, int variant, bool fp64, PlanInfo* out);
+
+template <typename R>
+hipError_t launch_pass(int kind, int n, int variant, int n_blocks,
+                       const PassArgs<R>& a, hipStream_t s);
+
+// Pointwise helpers -------------------------------------------------------
+
+// dst (cx<R> device state, beam b at off) = src (complex128 SI) * scale
+template <typename R>
+hipError_t launch_load_field(const double* src, void* dst, int64_t n_elem,
+                             double scale, hipStream_t s);
+
+// dst (complex128 SI) = sqrt(I_a) * [pending screen](state); optionally
+// intensity only (float64 I = I_a |u|^2).
+template <typename R>
+hipError_t launch_store_field(const void* state, const InstDev* inst, int b,
+                              int n, const R* screens,
+                              const int64_t* screen_steps, int64_t pending_step,
+                              double out_scale, double* dst, bool intensity,
+                              hipStream_t s);
+
+// Loss / cotangent seed.  For each point of beam b: u_N = screen(s_N);
+// mode 0 (g_scale = I_a): I = I_a |u|^2, partial sums of (I - w)^2 and
+// G_u = 4 (I - w) I_a u / sum w^2 (wsum[0] = sum w^2, SI);
+// mode 1 (g_scale = sqrt(I_a)): G_u = sqrt(I_a) G_ext (G_ext in SI).
+// Then the adjoint of the pending screen writes mu_N = S^*(G_u) into lam and
+// the ansatz terms of that screen go to part_theta[row][8].
+template <typename R>
+hipError_t launch_seed(int mode, const void* state, const InstDev* inst, int b,
+                       int n, const R* screens, const int64_t* screen_steps,
+                       int64_t pending_step, const double* target,
+                       const double* wsum, const double* g_ext,
+                       double g_scale, void* lam, double* part_loss,
+                       double* part_theta, int n_blocks, hipStream_t s);
+
+template <typename R>
+hipError_t launch_copy(const void* src, void* dst, int64_t n_elem, hipStream_t s);
+
+// Reduce per-workgroup diag partials of `steps` consecutive steps:
+// part[step][n_work][2] -> diag[b][(ring0 + step) % cap][2].
+hipError_t launch_diag_finalize(const double* part, int n_work,
+                                const int32_t* beam_work_begin, int n_beams,
+                                int steps, double* diag, int64_t ring0,
+                                int64_t cap, double power_scale_unused,
+                                hipStream_t s);
+
+// Fixed-order sum of rows of a [n_rows][width] FP64 array per beam range.
+hipError_t launch_reduce_rows(const double* part, int width,
+                              const int32_t* beam_begin, int n_beams,
+                              double* out, hipStream_t s);
+
+// Sum of squares of a float64 array divided by scale^2 (one value).
+hipError_t launch_sumsq(const double* x, int64_t n, double inv_scale,
+                        double* partial, double* out, hipStream_t s);
+
+template <typename R>
+hipError_t launch_noise(const InstDev* inst, int b, int n, int pair,
+                        uint64_t seed, double amp0, void* dst, hipStream_t s);
+
+template <typename R>
+hipError_t launch_screen_to_f64(const R* plane, int64_t n_elem, double* dst,
+                                hipStream_t s);
+
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+
+hipError_t launch_block_mean(const double* src, int n, int b, double* dst,
+                             hipStream_t s);
+
+}  // namespace ssfm

@@ -1,0 +1,191 @@
+// screen.hpp -- pointwise nonlinear screen of one split step and its adjoint.
+//
+// Device units: u = U / sqrt(I_a), x = |u|^2 = I / I_a.  With
+// cK = k0 n2 I_a dz and cM = (K-1) beta_K I_a^(K-1) dz the screen of one
+// step (Eq. (1) Kerr, Eq. (3) plasma refraction and multiphoton absorption,
+// Eq. (9) ansatz and turbulence) is E(x) = A(x) exp(i Phi(x)):
+//   Phi = cK x                                        (Kerr)
+//       - cK x^K / (1 + x^(K-1))                       (saturating plasma)
+//       + cK Re f(x)                                   (ansatz)
+//   ln A = -ln(1 + cM x^(K-1)) / (2(K-1))              (exact pointwise MPA)
+//        - cK Im f(x)                                  (ansatz)
+//   f(x) = [sum_p th_p x^p + i sum_p th_{4+p} x^p] / (1 + x^4)
+// and a turbulence phase phi_t (a precomputed plane) on screen steps.
+//
+// The adjoint of w = V E(|V|^2) for a real loss, with G = dL/dRe + i dL/dIm:
+//   G_V = G_w conj(E) (1 + x conj(g)) + conj(G_w) V^2 E g,   g = E'(x)/E(x)
+//   g   = (ln A)'(x) + i Phi'(x)
+// and the ansatz gradient dL/dth_p = Re(conj(G_w) w dlnE/dth_p), where
+// dlnE/dth_p = i cK x^p/(1+x^4) (p <= 4) and -cK x^(p-4)/(1+x^4) (p > 4).
+#pragma once
+
+#include "fft_core.hpp"
+
+namespace ssfm {
+
+enum : unsigned {
+  T_KERR = 1u,
+  T_MPA = 2u,
+  T_PLASMA = 4u,
+  T_ANSATZ = 8u,
+  T_TURB = 16u
+};
+
+template <typename R>
+struct ScreenConst {
+  R cK, cM, inv2k1;  // inv2k1 = 1 / (2 (K - 1))
+  R th[8];
+  int K;
+  unsigned terms;
+};
+
+template <typename R>
+__device__ __forceinline__ R ipow(R x, int m) {
+  R r = R(1);
+  for (int i = 0; i < m; ++i) r *= x;
+  return r;
+}
+
+__device__ __forceinline__ float fast_log2(float x) { return __log2f(x); }
+__device__ __forceinline__ double fast_log2(double x) { return log2(x); }
+__device__ __forceinline__ float fast_exp2(float x) { return exp2f(x); }
+__device__ __forceinline__ double fast_exp2(double x) { return exp2(x); }
+__device__ __forceinline__ void sin_cos(float a, float* s, float* c) { sincosf(a, s, c); }
+__device__ __forceinline__ void sin_cos(double a, double* s, double* c) { sincos(a, s, c); }
+
+// ln A and Phi (without turbulence) at x.
+template <typename R>
+__device__ __forceinline__ void screen_eval(const ScreenConst<R>& s, R x,
+                                            R& log_a, R& phi) {
+  log_a = R(0);
+  phi = R(0);
+  const unsigned tm = s.terms;
+  R xk1 = R(0);
+  if (tm & (T_MPA | T_PLASMA)) xk1 = ipow(x, s.K - 1);
+  if (tm & T_KERR) phi += s.cK * x;
+  if (tm & T_PLASMA) phi -= s.cK * x * xk1 / (R(1) + xk1);
+  if (tm & T_MPA) {
+    // ln A = -log2(1 + cM x^(K-1)) ln2 / (2(K-1))
+    log_a -= fast_log2(R(1) + s.cM * xk1) * (R(0.69314718055994530942) * s.inv2k1);
+  }
+  if (tm & T_ANSATZ) {
+    const R x2 = x * x, x3 = x2 * x, x4 = x2 * x2;
+    const R inv = R(1) / (R(1) + x4);
+    const R re = (s.th[0] * x + s.th[1] * x2 + s.th[2] * x3 + s.th[3] * x4) * inv;
+    const R im = (s.th[4] * x + s.th[5] * x2 + s.th[6] * x3 + s.th[7] * x4) * inv;
+    phi += s.cK * re;
+    log_a -= s.cK * im;
+  }
+}
+
+// A^2 at x (for the power diagnostics: |E V|^2 = x A^2).
+template <typename R>
+__device__ __forceinline__ R screen_amp2(const ScreenConst<R>& s, R x) {
+  const unsigned tm = s.terms;
+  R l2 = R(0);  // log2 of A^2
+  if (tm & T_MPA) {
+    const R xk1 = ipow(x, s.K - 1);
+    l2 -= fast_log2(R(1) + s.cM * xk1) * (R(2) * s.inv2k1);
+  }
+  if (tm & T_ANSATZ) {
+    const R x2 = x * x, x3 = x2 * x, x4 = x2 * x2;
+    const R im = (s.th[4] * x + s.th[5] * x2 + s.th[6] * x3 + s.th[7] * x4) /
+                 (R(1) + x4);
+    l2 -= R(2) * s.cK * im * R(1.44269504088896340736);
+  }
+  if (l2 == R(0)) return R(1);
+  return fast_exp2(l2);
+}
+
+// u <- u E(|u|^2) exp(i phi_t)
+template <typename R>
+__device__ __forceinline__ cx<R> screen_apply(const ScreenConst<R>& s, cx<R> u,
+                                              R phi_t) {
+  const R x = u.re * u.re + u.im * u.im;
+  R log_a, phi;
+  screen_eval(s, x, log_a, phi);
+  phi += phi_t;
+  const R a = (log_a == R(0)) ? R(1) : fast_exp2(log_a * R(1.44269504088896340736));
+  R sn, cs;
+  sin_cos(phi, &sn, &cs);
+  return {a * (u.re * cs - u.im * sn), a * (u.re * sn + u.im * cs)};
+}
+
+// Adjoint of the screen at the point V (pre-screen value).  lam is the
+// cotangent of the screened value (after turbulence).  Returns the
+// cotangent of V and adds the ansatz gradient terms to gth[8].
+template <typename R>
+__device__ __forceinline__ cx<R> screen_adjoint(const ScreenConst<R>& s,
+                                                cx<R> v, cx<R> lam, R phi_t,
+                                                double* gth) {
+  const unsigned tm = s.terms;
+  if (phi_t != R(0)) {  // lam <- conj(T) lam
+    R sn, cs;
+    sin_cos(phi_t, &sn, &cs);
+    lam = {lam.re * cs + lam.im * sn, lam.im * cs - lam.re * sn};
+  }
+  const R x = v.re * v.re + v.im * v.im;
+  R log_a = R(0), phi = R(0), dla = R(0), dphi = R(0);
+  R xk1 = R(0), xk2 = R(0);
+  if (tm & (T_MPA | T_PLASMA)) {
+    xk2 = ipow(x, s.K - 2);
+    xk1 = xk2 * x;
+  }
+  if (tm & T_KERR) {
+    phi += s.cK * x;
+    dphi += s.cK;
+  }
+  if (tm & T_PLASMA) {
+    const R d = R(1) + xk1;
+    phi -= s.cK * x * xk1 / d;
+    dphi -= s.cK * xk1 * (R(s.K) + xk1) / (d * d);
+  }
+  if (tm & T_MPA) {
+    const R q = R(1) + s.cM * xk1;
+    log_a -= fast_log2(q) * (R(0.69314718055994530942) * s.inv2k1);
+    dla -= s.cM * xk2 / (R(2) * q);
+  }
+  R bx[4] = {R(0), R(0), R(0), R(0)};
+  if (tm & T_ANSATZ) {
+    const R x2 = x * x, x3 = x2 * x, x4 = x2 * x2;
+    const R inv = R(1) / (R(1) + x4);
+    const R gre = s.th[0] * x + s.th[1] * x2 + s.th[2] * x3 + s.th[3] * x4;
+    const R gim = s.th[4] * x + s.th[5] * x2 + s.th[6] * x3 + s.th[7] * x4;
+    const R dgre = s.th[0] + R(2) * s.th[1] * x + R(3) * s.th[2] * x2 + R(4) * s.th[3] * x3;
+    const R dgim = s.th[4] + R(2) * s.th[5] * x + R(3) * s.th[6] * x2 + R(4) * s.th[7] * x3;
+    const R d4 = R(4) * x3 * inv;
+    const R re = gre * inv, im = gim * inv;
+    phi += s.cK * re;
+    log_a -= s.cK * im;
+    dphi += s.cK * (dgre * inv - re * d4);
+    dla -= s.cK * (dgim * inv - im * d4);
+    bx[0] = x * inv;
+    bx[1] = x2 * inv;
+    bx[2] = x3 * inv;
+    bx[3] = x4 * inv;
+  }
+  const R a = (log_a == R(0)) ? R(1) : fast_exp2(log_a * R(1.44269504088896340736));
+  R sn, cs;
+  sin_cos(phi, &sn, &cs);
+  const cx<R> e = {a * cs, a * sn};
+  // 1 + x conj(g), g = dla + i dphi
+  const cx<R> one_xg = {R(1) + x * dla, -x * dphi};
+  const cx<R> t1 = cmul(cmulc(lam, e), one_xg);  // lam conj(E) (1 + x conj g)
+  const cx<R> v2 = {v.re * v.re - v.im * v.im, R(2) * v.re * v.im};
+  const cx<R> eg = cmul(e, cx<R>{dla, dphi});
+  const cx<R> t2 = cmul(cmul(conjg(lam), v2), eg);  // conj(lam) V^2 E g
+  if (tm & T_ANSATZ) {
+    // q = conj(lam) w, w = V E
+    const cx<R> w = cmul(v, e);
+    const R q_re = lam.re * w.re + lam.im * w.im;
+    const R q_im = lam.re * w.im - lam.im * w.re;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      gth[p] += -double(s.cK) * double(q_im) * double(bx[p]);
+      gth[4 + p] += -double(s.cK) * double(q_re) * double(bx[p]);
+    }
+  }
+  return t1 + t2;
+}
+
+}  // namespace ssfm

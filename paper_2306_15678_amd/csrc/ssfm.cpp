@@ -1,0 +1,1161 @@
+// ssfm.cpp -- host plan, workspace layout and the C ABI of libssfm.
+//
+// The host side turns beam descriptions into device tables (twiddles and
+// diffraction factors computed in FP64 and rounded once, per-beam screen
+// constants), builds the per-pass work lists, and drives the march:
+//
+//   forward step n   ROW_FWD (pending screen n-1 applied on load) -> COL_FWD
+//   adjoint step n   COL_ADJ -> ROW_ADJ (adjoint of screen n-1 fused)
+//
+// All beams of a context march in lock-step; beams of equal grid size share
+// one launch per pass, so a batch of uneven beams costs one launch per
+// distinct size per pass (captured once into a HIP graph and replayed).
+#include "../../include/ssfm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+using namespace ssfm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(SSFM_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                             \
+  } while (0)
+
+constexpr int kDiagChunk = 64;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool supported_n(int n) {
+  return n == 128 || n == 256 || n == 512 || n == 768 || n == 1024 || n == 2048 || n == 4096;
+}
+
+int validate_desc(const ssfm_instance_desc* d, int32_t n_inst, int32_t precision) {
+  if (!d) return fail(SSFM_EINVAL, "desc is NULL");
+  if (n_inst < 1 || n_inst > 65536) return fail(SSFM_EINVAL, "n_inst %d out of range", n_inst);
+  if (precision != SSFM_FP32 && precision != SSFM_FP64)
+    return fail(SSFM_EINVAL, "precision must be 32 or 64, got %d", precision);
+  for (int i = 0; i < n_inst; ++i) {
+    const ssfm_instance_desc& x = d[i];
+    if (!supported_n(x.n))
+      return fail(SSFM_EUNSUPPORTED, "instance %d: grid size %d not supported", i, x.n);
+    if (!(x.length > 0) || !(x.dz > 0) || !(x.wavelength > 0) || !(x.i_ref > 0))
+      return fail(SSFM_EINVAL, "instance %d: length, dz, wavelength, i_ref must be > 0", i);
+    if (x.terms & ~31u) return fail(SSFM_EINVAL, "instance %d: unknown term bits", i);
+    if ((x.terms & (SSFM_MPA | SSFM_PLASMA)) && x.mpa_order < 2)
+      return fail(SSFM_EINVAL, "instance %d: mpa_order must be >= 2", i);
+    if (x.mpa_order > 32) return fail(SSFM_EINVAL, "instance %d: mpa_order > 32", i);
+    if (x.n_screens < 0 || x.n_screens > 4096)
+      return fail(SSFM_EINVAL, "instance %d: n_screens out of range", i);
+    if ((x.terms & SSFM_TURB) && x.n_screens > 0 && (!(x.screen_dz > 0) || !(x.cn2 >= 0)))
+      return fail(SSFM_EINVAL, "instance %d: turbulence needs screen_dz > 0, cn2 >= 0", i);
+  }
+  return SSFM_OK;
+}
+
+// Device-side layout of everything a context keeps in the workspace.
+struct Layout {
+  size_t inst, steps, work, wbegin_row, wbegin_col, tables;
+  size_t S, Wk, Lam, ckpt, stack, screens, stage, diag_part, diag, theta_acc,
+      theta_out, seed_loss, seed_theta, scal, sumsq_part;
+  size_t total;
+  int64_t field_elems;  // sum n^2
+  int64_t table_elems;
+  int64_t n_work_rows, n_work_cols;  // launch entries (with padding)
+  int64_t n_widx_rows, n_widx_cols;  // real work items
+  int64_t n_ckpt, n_stack, diag_cap, screen_elems, n_steps_total;
+  int max_n;
+};
+
+struct Group {
+  int n;
+  int row_var = 0, col_var = 0;
+  std::vector<int> beams;
+  // launch order (XCD-aware), offsets into the work array
+  int64_t row_work_off = 0, col_work_off = 0;
+  int row_blocks = 0, col_blocks = 0;
+};
+
+}  // namespace
+
+struct ssfm_ctx {
+  int precision = SSFM_FP32;
+  size_t el = 8;  // bytes per complex element
+  std::vector<ssfm_instance_desc> desc;
+  std::vector<InstDev> inst;
+  std::vector<int64_t> screen_steps;
+  std::vector<Group> groups;
+  std::vector<WorkItem> work;  // all launch entries, group by group
+  std::vector<int32_t> wbegin_row, wbegin_col;
+  Layout L{};
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int64_t max_steps = 0;
+  int32_t ckpt_every = 1;
+  // march state
+  int64_t step = 0;        // steps taken since the last set_field
+  bool pending = false;    // state holds V with its screen still to apply
+  int64_t diag_valid = 0;  // steps of diag kept from the last call
+  // adjoint record
+  int64_t rec_steps = 0, rec_step0 = 0;
+  bool rec_valid = false, seeded = false, grads_valid = false;
+  bool use_graphs = true;
+  std::map<std::tuple<int, int64_t, int64_t>, hipGraphExec_t> graphs;
+
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+  void* field(size_t off, int64_t k = 0) const {
+    return ws + off + size_t(k) * size_t(L.field_elems) * el;
+  }
+  ~ssfm_ctx() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  }
+};
+
+namespace {
+
+// Per-beam screen step list (turbulence): screen s (1-based) sits at
+// z_s = (s - 1/2) dz_s and is applied after step floor(z_s / dz + 1/2) - 1
+// (the step that reaches z_s; ties round up).
+std::vector<int64_t> screen_step_list(const ssfm_instance_desc& d) {
+  std::vector<int64_t> out;
+  if (!(d.terms & SSFM_TURB)) return out;
+  for (int s = 1; s <= d.n_screens; ++s) {
+    const double zs = (s - 0.5) * d.screen_dz;
+    out.push_back(int64_t(std::floor(zs / d.dz + 0.5)) - 1);
+  }
+  return out;
+}
+
+// Groups by grid size in first-appearance order.
+std::vector<Group> make_groups(const ssfm_instance_desc* d, int n_inst) {
+  std::vector<Group> g;
+  for (int i = 0; i < n_inst; ++i) {
+    auto it = std::find_if(g.begin(), g.end(), [&](const Group& x) { return x.n == d[i].n; });
+    if (it == g.end()) {
+      Group ng;
+      ng.n = d[i].n;
+      ng.beams.push_back(i);
+      g.push_back(ng);
+    } else {
+      it->beams.push_back(i);
+    }
+  }
+  return g;
+}
+
+// XCD-aware launch order: workgroups are dispatched round-robin over the 8
+// XCDs (blockIdx mod 8), so entry b runs on XCD b % 8.  Giving each XCD a
+// contiguous run of work items keeps neighbouring lines (which share cache
+// lines in the column pass) in one XCD's L2.
+std::vector<WorkItem> xcd_order(const std::vector<WorkItem>& items) {
+  const size_t n = items.size();
+  const size_t m = (n + 7) / 8 * 8;
+  const size_t chunk = m / 8;
+  std::vector<WorkItem> out(m, WorkItem{-1, 0, -1, 0});
+  for (size_t b = 0; b < m; ++b) {
+    const size_t x = b % 8, q = b / 8;
+    const size_t t = x * chunk + q;
+    if (t < n) out[b] = items[t];
+  }
+  return out;
+}
+
+// Builds groups, work lists and the layout.  Pure host computation.
+using VariantMap = std::map<int, std::pair<int, int>>;  // n -> (row, column)
+
+// Largest number of work items any variant gives a beam of size n.
+int64_t max_items(bool column, int n, bool fp64) {
+  int64_t m = 0;
+  for (int v = 0; v < plan_count(column, n); ++v) {
+    PlanInfo pi;
+    if (plan_info(column, n, v, fp64, &pi)) m = std::max<int64_t>(m, n / pi.lines);
+  }
+  return m;
+}
+
+int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t max_steps,
+                int32_t ckpt_every, const VariantMap* variants, std::vector<Group>* groups_out,
+                std::vector<WorkItem>* work_out, std::vector<int32_t>* wb_row,
+                std::vector<int32_t>* wb_col, Layout* L) {
+  const size_t el = precision == SSFM_FP64 ? 16 : 8;
+  const size_t rel = el / 2;
+  std::vector<Group> groups = make_groups(d, n_inst);
+  if (variants) {
+    for (auto& g : groups) {
+      auto it = variants->find(g.n);
+      if (it != variants->end()) {
+        g.row_var = it->second.first;
+        g.col_var = it->second.second;
+      }
+    }
+  }
+  // beam-contiguous work indices
+  std::vector<int32_t> row_first(n_inst + 1), col_first(n_inst + 1);
+  int64_t nr = 0, nc = 0;
+  std::vector<PlanInfo> rinfo(n_inst), cinfo(n_inst);
+  for (auto& g : groups) {
+    PlanInfo ri, ci;
+    if (!plan_info(false, g.n, g.row_var, precision == SSFM_FP64, &ri) ||
+        !plan_info(true, g.n, g.col_var, precision == SSFM_FP64, &ci))
+      return fail(SSFM_EUNSUPPORTED, "no kernel plan for n=%d", g.n);
+    for (int b : g.beams) {
+      rinfo[b] = ri;
+      cinfo[b] = ci;
+    }
+  }
+  for (int b = 0; b < n_inst; ++b) {
+    row_first[b] = int32_t(nr);
+    col_first[b] = int32_t(nc);
+    nr += d[b].n / rinfo[b].lines;
+    nc += d[b].n / cinfo[b].lines;
+  }
+  row_first[n_inst] = int32_t(nr);
+  col_first[n_inst] = int32_t(nc);
+  std::vector<WorkItem> work;
+  for (auto& g : groups) {
+    std::vector<WorkItem> rows, cols;
+    for (int b : g.beams) {
+      const int rl = rinfo[b].lines, cl = cinfo[b].lines;
+      for (int k = 0; k < d[b].n / rl; ++k)
+        rows.push_back(WorkItem{b, k * rl, row_first[b] + k, 0});
+      for (int k = 0; k < d[b].n / cl; ++k)
+        cols.push_back(WorkItem{b, k * cl, col_first[b] + k, 0});
+    }
+    auto ro = xcd_order(rows), co = xcd_order(cols);
+    g.row_work_off = int64_t(work.size());
+    g.row_blocks = int(ro.size());
+    work.insert(work.end(), ro.begin(), ro.end());
+    g.col_work_off = int64_t(work.size());
+    g.col_blocks = int(co.size());
+    work.insert(work.end(), co.begin(), co.end());
+  }
+  // partial-sum arrays are sized for the variant with the most work items
+  int64_t nr_max = 0, nc_max = 0;
+  for (int b = 0; b < n_inst; ++b) {
+    nr_max += max_items(false, d[b].n, precision == SSFM_FP64);
+    nc_max += max_items(true, d[b].n, precision == SSFM_FP64);
+  }
+  Layout l{};
+  int64_t fe = 0, te = 0, se = 0, nsteps = 0;
+  int max_n = 0;
+  std::vector<int> tw_done;
+  for (int b = 0; b < n_inst; ++b) {
+    fe += int64_t(d[b].n) * d[b].n;
+    max_n = std::max(max_n, d[b].n);
+    if (std::find(tw_done.begin(), tw_done.end(), d[b].n) == tw_done.end()) {
+      tw_done.push_back(d[b].n);
+      te += d[b].n;
+    }
+    te += d[b].n;  // propagator
+    if (d[b].terms & SSFM_TURB) {
+      se += int64_t(d[b].n_screens) * d[b].n * d[b].n;
+      nsteps += d[b].n_screens;
+    }
+  }
+  l.field_elems = fe;
+  l.table_elems = te;
+  l.screen_elems = se;
+  l.n_steps_total = nsteps;
+  l.max_n = max_n;
+  l.n_work_rows = nr;
+  l.n_work_cols = nc;
+  l.n_widx_rows = nr;
+  l.n_widx_cols = nc;
+  if (max_steps > 0) {
+    const int64_t m = std::max<int64_t>(1, ckpt_every);
+    const int64_t seg = std::min<int64_t>(m, max_steps);
+    l.n_ckpt = (max_steps + seg - 1) / seg;
+    l.n_stack = seg - 1;
+  }
+  l.diag_cap = std::max<int64_t>(max_steps, 4096);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  l.inst = take(sizeof(InstDev) * n_inst);
+  l.steps = take(sizeof(int64_t) * std::max<int64_t>(nsteps, 1));
+  // room for the work list of any variant choice (with XCD padding)
+  l.work = take(sizeof(WorkItem) * size_t(nr_max + nc_max + 16 * groups.size()));
+  l.wbegin_row = take(sizeof(int32_t) * (n_inst + 1));
+  l.wbegin_col = take(sizeof(int32_t) * (n_inst + 1));
+  l.tables = take(el * te);
+  l.S = take(el * fe);
+  l.Wk = take(el * fe);
+  l.Lam = take(max_steps > 0 ? el * fe : 0);
+  l.ckpt = take(el * fe * l.n_ckpt);
+  l.stack = take(el * fe * l.n_stack);
+  l.screens = take(rel * se);
+  l.stage = take(16 * size_t(max_n) * max_n);
+  l.diag_part = take(sizeof(double) * 2 * kDiagChunk * nc_max);
+  l.diag = take(sizeof(double) * 2 * l.diag_cap * n_inst);
+  l.theta_acc = take(sizeof(double) * 8 * nr_max);
+  l.theta_out = take(sizeof(double) * 8 * n_inst);
+  l.seed_loss = take(sizeof(double) * max_n);
+  l.seed_theta = take(sizeof(double) * 8 * max_n * n_inst);
+  l.scal = take(sizeof(double) * 16);
+  l.sumsq_part = take(sizeof(double) * 256);
+  l.total = off;
+  if (groups_out) *groups_out = groups;
+  if (work_out) *work_out = work;
+  if (wb_row) *wb_row = row_first;
+  if (wb_col) *wb_col = col_first;
+  *L = l;
+  return SSFM_OK;
+}
+
+// exp(-2 pi i m / n) in FP64, rounded to the working precision.
+void twiddles(int n, std::vector<double>* out) {
+  out->resize(2 * size_t(n));
+  for (int m = 0; m < n; ++m) {
+    const double a = 2.0 * M_PI * double(m) / double(n);
+    (*out)[2 * m] = std::cos(a);
+    (*out)[2 * m + 1] = -std::sin(a);
+  }
+}
+
+// exp(-i k_m^2 dz / 2k0) / n, phase reduced modulo 2 pi in FP64.
+void propagator(const ssfm_instance_desc& d, std::vector<double>* out) {
+  const int n = d.n;
+  const double k0 = 2.0 * M_PI / d.wavelength;
+  out->resize(2 * size_t(n));
+  for (int m = 0; m < n; ++m) {
+    const int ms = (m <= n / 2) ? m : m - n;
+    const double k = 2.0 * M_PI * double(ms) / d.length;
+    double ph = std::fmod(k * k * d.dz / (2.0 * k0), 2.0 * M_PI);
+    (*out)[2 * m] = std::cos(ph) / n;
+    (*out)[2 * m + 1] = -std::sin(ph) / n;
+  }
+}
+
+template <typename R>
+void append_table(std::vector<unsigned char>* blob, const std::vector<double>& v) {
+  const size_t n = v.size();
+  const size_t o = blob->size();
+  blob->resize(o + n * sizeof(R));
+  R* p = reinterpret_cast<R*>(blob->data() + o);
+  for (size_t i = 0; i < n; ++i) p[i] = R(v[i]);
+}
+
+int check_ctx(ssfm_ctx* c) {
+  if (!c) return fail(SSFM_EINVAL, "ctx is NULL");
+  return SSFM_OK;
+}
+
+int check_inst(ssfm_ctx* c, int32_t i) {
+  if (int r = check_ctx(c)) return r;
+  if (i < 0 || i >= int32_t(c->desc.size()))
+    return fail(SSFM_EINVAL, "instance %d out of range [0, %zu)", i, c->desc.size());
+  return SSFM_OK;
+}
+
+// ---------------------------------------------------------------- passes
+template <typename R>
+PassArgs<R> base_args(ssfm_ctx* c) {
+  PassArgs<R> a{};
+  a.inst = c->at<InstDev>(c->L.inst);
+  a.tables = c->ws + c->L.tables;
+  a.screens = c->at<R>(c->L.screens);
+  a.screen_steps = c->at<int64_t>(c->L.steps);
+  a.step = -1;
+  return a;
+}
+
+template <typename R>
+int run_pass(ssfm_ctx* c, int kind, PassArgs<R> a) {
+  const bool col = kind >= COL_FWD;
+  for (auto& g : c->groups) {
+    a.work = c->at<WorkItem>(c->L.work) + (col ? g.col_work_off : g.row_work_off);
+    const int nb = col ? g.col_blocks : g.row_blocks;
+    const int v = col ? g.col_var : g.row_var;
+    HIP_TRY(launch_pass<R>(kind, g.n, v, nb, a, c->stream));
+  }
+  return SSFM_OK;
+}
+
+// One forward step: src (s_n) -> Wk -> dst (s_{n+1}).
+template <typename R>
+int fwd_step(ssfm_ctx* c, const void* src, void* dst, int64_t pending_step, double* part) {
+  PassArgs<R> a = base_args<R>(c);
+  a.src = src;
+  a.dst = c->field(c->L.Wk);
+  a.step = pending_step;
+  if (int r = run_pass<R>(c, ROW_FWD, a)) return r;
+  PassArgs<R> b = base_args<R>(c);
+  b.src = c->field(c->L.Wk);
+  b.dst = dst;
+  b.part = part;
+  return run_pass<R>(c, COL_FWD, b);
+}
+
+// One adjoint step: Lam -> Wk (columns) -> Lam (rows + adjoint screen with
+// the pre-screen field `sv` of the screen applied after step pending_step).
+template <typename R>
+int adj_step(ssfm_ctx* c, const void* sv, int64_t pending_step) {
+  PassArgs<R> a = base_args<R>(c);
+  a.src = c->field(c->L.Lam);
+  a.dst = c->field(c->L.Wk);
+  if (int r = run_pass<R>(c, COL_ADJ, a)) return r;
+  PassArgs<R> b = base_args<R>(c);
+  b.src = c->field(c->L.Wk);
+  b.dst = c->field(c->L.Lam);
+  b.aux = sv;
+  b.step = pending_step;
+  b.part = c->at<double>(c->L.theta_acc);
+  return run_pass<R>(c, ROW_ADJ, b);
+}
+
+template <typename R>
+int diag_flush(ssfm_ctx* c, int steps, int64_t first_step) {
+  HIP_TRY(launch_diag_finalize(c->at<double>(c->L.diag_part), int(c->L.n_widx_cols),
+                               c->at<int32_t>(c->L.wbegin_col), int(c->desc.size()), steps,
+                               c->at<double>(c->L.diag), first_step, c->L.diag_cap, 0.0,
+                               c->stream));
+  return SSFM_OK;
+}
+
+// Enqueue n plain forward steps starting at c->step.
+template <typename R>
+int enqueue_propagate(ssfm_ctx* c, int64_t n, int64_t step0, bool pending0) {
+  int64_t chunk_start = step0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t step = step0 + i;
+    const int slot = int(i % kDiagChunk);
+    double* part = c->at<double>(c->L.diag_part) + size_t(slot) * 2 * c->L.n_widx_cols;
+    const int64_t pend = (i == 0 && !pending0) ? -1 : step - 1;
+    if (int r = fwd_step<R>(c, c->field(c->L.S), c->field(c->L.S), pend, part)) return r;
+    if (slot == kDiagChunk - 1 || i == n - 1) {
+      if (int r = diag_flush<R>(c, slot + 1, chunk_start)) return r;
+      chunk_start = step + 1;
+    }
+  }
+  return SSFM_OK;
+}
+
+// Runs `body` directly or through a cached graph keyed by (kind, a, b).
+template <typename F>
+int maybe_graph(ssfm_ctx* c, int kind, int64_t a, int64_t b, F body) {
+  if (!c->use_graphs) return body();
+  auto key = std::make_tuple(kind, a, b);
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    hipStream_t cap;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipStream_t saved = c->stream;
+    c->stream = cap;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      c->stream = saved;
+      (void)hipStreamDestroy(cap);
+      return fail(SSFM_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    int r = body();
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    c->stream = saved;
+    (void)hipStreamDestroy(cap);
+    if (r) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return r;
+    }
+    if (e2 != hipSuccess) return fail(SSFM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return fail(SSFM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+    it = c->graphs.emplace(key, exec).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, c->stream));
+  return SSFM_OK;
+}
+
+template <typename R>
+int do_propagate(ssfm_ctx* c, int64_t n) {
+  const int64_t step0 = c->step;
+  const bool pend = c->pending;
+  int r = maybe_graph(c, 0, step0 * 2 + (pend ? 1 : 0), n,
+                      [&] { return enqueue_propagate<R>(c, n, step0, pend); });
+  if (r) return r;
+  c->step += n;
+  c->pending = true;
+  c->diag_valid = std::min<int64_t>(n, c->L.diag_cap);
+  c->rec_valid = false;
+  c->seeded = false;
+  return SSFM_OK;
+}
+
+// Apply the pending screen in place (state becomes U_n).
+template <typename R>
+int flush_pending(ssfm_ctx* c) {
+  if (!c->pending) return SSFM_OK;
+  // store_field into the stage buffer (complex128, device units) per beam,
+  // then load it back: a pointwise round trip through the staging area.
+  for (size_t b = 0; b < c->desc.size(); ++b) {
+    const InstDev& in = c->inst[b];
+    const int64_t n2 = int64_t(in.n) * in.n;
+    double* stage = c->at<double>(c->L.stage);
+    HIP_TRY(launch_store_field<R>(c->field(c->L.S), c->at<InstDev>(c->L.inst), int(b), in.n,
+                                  c->at<R>(c->L.screens), c->at<int64_t>(c->L.steps),
+                                  c->step - 1, 1.0, stage, false, c->stream));
+    HIP_TRY(launch_load_field<R>(stage, static_cast<char*>(c->field(c->L.S)) + in.off * c->el,
+                                 n2, 1.0, c->stream));
+  }
+  c->pending = false;
+  return SSFM_OK;
+}
+
+// Location of s_i during a record of n steps (i in [0, n]).
+void* rec_slot(ssfm_ctx* c, int64_t i, int64_t n) {
+  const int64_t M = std::min<int64_t>(std::max<int32_t>(c->ckpt_every, 1), n);
+  if (i == n) return c->field(c->L.S);
+  if (i % M == 0) return c->field(c->L.ckpt, i / M);
+  if (n <= M) return c->field(c->L.stack, i - 1);  // single segment: all stored
+  return c->field(c->L.S);
+}
+
+template <typename R>
+int enqueue_record(ssfm_ctx* c, int64_t n, int64_t step0) {
+  HIP_TRY(launch_copy<R>(c->field(c->L.S), c->field(c->L.ckpt, 0), c->L.field_elems, c->stream));
+  int64_t chunk_start = step0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int slot = int(i % kDiagChunk);
+    double* part = c->at<double>(c->L.diag_part) + size_t(slot) * 2 * c->L.n_widx_cols;
+    const int64_t pend = (i == 0) ? -1 : step0 + i - 1;
+    if (int r = fwd_step<R>(c, rec_slot(c, i, n), rec_slot(c, i + 1, n), pend, part)) return r;
+    if (slot == kDiagChunk - 1 || i == n - 1) {
+      if (int r = diag_flush<R>(c, slot + 1, chunk_start)) return r;
+      chunk_start = step0 + i + 1;
+    }
+  }
+  return SSFM_OK;
+}
+
+template <typename R>
+int do_record(ssfm_ctx* c, int64_t n) {
+  if (c->max_steps <= 0 || n > c->max_steps)
+    return fail(SSFM_EINVAL, "record of %lld steps exceeds max_steps %lld", (long long)n,
+                (long long)c->max_steps);
+  if (int r = flush_pending<R>(c)) return r;
+  const int64_t step0 = c->step;
+  int r = maybe_graph(c, 1, step0, n, [&] { return enqueue_record<R>(c, n, step0); });
+  if (r) return r;
+  c->step += n;
+  c->pending = true;
+  c->diag_valid = std::min<int64_t>(n, c->L.diag_cap);
+  c->rec_steps = n;
+  c->rec_step0 = step0;
+  c->rec_valid = true;
+  c->seeded = false;
+  c->grads_valid = false;
+  return SSFM_OK;
+}
+
+template <typename R>
+int enqueue_backward(ssfm_ctx* c) {
+  const int64_t n = c->rec_steps, step0 = c->rec_step0;
+  const int64_t M = std::min<int64_t>(std::max<int32_t>(c->ckpt_every, 1), n);
+  const int64_t n_seg = (n + M - 1) / M;
+  const bool stored = n <= M;
+  HIP_TRY(launch_fill_f64(c->at<double>(c->L.theta_acc), 8 * c->L.n_widx_rows, 0.0, c->stream));
+  for (int64_t k = n_seg - 1; k >= 0; --k) {
+    const int64_t s0 = k * M;
+    const int64_t len = std::min<int64_t>(M, n - s0);
+    auto sv = [&](int64_t i) -> void* {  // s_{s0+i}
+      if (i == 0) return c->field(c->L.ckpt, k);
+      return c->field(c->L.stack, i - 1);
+    };
+    if (!stored) {
+      for (int64_t i = 0; i + 1 < len; ++i) {
+        const int64_t g = s0 + i;
+        const int64_t pend = (g == 0) ? -1 : step0 + g - 1;
+        if (int r = fwd_step<R>(c, sv(i), c->field(c->L.stack, i), pend, nullptr)) return r;
+      }
+    }
+    for (int64_t i = len - 1; i >= 0; --i) {
+      const int64_t g = s0 + i;
+      const int64_t pend = (g == 0) ? -1 : step0 + g - 1;
+      if (int r = adj_step<R>(c, sv(i), pend)) return r;
+    }
+  }
+  HIP_TRY(launch_reduce_rows(c->at<double>(c->L.theta_acc), 8, c->at<int32_t>(c->L.wbegin_row),
+                             int(c->desc.size()), c->at<double>(c->L.theta_out), c->stream));
+  return SSFM_OK;
+}
+
+template <typename R>
+int do_backward(ssfm_ctx* c) {
+  if (!c->rec_valid) return fail(SSFM_ESTATE, "backward needs a preceding ssfm_forward_record");
+  if (!c->seeded) return fail(SSFM_ESTATE, "backward needs a cotangent (set_cotangent/fluence_loss)");
+  int r = maybe_graph(c, 2, c->rec_step0, c->rec_steps, [&] { return enqueue_backward<R>(c); });
+  if (r) return r;
+  c->grads_valid = true;
+  return SSFM_OK;
+}
+
+// Seed (mode 0: loss; mode 1: external cotangent) for one beam.
+template <typename R>
+int do_seed(ssfm_ctx* c, int b, int mode, const double* target_dev, const double* g_dev) {
+  const InstDev& in = c->inst[b];
+  const ssfm_instance_desc& d = c->desc[b];
+  const int64_t pend = c->step - 1;  // rec: the last recorded step's screen
+  double* loss = c->at<double>(c->L.seed_loss);
+  double* th = c->at<double>(c->L.seed_theta) + size_t(b) * 8 * c->L.max_n;
+  if (mode == 0) {
+    HIP_TRY(launch_sumsq(target_dev, int64_t(in.n) * in.n, 1.0, c->at<double>(c->L.sumsq_part),
+                         c->at<double>(c->L.scal), c->stream));
+  }
+  const double gs = (mode == 0) ? d.i_ref : std::sqrt(d.i_ref);
+  HIP_TRY(launch_seed<R>(mode, c->field(c->L.S), c->at<InstDev>(c->L.inst), b, in.n,
+                         c->at<R>(c->L.screens), c->at<int64_t>(c->L.steps), pend, target_dev,
+                         c->at<double>(c->L.scal), g_dev, gs, c->field(c->L.Lam), loss, th,
+                         in.n, c->stream));
+  return SSFM_OK;
+}
+
+
+// Turbulence screens: for every screen pair p, Philox/Box-Muller white noise
+// shaped by the Kolmogorov amplitude goes into the work buffer, then an
+// unscaled inverse DFT (rows in place, columns into planes 2p and 2p+1).
+template <typename R>
+int do_gen_screens(ssfm_ctx* c) {
+  int max_pairs = 0;
+  for (auto& d : c->desc)
+    if ((d.terms & SSFM_TURB) && d.n_screens > 0) max_pairs = std::max(max_pairs, (d.n_screens + 1) / 2);
+  for (int p = 0; p < max_pairs; ++p) {
+    for (size_t b = 0; b < c->desc.size(); ++b) {
+      const ssfm_instance_desc& d = c->desc[b];
+      if (!(d.terms & SSFM_TURB) || 2 * p >= d.n_screens) continue;
+      const double k0 = 2.0 * M_PI / d.wavelength;
+      double amp0 = 0.0;
+      if (d.cn2 > 0) {
+        // sqrt(Phi(f)) df with Phi(f) = 0.023 r0^(-5/3) f^(-11/3), f = m / L,
+        // df = 1 / L:  amplitude = sqrt(0.023) (L / r0)^(5/6) m^(-11/6)
+        const double r0 = std::pow(0.423 * k0 * k0 * d.cn2 * d.screen_dz, -0.6);
+        amp0 = std::sqrt(0.023) * std::pow(d.length / r0, 5.0 / 6.0);
+      }
+      HIP_TRY(launch_noise<R>(c->at<InstDev>(c->L.inst), int(b), d.n, p, d.seed, amp0,
+                              c->field(c->L.Wk), c->stream));
+    }
+    PassArgs<R> a = base_args<R>(c);
+    a.src = c->field(c->L.Wk);
+    a.dst = c->field(c->L.Wk);
+    a.pair = p;
+    if (int r = run_pass<R>(c, ROW_INV, a)) return r;
+    PassArgs<R> b = base_args<R>(c);
+    b.src = c->field(c->L.Wk);
+    b.planes_out = c->at<R>(c->L.screens);
+    b.pair = p;
+    if (int r = run_pass<R>(c, COL_INV, b)) return r;
+  }
+  return SSFM_OK;
+}
+
+// Upload host tables, beam constants and work lists.
+template <typename R>
+int upload_plan(ssfm_ctx* c) {
+  const int n_inst = int(c->desc.size());
+  // tables: twiddles per distinct n, then one propagator per beam
+  std::vector<unsigned char> blob;
+  std::map<int, int64_t> tw_off;
+  std::vector<double> tmp;
+  c->inst.assign(n_inst, InstDev{});
+  c->screen_steps.clear();
+  int64_t foff = 0, soff = 0;
+  for (int b = 0; b < n_inst; ++b) {
+    const ssfm_instance_desc& d = c->desc[b];
+    InstDev& in = c->inst[b];
+    if (!tw_off.count(d.n)) {
+      tw_off[d.n] = int64_t(blob.size() / c->el);
+      twiddles(d.n, &tmp);
+      append_table<R>(&blob, tmp);
+    }
+    in.n = d.n;
+    in.K = (d.mpa_order >= 2) ? d.mpa_order : 2;
+    in.terms = d.terms;
+    in.n_screens = (d.terms & SSFM_TURB) ? d.n_screens : 0;
+    in.off = foff;
+    foff += int64_t(d.n) * d.n;
+    in.screen_off = soff;
+    soff += int64_t(in.n_screens) * d.n * d.n;
+    in.tw_off = tw_off[d.n];
+    in.prop_off = int64_t(blob.size() / c->el);
+    propagator(d, &tmp);
+    append_table<R>(&blob, tmp);
+    in.steps_off = int64_t(c->screen_steps.size());
+    for (int64_t s : screen_step_list(d)) c->screen_steps.push_back(s);
+    const double k0 = 2.0 * M_PI / d.wavelength;
+    in.cK = k0 * d.n2 * d.i_ref * d.dz;
+    in.cM = (d.terms & SSFM_MPA) ? (in.K - 1) * d.beta_k * std::pow(d.i_ref, in.K - 1) * d.dz : 0.0;
+    in.inv2k1 = 1.0 / (2.0 * (in.K - 1));
+    for (int p = 0; p < 8; ++p) in.theta[p] = 0.0;
+  }
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.tables, blob.data(), blob.size(), hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.inst, c->inst.data(), sizeof(InstDev) * n_inst,
+                         hipMemcpyHostToDevice, c->stream));
+  if (!c->screen_steps.empty())
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.steps, c->screen_steps.data(),
+                           sizeof(int64_t) * c->screen_steps.size(), hipMemcpyHostToDevice,
+                           c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.work, c->work.data(), sizeof(WorkItem) * c->work.size(),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.wbegin_row, c->wbegin_row.data(),
+                         sizeof(int32_t) * c->wbegin_row.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.wbegin_col, c->wbegin_col.data(),
+                         sizeof(int32_t) * c->wbegin_col.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemsetAsync(c->field(c->L.S), 0, c->el * c->L.field_elems, c->stream));
+  HIP_TRY(hipMemsetAsync(c->ws + c->L.diag, 0, sizeof(double) * 2 * c->L.diag_cap * n_inst,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));  // host vectors above are temporaries
+  return SSFM_OK;
+}
+
+
+#define SSFM_DISPATCH(ctx, fn, ...) \
+  ((ctx)->precision == SSFM_FP64 ? fn<double>(__VA_ARGS__) : fn<float>(__VA_ARGS__))
+
+// Device pointer of a caller buffer, staging host data through the
+// workspace's complex128 staging area (bytes <= 16 n_max^2).
+int stage_in(ssfm_ctx* c, const void* src, int32_t where, size_t bytes, const double** out) {
+  if (!src) return fail(SSFM_EINVAL, "source pointer is NULL");
+  if (where == SSFM_DEVICE) {
+    *out = static_cast<const double*>(src);
+    return SSFM_OK;
+  }
+  if (where != SSFM_HOST) return fail(SSFM_EINVAL, "where must be SSFM_HOST or SSFM_DEVICE");
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.stage, src, bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));  // the caller may free src on return
+  *out = c->at<double>(c->L.stage);
+  return SSFM_OK;
+}
+
+template <typename R>
+int store_out(ssfm_ctx* c, int b, const void* state, int64_t pending, double scale, void* dst,
+              int32_t where, bool intensity) {
+  if (!dst) return fail(SSFM_EINVAL, "destination pointer is NULL");
+  if (where != SSFM_HOST && where != SSFM_DEVICE)
+    return fail(SSFM_EINVAL, "where must be SSFM_HOST or SSFM_DEVICE");
+  const int n = c->desc[b].n;
+  const size_t bytes = (intensity ? 8 : 16) * size_t(n) * n;
+  double* out = (where == SSFM_DEVICE) ? static_cast<double*>(dst) : c->at<double>(c->L.stage);
+  HIP_TRY(launch_store_field<R>(state, c->at<InstDev>(c->L.inst), b, n, c->at<R>(c->L.screens),
+                                c->at<int64_t>(c->L.steps), pending, scale, out, intensity,
+                                c->stream));
+  if (where == SSFM_HOST) {
+    HIP_TRY(hipMemcpyAsync(dst, out, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return SSFM_OK;
+}
+
+template <typename R>
+int do_set_field(ssfm_ctx* c, int b, const void* src, int32_t where) {
+  if (c->step > 0 || c->pending) {
+    // keep the other beams exact: apply their pending screen first
+    if (int r = flush_pending<R>(c)) return r;
+  }
+  const int n = c->desc[b].n;
+  const double* dsrc;
+  if (int r = stage_in(c, src, where, 16 * size_t(n) * n, &dsrc)) return r;
+  HIP_TRY(launch_load_field<R>(dsrc, static_cast<char*>(c->field(c->L.S)) + c->inst[b].off * c->el,
+                               int64_t(n) * n, 1.0 / std::sqrt(c->desc[b].i_ref), c->stream));
+  c->step = 0;
+  c->pending = false;
+  c->diag_valid = 0;
+  c->rec_valid = false;
+  c->seeded = false;
+  c->grads_valid = false;
+  return SSFM_OK;
+}
+
+int do_select(ssfm_ctx* c, int32_t n, int32_t variant) {
+  const int rc = plan_count(false, n), cc = plan_count(true, n);
+  if (rc == 0) return fail(SSFM_EUNSUPPORTED, "grid size %d not supported", n);
+  if (variant < 0 || variant >= rc * cc)
+    return fail(SSFM_EINVAL, "variant %d out of range [0, %d)", variant, rc * cc);
+  bool found = false;
+  VariantMap vm;
+  for (auto& g : c->groups) {
+    vm[g.n] = {g.row_var, g.col_var};
+    if (g.n == n) found = true;
+  }
+  if (!found) return fail(SSFM_EINVAL, "no instance with n=%d in this context", n);
+  vm[n] = {variant / cc, variant % cc};
+  // rebuild work lists; the layout's partial arrays are already sized for
+  // the variant with the most work items, so offsets stay valid
+  Layout L2;
+  std::vector<Group> groups;
+  std::vector<WorkItem> work;
+  std::vector<int32_t> wr, wc;
+  if (int r = plan_layout(c->desc.data(), int(c->desc.size()), c->precision, c->max_steps,
+                          c->ckpt_every, &vm, &groups, &work, &wr, &wc, &L2))
+    return r;
+  if (L2.total != c->L.total) return fail(SSFM_EUNSUPPORTED, "variant changes the workspace layout");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->groups = groups;
+  c->work = work;
+  c->wbegin_row = wr;
+  c->wbegin_col = wc;
+  c->L = L2;
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.work, c->work.data(), sizeof(WorkItem) * c->work.size(),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.wbegin_row, c->wbegin_row.data(),
+                         sizeof(int32_t) * c->wbegin_row.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.wbegin_col, c->wbegin_col.data(),
+                         sizeof(int32_t) * c->wbegin_col.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  return SSFM_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+int ssfm_version(void) { return SSFM_VERSION; }
+
+const char* ssfm_strerror(int s) {
+  switch (s) {
+    case SSFM_OK: return "ok";
+    case SSFM_EINVAL: return "invalid argument";
+    case SSFM_EUNSUPPORTED: return "unsupported grid size or option";
+    case SSFM_EHIP: return "HIP runtime error";
+    case SSFM_ESTATE: return "call out of order";
+    case SSFM_ENONFINITE: return "non-finite power in diagnostics";
+    case SSFM_EWORKSPACE: return "workspace missing, misaligned or too small";
+    default: return "unknown status";
+  }
+}
+
+const char* ssfm_last_error(void) { return g_last_error.c_str(); }
+
+int ssfm_workspace_bytes(const ssfm_instance_desc* desc, int32_t n_inst, int32_t precision,
+                         int64_t max_steps, int32_t ckpt_every, size_t* bytes) {
+  g_last_error.clear();
+  if (!bytes) return fail(SSFM_EINVAL, "bytes is NULL");
+  if (int r = validate_desc(desc, n_inst, precision)) return r;
+  if (max_steps < 0 || ckpt_every < 1) return fail(SSFM_EINVAL, "need max_steps >= 0, ckpt_every >= 1");
+  Layout L;
+  if (int r = plan_layout(desc, n_inst, precision, max_steps, ckpt_every, nullptr, nullptr,
+                          nullptr, nullptr, nullptr, &L))
+    return r;
+  *bytes = L.total;
+  return SSFM_OK;
+}
+
+int ssfm_create(const ssfm_instance_desc* desc, int32_t n_inst, int32_t precision,
+                int64_t max_steps, int32_t ckpt_every, void* workspace, size_t ws_bytes,
+                void* stream, ssfm_ctx** out) {
+  g_last_error.clear();
+  if (!out) return fail(SSFM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (int r = validate_desc(desc, n_inst, precision)) return r;
+  if (max_steps < 0 || ckpt_every < 1) return fail(SSFM_EINVAL, "need max_steps >= 0, ckpt_every >= 1");
+  std::unique_ptr<ssfm_ctx> c(new ssfm_ctx);
+  c->precision = precision;
+  c->el = precision == SSFM_FP64 ? 16 : 8;
+  c->desc.assign(desc, desc + n_inst);
+  c->max_steps = max_steps;
+  c->ckpt_every = ckpt_every;
+  c->stream = static_cast<hipStream_t>(stream);
+  if (int r = plan_layout(desc, n_inst, precision, max_steps, ckpt_every, nullptr, &c->groups,
+                          &c->work, &c->wbegin_row, &c->wbegin_col, &c->L))
+    return r;
+  if (!workspace) return fail(SSFM_EWORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(SSFM_EWORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+  if (ws_bytes < c->L.total)
+    return fail(SSFM_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, c->L.total);
+  c->ws = static_cast<char*>(workspace);
+  int r = SSFM_DISPATCH(c, upload_plan, c.get());
+  if (r) return r;
+  *out = c.release();
+  return SSFM_OK;
+}
+
+int ssfm_destroy(ssfm_ctx* ctx) {
+  if (!ctx) return SSFM_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+  return SSFM_OK;
+}
+
+int ssfm_set_field(ssfm_ctx* c, int32_t inst, const void* src, int32_t where) {
+  if (int r = check_inst(c, inst)) return r;
+  return SSFM_DISPATCH(c, do_set_field, c, inst, src, where);
+}
+
+int ssfm_set_theta(ssfm_ctx* c, int32_t inst, const double* theta) {
+  if (int r = check_inst(c, inst)) return r;
+  if (!theta) return fail(SSFM_EINVAL, "theta is NULL");
+  for (int p = 0; p < 8; ++p) {
+    if (!std::isfinite(theta[p])) return fail(SSFM_EINVAL, "theta[%d] not finite", p);
+    c->inst[inst].theta[p] = theta[p];
+  }
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.inst + sizeof(InstDev) * inst, &c->inst[inst],
+                         sizeof(InstDev), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return SSFM_OK;
+}
+
+int ssfm_gen_screens(ssfm_ctx* c) {
+  if (int r = check_ctx(c)) return r;
+  return SSFM_DISPATCH(c, do_gen_screens, c);
+}
+
+int ssfm_get_screen(ssfm_ctx* c, int32_t inst, int32_t s, void* dst, int32_t where) {
+  if (int r = check_inst(c, inst)) return r;
+  const InstDev& in = c->inst[inst];
+  if (s < 0 || s >= in.n_screens) return fail(SSFM_EINVAL, "screen %d out of range", s);
+  if (!dst) return fail(SSFM_EINVAL, "dst is NULL");
+  const int64_t n2 = int64_t(in.n) * in.n;
+  double* out = (where == SSFM_DEVICE) ? static_cast<double*>(dst) : c->at<double>(c->L.stage);
+  const size_t rel = c->el / 2;
+  const void* plane = c->ws + c->L.screens + rel * size_t(in.screen_off + int64_t(s) * n2);
+  if (c->precision == SSFM_FP64)
+    HIP_TRY(launch_screen_to_f64<double>(static_cast<const double*>(plane), n2, out, c->stream));
+  else
+    HIP_TRY(launch_screen_to_f64<float>(static_cast<const float*>(plane), n2, out, c->stream));
+  if (where == SSFM_HOST) {
+    HIP_TRY(hipMemcpyAsync(dst, out, 8 * n2, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return SSFM_OK;
+}
+
+int ssfm_propagate(ssfm_ctx* c, int64_t n_steps) {
+  if (int r = check_ctx(c)) return r;
+  if (n_steps < 0) return fail(SSFM_EINVAL, "n_steps < 0");
+  if (n_steps == 0) return SSFM_OK;
+  return SSFM_DISPATCH(c, do_propagate, c, n_steps);
+}
+
+int ssfm_get_field(ssfm_ctx* c, int32_t inst, void* dst, int32_t where) {
+  if (int r = check_inst(c, inst)) return r;
+  const double sc = std::sqrt(c->desc[inst].i_ref);
+  const int64_t pend = c->pending ? c->step - 1 : -1;
+  return SSFM_DISPATCH(c, store_out, c, inst, c->field(c->L.S), pend, sc, dst, where, false);
+}
+
+int ssfm_get_intensity(ssfm_ctx* c, int32_t inst, void* dst, int32_t where) {
+  if (int r = check_inst(c, inst)) return r;
+  const double sc = std::sqrt(c->desc[inst].i_ref);
+  const int64_t pend = c->pending ? c->step - 1 : -1;
+  return SSFM_DISPATCH(c, store_out, c, inst, c->field(c->L.S), pend, sc, dst, where, true);
+}
+
+int ssfm_get_diag(ssfm_ctx* c, int32_t inst, double* power, double* peak, int64_t n) {
+  if (int r = check_inst(c, inst)) return r;
+  if (n < 0 || n > c->diag_valid)
+    return fail(SSFM_EINVAL, "n=%lld exceeds the %lld recorded diagnostic steps", (long long)n,
+                (long long)c->diag_valid);
+  if (n == 0) return SSFM_OK;
+  std::vector<double> buf(2 * size_t(c->L.diag_cap));
+  HIP_TRY(hipMemcpyAsync(buf.data(), c->ws + c->L.diag + sizeof(double) * 2 * c->L.diag_cap * inst,
+                         sizeof(double) * 2 * c->L.diag_cap, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const ssfm_instance_desc& d = c->desc[inst];
+  const double dx = d.length / d.n;
+  int status = SSFM_OK;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t step = c->step - n + i;
+    const int64_t slot = step % c->L.diag_cap;
+    const double pw = buf[2 * slot] * d.i_ref * dx * dx;
+    const double pk = buf[2 * slot + 1] * d.i_ref;
+    if (power) power[i] = pw;
+    if (peak) peak[i] = pk;
+    if (!std::isfinite(pw)) status = SSFM_ENONFINITE;
+  }
+  if (status) return fail(status, "non-finite power in the diagnostics of instance %d", inst);
+  return SSFM_OK;
+}
+
+int ssfm_forward_record(ssfm_ctx* c, int64_t n_steps) {
+  if (int r = check_ctx(c)) return r;
+  if (n_steps < 1) return fail(SSFM_EINVAL, "n_steps must be >= 1");
+  return SSFM_DISPATCH(c, do_record, c, n_steps);
+}
+
+int ssfm_set_cotangent(ssfm_ctx* c, int32_t inst, const void* g, int32_t where) {
+  if (int r = check_inst(c, inst)) return r;
+  if (!c->rec_valid) return fail(SSFM_ESTATE, "set_cotangent needs a preceding forward_record");
+  const int n = c->desc[inst].n;
+  const double* dg;
+  if (int r = stage_in(c, g, where, 16 * size_t(n) * n, &dg)) return r;
+  int r = SSFM_DISPATCH(c, do_seed, c, inst, 1, nullptr, dg);
+  if (r) return r;
+  if (where == SSFM_HOST) HIP_TRY(hipStreamSynchronize(c->stream));
+  c->seeded = true;
+  return SSFM_OK;
+}
+
+int ssfm_fluence_loss(ssfm_ctx* c, int32_t inst, const void* target, int32_t where, double* loss) {
+  if (int r = check_inst(c, inst)) return r;
+  if (!c->rec_valid) return fail(SSFM_ESTATE, "fluence_loss needs a preceding forward_record");
+  const int n = c->desc[inst].n;
+  const double* dt;
+  if (int r = stage_in(c, target, where, 8 * size_t(n) * n, &dt)) return r;
+  int r = SSFM_DISPATCH(c, do_seed, c, inst, 0, dt, nullptr);
+  if (r) return r;
+  std::vector<double> part(n);
+  double wsum = 0.0;
+  HIP_TRY(hipMemcpyAsync(part.data(), c->ws + c->L.seed_loss, sizeof(double) * n,
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(&wsum, c->ws + c->L.scal, sizeof(double), hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += part[i];
+  if (loss) *loss = s / wsum;
+  c->seeded = true;
+  return SSFM_OK;
+}
+
+int ssfm_backward(ssfm_ctx* c) {
+  if (int r = check_ctx(c)) return r;
+  return SSFM_DISPATCH(c, do_backward, c);
+}
+
+int ssfm_get_grad_field(ssfm_ctx* c, int32_t inst, void* dst, int32_t where) {
+  if (int r = check_inst(c, inst)) return r;
+  if (!c->grads_valid) return fail(SSFM_ESTATE, "no gradient: call ssfm_backward first");
+  const double sc = 1.0 / std::sqrt(c->desc[inst].i_ref);
+  return SSFM_DISPATCH(c, store_out, c, inst, c->field(c->L.Lam), -1, sc, dst, where, false);
+}
+
+int ssfm_get_grad_theta(ssfm_ctx* c, int32_t inst, double* g) {
+  if (int r = check_inst(c, inst)) return r;
+  if (!c->grads_valid) return fail(SSFM_ESTATE, "no gradient: call ssfm_backward first");
+  if (!g) return fail(SSFM_EINVAL, "g is NULL");
+  double acc[8], seed_part[8];
+  const int n = c->desc[inst].n;
+  std::vector<double> sp(size_t(8) * n);
+  HIP_TRY(hipMemcpyAsync(acc, c->ws + c->L.theta_out + sizeof(double) * 8 * inst,
+                         sizeof(double) * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(sp.data(), c->ws + c->L.seed_theta + sizeof(double) * 8 * c->L.max_n * inst,
+                         sizeof(double) * 8 * n, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int p = 0; p < 8; ++p) {
+    seed_part[p] = 0.0;
+    for (int r = 0; r < n; ++r) seed_part[p] += sp[size_t(r) * 8 + p];
+    g[p] = acc[p] + seed_part[p];
+  }
+  return SSFM_OK;
+}
+
+int ssfm_block_mean(ssfm_ctx* c, const double* src, int32_t n, int32_t b, double* dst) {
+  if (int r = check_ctx(c)) return r;
+  if (!src || !dst) return fail(SSFM_EINVAL, "src/dst is NULL");
+  if (n < 1 || b < 1 || n % b) return fail(SSFM_EINVAL, "block %d must divide n=%d", b, n);
+  HIP_TRY(launch_block_mean(src, n, b, dst, c->stream));
+  return SSFM_OK;
+}
+
+int ssfm_use_graphs(ssfm_ctx* c, int32_t enable) {
+  if (int r = check_ctx(c)) return r;
+  c->use_graphs = enable != 0;
+  return SSFM_OK;
+}
+
+int ssfm_plan_variants(int32_t n, int32_t precision, int32_t* count) {
+  if (!count) return fail(SSFM_EINVAL, "count is NULL");
+  if (precision != SSFM_FP32 && precision != SSFM_FP64) return fail(SSFM_EINVAL, "precision");
+  *count = plan_count(false, n) * plan_count(true, n);
+  if (*count == 0) return fail(SSFM_EUNSUPPORTED, "grid size %d not supported", n);
+  return SSFM_OK;
+}
+
+int ssfm_select_plan(ssfm_ctx* c, int32_t n, int32_t variant) {
+  if (int r = check_ctx(c)) return r;
+  return do_select(c, n, variant);
+}
+
+int ssfm_time_passes(ssfm_ctx* c, int32_t reps, double* ms_row, double* ms_col,
+                     double* bytes_row, double* bytes_col) {
+  if (int r = check_ctx(c)) return r;
+  if (reps < 1) return fail(SSFM_EINVAL, "reps must be >= 1");
+  hipEvent_t e0, e1, e2;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventCreate(&e2));
+  int r = SSFM_OK;
+  auto body = [&]<typename R>(R*) -> int {
+    PassArgs<R> a = base_args<R>(c);
+    a.src = c->field(c->L.S);
+    a.dst = c->field(c->L.Wk);
+    a.step = c->pending ? c->step - 1 : -1;
+    PassArgs<R> b = base_args<R>(c);
+    b.src = c->field(c->L.Wk);
+    b.dst = c->field(c->L.Wk);
+    b.part = c->at<double>(c->L.diag_part);
+    HIP_TRY(hipEventRecord(e0, c->stream));
+    for (int i = 0; i < reps; ++i)
+      if (int q = run_pass<R>(c, ROW_FWD, a)) return q;
+    HIP_TRY(hipEventRecord(e1, c->stream));
+    for (int i = 0; i < reps; ++i)
+      if (int q = run_pass<R>(c, COL_FWD, b)) return q;
+    HIP_TRY(hipEventRecord(e2, c->stream));
+    return SSFM_OK;
+  };
+  r = (c->precision == SSFM_FP64) ? body((double*)nullptr) : body((float*)nullptr);
+  if (r == SSFM_OK) {
+    HIP_TRY(hipEventSynchronize(e2));
+    float t1 = 0, t2 = 0;
+    HIP_TRY(hipEventElapsedTime(&t1, e0, e1));
+    HIP_TRY(hipEventElapsedTime(&t2, e1, e2));
+    if (ms_row) *ms_row = double(t1) / reps;
+    if (ms_col) *ms_col = double(t2) / reps;
+    const double b = 2.0 * double(c->el) * double(c->L.field_elems);
+    if (bytes_row) *bytes_row = b;
+    if (bytes_col) *bytes_col = b;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  return r;
+}
+
+int ssfm_synchronize(ssfm_ctx* c) {
+  if (int r = check_ctx(c)) return r;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return SSFM_OK;
+}
+
+}  // extern "C"

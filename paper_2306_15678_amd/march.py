@@ -1,0 +1,209 @@
+"""Python front end of the HIP split-step march (libssfm).
+
+``Propagator`` owns one library context: a caller-owned device workspace (a
+torch uint8 tensor), the torch stream the kernels run on, and the beams.
+Fields cross this boundary as complex128 in SI units (sqrt(W/m^2)), either
+numpy arrays (host) or CUDA tensors (device).  All arithmetic happens in
+the library's kernels; torch is used only to hold memory and pick streams.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def make_desc(n: int, length: float, dz: float, *, wavelength: float, n2: float,
+              terms: int, mpa_order: int = 8, beta_k: float = 0.0,
+              i_ref: float = 5e17, cn2: float = 0.0, screen_dz: float = 0.0,
+              n_screens: int = 0, seed: int = 0) -> L.InstanceDesc:
+    d = L.InstanceDesc()
+    d.n, d.mpa_order, d.terms, d.n_screens = n, mpa_order, terms, n_screens
+    d.length, d.dz, d.wavelength, d.n2 = length, dz, wavelength, n2
+    d.beta_k, d.i_ref, d.cn2, d.screen_dz, d.seed = beta_k, i_ref, cn2, screen_dz, seed
+    return d
+
+
+def desc_of(inst) -> L.InstanceDesc:
+    """Descriptor from any object with the beam/grid/medium attributes
+    (n, length, dz, medium.{wavelength, n2, mpa_order, beta_k, i_ref, terms},
+    cn2, screen_dz, n_screens, seed)."""
+    m = inst.medium
+    return make_desc(inst.n, inst.length, inst.dz, wavelength=m.wavelength, n2=m.n2,
+                     terms=m.terms, mpa_order=m.mpa_order, beta_k=m.beta_k,
+                     i_ref=m.i_ref, cn2=getattr(inst, "cn2", 0.0),
+                     screen_dz=getattr(inst, "screen_dz", 0.0),
+                     n_screens=getattr(inst, "n_screens", 0),
+                     seed=getattr(inst, "seed", 0))
+
+
+def _ptr_where(x, dtype_np, dtype_t):
+    """(pointer, where, keepalive) for a host numpy or CUDA torch buffer."""
+    if isinstance(x, torch.Tensor):
+        if not x.is_cuda:
+            x = x.detach().numpy()
+        else:
+            t = x.detach()
+            if t.dtype != dtype_t:
+                raise TypeError(f"expected {dtype_t}, got {t.dtype}")
+            t = t.contiguous()
+            return ctypes.c_void_p(t.data_ptr()), L.DEVICE, t
+    a = np.ascontiguousarray(x, dtype=dtype_np)
+    return a.ctypes.data_as(ctypes.c_void_p), L.HOST, a
+
+
+class Propagator:
+    """A batch of beams marching in lock-step on one GPU."""
+
+    def __init__(self, descs: Sequence[L.InstanceDesc], precision: int = 32,
+                 max_steps: int = 0, ckpt_every: int = 1,
+                 device: Optional[torch.device] = None,
+                 stream: Optional[torch.cuda.Stream] = None):
+        L.lib()
+        if not torch.cuda.is_available():
+            raise RuntimeError("Propagator needs a GPU (HIP device); none is visible")
+        self.device = torch.device(device or "cuda")
+        self.descs = list(descs)
+        self.n_inst = len(self.descs)
+        arr = (L.InstanceDesc * self.n_inst)(*self.descs)
+        self._arr = arr
+        self.precision = precision
+        nbytes = ctypes.c_size_t()
+        L.call("ssfm_workspace_bytes", arr, self.n_inst, precision, max_steps,
+               ckpt_every, ctypes.byref(nbytes))
+        self.ws_bytes = nbytes.value
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8,
+                                     device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        L.call("ssfm_create", arr, self.n_inst, precision, max_steps, ckpt_every,
+               ctypes.c_void_p(self._ws_ptr), self.ws_bytes,
+               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        self.ctx = ctx
+
+    # ------------------------------------------------------------ lifecycle
+    def close(self) -> None:
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            L.lib().ssfm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _n(self, i: int) -> int:
+        return self.descs[i].n
+
+    # -------------------------------------------------------------- inputs
+    def set_field(self, i: int, u) -> None:
+        p, w, keep = _ptr_where(u, np.complex128, torch.complex128)
+        L.call("ssfm_set_field", self.ctx, i, p, w)
+        if w == L.DEVICE:
+            self.stream.synchronize()
+        del keep
+
+    def set_theta(self, i: int, theta: Iterable[float]) -> None:
+        th = (ctypes.c_double * 8)(*[float(v) for v in theta])
+        L.call("ssfm_set_theta", self.ctx, i, th)
+
+    def gen_screens(self) -> None:
+        L.call("ssfm_gen_screens", self.ctx)
+
+    # ---------------------------------------------------------------- march
+    def propagate(self, n_steps: int) -> None:
+        L.call("ssfm_propagate", self.ctx, int(n_steps))
+
+    def forward_record(self, n_steps: int) -> None:
+        L.call("ssfm_forward_record", self.ctx, int(n_steps))
+
+    def set_cotangent(self, i: int, g) -> None:
+        p, w, keep = _ptr_where(g, np.complex128, torch.complex128)
+        L.call("ssfm_set_cotangent", self.ctx, i, p, w)
+        if w == L.DEVICE:
+            self.stream.synchronize()
+        del keep
+
+    def fluence_loss(self, i: int, target) -> float:
+        p, w, keep = _ptr_where(target, np.float64, torch.float64)
+        out = ctypes.c_double()
+        L.call("ssfm_fluence_loss", self.ctx, i, p, w, ctypes.byref(out))
+        del keep
+        return out.value
+
+    def backward(self) -> None:
+        L.call("ssfm_backward", self.ctx)
+
+    def synchronize(self) -> None:
+        L.call("ssfm_synchronize", self.ctx)
+
+    # -------------------------------------------------------------- outputs
+    def _out(self, name: str, i: int, shape: Tuple[int, ...], dtype_t, device: bool,
+             extra: Tuple = ()):
+        n = self._n(i)
+        if device:
+            t = torch.empty((n, n), dtype=dtype_t, device=self.device)
+            L.call(name, self.ctx, i, *extra, ctypes.c_void_p(t.data_ptr()), L.DEVICE)
+            return t
+        dt = np.complex128 if dtype_t == torch.complex128 else np.float64
+        a = np.empty((n, n), dtype=dt)
+        L.call(name, self.ctx, i, *extra, a.ctypes.data_as(ctypes.c_void_p), L.HOST)
+        return a
+
+    def field(self, i: int = 0, device: bool = False):
+        return self._out("ssfm_get_field", i, (), torch.complex128, device)
+
+    def intensity(self, i: int = 0, device: bool = False):
+        return self._out("ssfm_get_intensity", i, (), torch.float64, device)
+
+    def grad_field(self, i: int = 0, device: bool = False):
+        return self._out("ssfm_get_grad_field", i, (), torch.complex128, device)
+
+    def screen(self, i: int, s: int, device: bool = False):
+        return self._out("ssfm_get_screen", i, (), torch.float64, device, extra=(s,))
+
+    def grad_theta(self, i: int = 0) -> np.ndarray:
+        g = (ctypes.c_double * 8)()
+        L.call("ssfm_get_grad_theta", self.ctx, i, g)
+        return np.array(list(g))
+
+    def diag(self, i: int, n: int) -> Tuple[np.ndarray, np.ndarray]:
+        pw = np.empty(n)
+        pk = np.empty(n)
+        L.call("ssfm_get_diag", self.ctx, i, pw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+               pk.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n)
+        return pw, pk
+
+    # ------------------------------------------------------------- tuning
+    def use_graphs(self, enable: bool) -> None:
+        L.call("ssfm_use_graphs", self.ctx, 1 if enable else 0)
+
+    def select_plan(self, n: int, variant: int) -> None:
+        L.call("ssfm_select_plan", self.ctx, n, variant)
+
+    def time_passes(self, reps: int = 20):
+        """(ms_row, ms_col, bytes_row, bytes_col) per launch of one pass."""
+        vals = [ctypes.c_double() for _ in range(4)]
+        L.call("ssfm_time_passes", self.ctx, reps, *[ctypes.byref(v) for v in vals])
+        return tuple(v.value for v in vals)
+
+    def block_mean(self, src: torch.Tensor, b: int) -> torch.Tensor:
+        n = src.shape[0]
+        src = src.contiguous()
+        out = torch.empty((n // b, n // b), dtype=torch.float64, device=self.device)
+        L.call("ssfm_block_mean", self.ctx, ctypes.c_void_p(src.data_ptr()), n, b,
+               ctypes.c_void_p(out.data_ptr()))
+        return out
+
+
+def plan_variants(n: int, precision: int = 32) -> int:
+    c = ctypes.c_int32()
+    L.call("ssfm_plan_variants", n, precision, ctypes.byref(c))
+    return c.value

@@ -1,0 +1,135 @@
+"""Rounding floors of the split-step march, computed with the FP64 oracle only.
+
+Filamentation is chaotic: modulational instability and collapse amplify any
+perturbation, so two correct discretisations that differ only in rounding
+drift apart.  The tolerance of a GPU run against the FP64 oracle is
+therefore stated relative to a floor measured on the oracle itself:
+
+* ``in64`` / ``in32``: rel L2 between the oracle run from U0 and from
+  U0 (1 + eps eta) with eps = 2^-53 / 2^-24 and eta a unit complex normal
+  (a one-time perturbation at the input);
+* ``step32`` / ``step64``: the same, but a perturbation of size
+  eps sqrt(4 log2 N + 4) injected at every step (the expected relative
+  rounding of one FP32/FP64 step: four length-N FFTs plus pointwise
+  multiplies), maximum over two noise seeds.
+
+Writes tests/golden/floor_<name>.json with the field and fluence floors at
+the listed step counts, and the oracle's own samples of the reference run at
+the same steps (total power and peak intensity after every step, the
+fluence averaged over 32x32 blocks at a quarter, half, three quarters and
+all of the march, and the field at 64 seeded grid points), which full-size GPU tests compare against.  Usage:
+    python tests/golden/calibrate_floor.py c1
+    python tests/golden/calibrate_floor.py c2 --steps 2000 --every 100
+"""
+import argparse
+import json
+import math
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import workloads as W  # noqa: E402
+from oracle import march as M  # noqa: E402
+
+
+def _eta(rng, shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / math.sqrt(2)
+
+
+def floors(inst, n_steps, every, screens=None):
+    u0 = W.initial_field(inst)
+    marks = list(range(every, n_steps + 1, every))
+    # reference trajectory
+    ref = {}
+    power, peak = [], []
+    u = u0.copy()
+    done = 0
+    for m in marks:
+        r = M.march(u, inst, n_steps=m - done, screens=_shift(screens, done))
+        u = r.field
+        power += r.power.tolist()
+        peak += r.peak.tolist()
+        done = m
+        ref[m] = u
+    out = {"steps": marks}
+    pts = np.random.default_rng(777).integers(0, inst.n, size=(64, 2))
+    out["sample_points"] = pts.tolist()
+    out["reference"] = {
+        "power": power, "peak": peak,
+        "block_fluence": {str(m): M.block_mean(np.abs(ref[m]) ** 2, inst.n // 32).tolist()
+                          for m in _quarters(marks)},
+        "field_re": {str(m): ref[m][pts[:, 0], pts[:, 1]].real.tolist() for m in marks},
+        "field_im": {str(m): ref[m][pts[:, 0], pts[:, 1]].imag.tolist() for m in marks},
+    }
+    rng = np.random.default_rng(12345)
+    for name, eps in (("in64", 2.0 ** -53), ("in32", 2.0 ** -24)):
+        u = u0 * (1 + eps * _eta(rng, u0.shape))
+        done = 0
+        f, w = [], []
+        for m in marks:
+            u = M.march(u, inst, n_steps=m - done, screens=_shift(screens, done)).field
+            done = m
+            f.append(M.rel_l2(u, ref[m]))
+            w.append(M.rel_l2(np.abs(u) ** 2, np.abs(ref[m]) ** 2))
+        out[name] = {"field": f, "fluence": w}
+    amp = math.sqrt(4 * math.log2(inst.n) + 4)
+    for name, eps in (("step64", 2.0 ** -53 * amp), ("step32", 2.0 ** -24 * amp)):
+        fmax = np.zeros(len(marks))
+        wmax = np.zeros(len(marks))
+        for seed in (1, 2):
+            r = np.random.default_rng(seed)
+            u = u0.copy()
+            k = 0
+            for n in range(n_steps):
+                u = u * (1 + eps * _eta(r, u.shape))
+                u = M.march(u, inst, n_steps=1, screens=_shift(screens, n)).field
+                if n + 1 == marks[k]:
+                    fmax[k] = max(fmax[k], M.rel_l2(u, ref[marks[k]]))
+                    wmax[k] = max(wmax[k], M.rel_l2(np.abs(u) ** 2, np.abs(ref[marks[k]]) ** 2))
+                    k += 1
+        out[name] = {"field": fmax.tolist(), "fluence": wmax.tolist()}
+    return out
+
+
+def _quarters(marks):
+    """The marks nearest to 1/4, 1/2, 3/4 and all of the march."""
+    last = marks[-1]
+    out = []
+    for q in (0.25, 0.5, 0.75, 1.0):
+        m = min(marks, key=lambda v: abs(v - q * last))
+        if m not in out:
+            out.append(m)
+    return out
+
+
+def _shift(screens, offset):
+    if not screens:
+        return None
+    return {k - offset: v for k, v in screens.items() if k - offset >= 0}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("config", choices=["c1", "c2"])
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--every", type=int, default=20)
+    args = ap.parse_args()
+    inst = {"c1": W.config1, "c2": W.config2}[args.config]()[0]
+    n_steps = args.steps or inst.n_steps
+    res = floors(inst, n_steps, args.every)
+    res["config"] = args.config
+    res["n"] = inst.n
+    path = os.path.join(HERE, f"floor_{args.config}.json")
+    with open(path, "w") as f:
+        json.dump(res, f, indent=1)
+    for k in ("in64", "in32", "step64", "step32"):
+        print(k, "field", ["%.1e" % x for x in res[k]["field"]])
+        print(k, "fluence", ["%.1e" % x for x in res[k]["fluence"]])
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,106 @@
+"""The C-ABI library: loads, exports every declared symbol, host-side checks.
+
+No test here launches a kernel; all run without a GPU.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+import workloads as W
+from paper_2306_15678_amd import _lib as L
+from paper_2306_15678_amd.march import desc_of
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ssfm.h")).read()
+    return sorted(set(re.findall(r"\b(ssfm_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    h = L.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(h, n), n
+    assert set(names) == set(L._SIGS)
+
+
+def test_version_and_status_strings():
+    h = L.lib()
+    assert h.ssfm_version() == 10000
+    for s in (L.OK, L.EINVAL, L.EUNSUPPORTED, L.EHIP, L.ESTATE, L.ENONFINITE, L.EWORKSPACE):
+        assert h.ssfm_strerror(s)
+    assert h.ssfm_strerror(-99) == b"unknown status"
+
+
+def _ws(insts, precision=32, max_steps=0, ckpt=1):
+    arr = (L.InstanceDesc * len(insts))(*[desc_of(i) for i in insts])
+    out = ctypes.c_size_t()
+    st = L.lib().ssfm_workspace_bytes(arr, len(insts), precision, max_steps, ckpt,
+                                      ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_bytes_scale_with_grid_and_precision():
+    c1 = W.config1()[0]
+    st, b32 = _ws([c1], 32)
+    assert st == 0
+    st, b64 = _ws([c1], 64)
+    assert st == 0 and b64 > b32 >= 3 * 128 * 128 * 8
+    c2 = W.config2()[0]
+    st, big = _ws([c2], 32)
+    assert st == 0 and big > 3 * 1024 * 1024 * 8
+    # checkpoints: store-all needs more than every-50
+    st, a = _ws([c2], 32, 2000, 50)
+    st2, b = _ws([c2], 32, 2000, 2000)
+    assert st == 0 and st2 == 0 and b > a
+
+
+def test_workspace_bytes_rejects_bad_arguments():
+    c1 = W.config1()[0]
+    arr = (L.InstanceDesc * 1)(desc_of(c1))
+    d = arr[0]
+    d.n = 100
+    out = ctypes.c_size_t()
+    h = L.lib()
+    assert h.ssfm_workspace_bytes(arr, 1, 32, 0, 1, ctypes.byref(out)) == L.EUNSUPPORTED
+    assert b"grid size 100" in h.ssfm_last_error()
+    d.n = 128
+    d.dz = -1.0
+    assert h.ssfm_workspace_bytes(arr, 1, 32, 0, 1, ctypes.byref(out)) == L.EINVAL
+    d.dz = 1e-3
+    assert h.ssfm_workspace_bytes(arr, 1, 48, 0, 1, ctypes.byref(out)) == L.EINVAL
+    assert h.ssfm_workspace_bytes(arr, 0, 32, 0, 1, ctypes.byref(out)) == L.EINVAL
+    assert h.ssfm_workspace_bytes(arr, 1, 32, 0, 0, ctypes.byref(out)) == L.EINVAL
+    assert h.ssfm_workspace_bytes(None, 1, 32, 0, 1, ctypes.byref(out)) == L.EINVAL
+
+
+def test_create_checks_workspace_before_touching_the_device():
+    c1 = W.config1()[0]
+    arr = (L.InstanceDesc * 1)(desc_of(c1))
+    ctx = ctypes.c_void_p()
+    h = L.lib()
+    assert h.ssfm_create(arr, 1, 32, 0, 1, None, 0, None, ctypes.byref(ctx)) == L.EWORKSPACE
+    assert not ctx.value
+    assert h.ssfm_create(arr, 1, 32, 0, 1, ctypes.c_void_p(256), 16, None,
+                         ctypes.byref(ctx)) == L.EWORKSPACE
+    assert h.ssfm_create(arr, 1, 32, 0, 1, ctypes.c_void_p(257), 1 << 30, None,
+                         ctypes.byref(ctx)) == L.EWORKSPACE
+
+
+def test_null_context_is_rejected():
+    h = L.lib()
+    assert h.ssfm_propagate(None, 1) == L.EINVAL
+    assert h.ssfm_backward(None) == L.EINVAL
+    assert h.ssfm_destroy(None) == L.OK
+
+
+def test_plan_variant_counts():
+    c = ctypes.c_int32()
+    for n in (128, 256, 512, 768, 1024, 2048, 4096):
+        assert L.lib().ssfm_plan_variants(n, 32, ctypes.byref(c)) == 0 and c.value >= 1
+    assert L.lib().ssfm_plan_variants(100, 32, ctypes.byref(c)) == L.EUNSUPPORTED

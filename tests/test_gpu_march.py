@@ -1,0 +1,288 @@
+"""GPU parity of the HIP split-step march against the FP64 oracle.
+
+Every test runs the library through its C ABI (via the ctypes binding) on
+seeded synthetic inputs from ``workloads`` and compares with ``oracle`` on
+the same inputs.  Tolerances: complex128 kernels agree with the oracle to
+rounding (rel L2 <= 1e-11 after the stated steps); complex64 kernels to
+the FP32 rounding floor of the same march (stated per test).
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import march as M
+from oracle import turbulence as T
+
+pytestmark = pytest.mark.gpu
+
+
+def _prop(insts, precision, **kw):
+    from paper_2306_15678_amd.march import Propagator, desc_of
+    return Propagator([desc_of(i) for i in insts], precision=precision, **kw)
+
+
+def _report(name, **vals):
+    print(name, " ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}"
+                         for k, v in vals.items()), flush=True)
+
+
+# ------------------------------------------------------------------ C1
+# Rounding floors of this march (tests/golden/floor_c1.json, written by
+# tests/golden/calibrate_floor.py c1 from the oracle alone): the rel L2 drift
+# of the FP64 oracle itself under per-step perturbations of one FP32 / FP64
+# step's rounding size.  The beam collapses near step 110 (Kerr only, no
+# arrest), after which the march is chaotic and the floor grows ~1000x.
+#                  step 100 field / fluence      step 200 field / fluence
+#   FP64 floor     1.8e-14 / 2.6e-14              2.7e-11 / 5.0e-12
+#   FP32 floor     7.0e-6  / 1.0e-5               1.2e-2  / 2.2e-3
+# Tolerance: 10x the floor.
+C1_TOL = {64: {100: (2e-13, 3e-13), 200: (3e-10, 5e-11)},
+          32: {100: (7e-5, 1e-4), 200: (1.2e-1, 2.2e-2)}}
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_config1_full_march(precision):
+    """128^2 Kerr-only, 200 steps (the CPU-scale workload): field, fluence,
+    power and peak against the oracle before and after the collapse."""
+    inst = W.config1()[0]
+    u0 = W.initial_field(inst)
+    p = _prop([inst], precision)
+    p.set_field(0, u0)
+    u = u0
+    pw_all, pk_all = [], []
+    for stop in (100, 200):
+        ref = M.march(u, inst, n_steps=100)
+        u = ref.field
+        p.propagate(100)
+        got = p.field(0)
+        pw, pk = p.diag(0, 100)
+        pw_all += list(pw / ref.power - 1)
+        pk_all += list(pk / ref.peak - 1)
+        err = M.rel_l2(got, ref.field)
+        ferr = M.rel_l2(np.abs(got) ** 2, np.abs(ref.field) ** 2)
+        _report(f"c1 fp{precision} step {stop}", field=err, fluence=ferr)
+        tf, tw = C1_TOL[precision][stop]
+        assert err < tf and ferr < tw
+    perr = float(np.max(np.abs(pw_all)))
+    _report(f"c1 fp{precision}", power=perr, peak=float(np.max(np.abs(pk_all))))
+    assert perr < (1e-12 if precision == 64 else 1e-4)
+
+
+# -------------------------------------------------- every size, all terms
+def _strong(n, terms, theta=None, n_steps=6, length=4e-3, power=400 * W.P_CR, **kw):
+    return W.Instance(n=n, length=length, dz=0.01, n_steps=n_steps,
+                      medium=W.Medium(terms=terms), w0=0.5e-3, power=power,
+                      sigma=0.2, seed=100 + n, theta=theta, **kw)
+
+
+SIZES = [128, 256, 512, 768, 1024, 2048]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("precision", [64, 32])
+def test_every_size_all_screen_terms(n, precision):
+    terms = W.KPM | W.TERM_ANSATZ
+    theta = tuple(np.array(W.THETA0) + W.random_theta(n, 0.2))
+    inst = _strong(n, terms, theta=theta)
+    u0 = W.initial_field(inst)
+    ref = M.march(u0, inst)
+    p = _prop([inst], precision)
+    p.set_field(0, u0)
+    p.set_theta(0, theta)
+    p.propagate(inst.n_steps)
+    got = p.field(0)
+    err = M.rel_l2(got, ref.field)
+    pw, pk = p.diag(0, inst.n_steps)
+    perr = float(np.max(np.abs(pw / ref.power - 1)))
+    _report(f"n={n} fp{precision}", field=err, power=perr,
+            peak_x=float(ref.peak.max() / W.I_A))
+    tol = 1e-11 if precision == 64 else 2e-5
+    assert err < tol
+    assert perr < (1e-12 if precision == 64 else 2e-6)
+
+
+# ------------------------------------------------------------ screens
+@pytest.mark.parametrize("precision,tol", [(64, 1e-12), (32, 2e-6)])
+def test_turbulence_screens_match_oracle(precision, tol):
+    inst = _strong(256, W.TERM_KERR | W.TERM_TURB, cn2=1e-12, screen_dz=0.02,
+                   n_screens=5)
+    want = T.instance_screens(inst)
+    p = _prop([inst], precision)
+    p.gen_screens()
+    steps = inst.screen_steps()
+    for s in range(inst.n_screens):
+        got = p.screen(0, s)
+        ref = want[steps[s]]
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        _report(f"screen {s} fp{precision}", maxrel=err, rms=float(np.std(ref)))
+        assert err < tol
+
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-11), (32, 2e-5)])
+def test_march_with_turbulence_matches_oracle(precision, tol):
+    inst = _strong(512, W.KPM | W.TERM_TURB, n_steps=9, cn2=3e-13,
+                   screen_dz=0.03, n_screens=3)  # z_s/dz = 1.5, 4.5, 7.5: ties round up
+    u0 = W.initial_field(inst)
+    screens = T.instance_screens(inst)
+    ref = M.march(u0, inst, screens=screens)
+    p = _prop([inst], precision)
+    p.gen_screens()
+    p.set_field(0, u0)
+    p.propagate(inst.n_steps)
+    err = M.rel_l2(p.field(0), ref.field)
+    _report(f"turb march fp{precision}", field=err)
+    assert err < tol
+
+
+# ------------------------------------------------------ batch, determinism
+def test_batch_of_uneven_beams_equals_each_alone():
+    a = _strong(256, W.KPM, n_steps=5)
+    b = _strong(512, W.KPM, n_steps=5, power=150 * W.P_CR)
+    c = dataclasses.replace(_strong(256, W.KPM, n_steps=5), seed=999)
+    insts = [a, b, c]
+    fields = [W.initial_field(i) for i in insts]
+    batch = _prop(insts, 32)
+    for k, u in enumerate(fields):
+        batch.set_field(k, u)
+    batch.propagate(5)
+    for k, (inst, u) in enumerate(zip(insts, fields)):
+        alone = _prop([inst], 32)
+        alone.set_field(0, u)
+        alone.propagate(5)
+        assert np.array_equal(batch.field(k), alone.field(0)), k
+
+
+def test_runs_are_bitwise_deterministic_and_graphs_match_eager():
+    inst = _strong(1024, W.KPM, n_steps=12)
+    u0 = W.initial_field(inst)
+    outs = []
+    for graphs in (True, True, False):
+        p = _prop([inst], 32)
+        p.use_graphs(graphs)
+        p.set_field(0, u0)
+        p.propagate(inst.n_steps)
+        outs.append((p.field(0), p.diag(0, inst.n_steps)))
+    for f, (pw, pk) in outs[1:]:
+        assert np.array_equal(f, outs[0][0])
+        assert np.array_equal(pw, outs[0][1][0]) and np.array_equal(pk, outs[0][1][1])
+
+
+def test_propagate_in_chunks_equals_one_call():
+    inst = _strong(256, W.KPM | W.TERM_TURB, n_steps=10, cn2=3e-13, screen_dz=0.03,
+                   n_screens=3)
+    u0 = W.initial_field(inst)
+    p1 = _prop([inst], 32)
+    p1.gen_screens()
+    p1.set_field(0, u0)
+    p1.propagate(10)
+    p2 = _prop([inst], 32)
+    p2.gen_screens()
+    p2.set_field(0, u0)
+    for k in (3, 4, 3):
+        p2.propagate(k)
+    assert np.array_equal(p1.field(0), p2.field(0))
+
+
+# ------------------------------------------------------------- gradients
+def _grad_case(n=256, turb=False):
+    terms = W.KPM | W.TERM_ANSATZ
+    kw = {}
+    if turb:
+        terms |= W.TERM_TURB
+        kw = dict(cn2=3e-13, screen_dz=0.03, n_screens=3)
+    theta = tuple(np.array(W.THETA0) + W.random_theta(7, 0.1))
+    inst = _strong(n, terms, theta=theta, n_steps=8, power=200 * W.P_CR, **kw)
+    return inst
+
+
+@pytest.mark.parametrize("turb", [False, True])
+@pytest.mark.parametrize("precision,ckpt", [(64, 3), (64, 100), (32, 3), (32, 100)])
+def test_gradient_matches_oracle(precision, ckpt, turb):
+    inst = _grad_case(turb=turb)
+    u0 = W.initial_field(inst)
+    target = W.synthetic_target(inst, 5)
+    screens = T.instance_screens(inst) if turb else None
+    loss, g_u0, g_th = M.gradient(u0, inst, screens=screens,
+                                  cotangent=lambda u: M.fluence_loss(u, target))
+    p = _prop([inst], precision, max_steps=inst.n_steps, ckpt_every=ckpt)
+    if turb:
+        p.gen_screens()
+    p.set_field(0, u0)
+    p.set_theta(0, inst.theta)
+    p.forward_record(inst.n_steps)
+    gl = p.fluence_loss(0, target)
+    p.backward()
+    gg = p.grad_field(0)
+    gt = p.grad_theta(0)
+    lerr = abs(gl / loss - 1)
+    ferr = M.rel_l2(gg, g_u0)
+    terr = float(np.max(np.abs(gt - g_th)) / np.max(np.abs(g_th)))
+    _report(f"grad fp{precision} M={ckpt} turb={turb}", loss=lerr, g_u0=ferr, g_theta=terr)
+    tol = 1e-10 if precision == 64 else 1e-4
+    assert lerr < tol and ferr < tol and terr < tol
+
+
+def test_checkpointed_and_stored_adjoints_are_bitwise_equal():
+    inst = _grad_case()
+    u0 = W.initial_field(inst)
+    target = W.synthetic_target(inst, 5)
+    res = []
+    for ckpt in (3, 100):
+        p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=ckpt)
+        p.set_field(0, u0)
+        p.set_theta(0, inst.theta)
+        p.forward_record(inst.n_steps)
+        p.fluence_loss(0, target)
+        p.backward()
+        res.append((p.grad_field(0), p.grad_theta(0)))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+
+
+def test_external_cotangent_matches_loss_seed():
+    inst = _grad_case()
+    u0 = W.initial_field(inst)
+    target = W.synthetic_target(inst, 5)
+    p = _prop([inst], 64, max_steps=inst.n_steps, ckpt_every=4)
+    p.set_field(0, u0)
+    p.set_theta(0, inst.theta)
+    p.forward_record(inst.n_steps)
+    u_n = p.field(0)
+    _, g = M.fluence_loss(u_n, target)
+    p.set_cotangent(0, g)
+    p.backward()
+    g1, t1 = p.grad_field(0), p.grad_theta(0)
+    p.fluence_loss(0, target)
+    p.backward()
+    g2, t2 = p.grad_field(0), p.grad_theta(0)
+    assert M.rel_l2(g1, g2) < 1e-12
+    assert np.max(np.abs(t1 - t2)) < 1e-12 * np.max(np.abs(t2))
+
+
+def test_autograd_function_matches_oracle_gradient():
+    """torch.autograd through the library: a loss written in torch on U_N,
+    gradients w.r.t. U0 and theta against the oracle (FP64 kernels)."""
+    import torch
+    from paper_2306_15678_amd.autograd import march
+
+    inst = _grad_case(n=128)
+    u0 = W.initial_field(inst)
+    target = W.synthetic_target(inst, 9)
+    loss_o, g_u0, g_th = M.gradient(u0, inst, cotangent=lambda u: M.fluence_loss(u, target))
+    p = _prop([inst], 64, max_steps=inst.n_steps, ckpt_every=3)
+    dev = torch.device("cuda")
+    tu = torch.from_numpy(u0).to(dev).requires_grad_(True)
+    tth = torch.tensor(inst.theta, dtype=torch.float64, device=dev, requires_grad=True)
+    tt = torch.from_numpy(target).to(dev)
+    u_n = march(tu, tth, p, inst.n_steps)
+    inten = (u_n * u_n.conj()).real
+    loss = ((inten - tt) ** 2).sum() / (tt ** 2).sum()
+    loss.backward()
+    lerr = abs(loss.item() / loss_o - 1)
+    ferr = M.rel_l2(tu.grad.cpu().numpy(), g_u0)
+    terr = float(np.max(np.abs(tth.grad.cpu().numpy() - g_th)) / np.max(np.abs(g_th)))
+    _report("autograd fp64", loss=lerr, g_u0=ferr, g_theta=terr)
+    assert lerr < 1e-10 and ferr < 1e-10 and terr < 1e-10

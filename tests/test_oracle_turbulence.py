@@ -112,3 +112,18 @@ def test_fried_parameter_textbook_value():
     k0 = 2 * math.pi / 800e-9
     assert abs(T.fried_parameter(k0, 1e-15, 10.0) / 2.2386 - 1) < 1e-3
     assert abs(T.fried_parameter(k0, 1e-14, 10.0) / 0.56231 - 1) < 1e-3
+
+
+def test_screen_schedule_follows_slab_midplanes():
+    """Screen s sits at (s - 1/2) dz_s and follows the step reaching it:
+    10 m slabs with dz = 0.1 m give steps 49, 149, ...; exact ties
+    (z_s/dz = 1.5, 4.5) round up."""
+    import workloads as W
+    c3 = W.config3(2)[0]
+    assert c3.screen_steps()[:3] == [49, 149, 249]
+    tie = W.Instance(n=64, length=0.01, dz=0.01, n_steps=9, medium=W.Medium(),
+                     w0=1e-3, power=1.0, sigma=0.0, seed=0, cn2=1e-13,
+                     screen_dz=0.03, n_screens=3)
+    tie.medium.terms = W.TERM_TURB
+    assert tie.screen_steps() == [1, 4, 7]
+    assert sorted(T.instance_screens(tie)) == [1, 4, 7]

@@ -22,7 +22,8 @@ Readings of the paper that fix the numbers below (Math and Equations, Eq. (1),
 * Amplitude noise is multiplicative, ``(1 + sigma eta)`` with ``eta`` a unit
   complex normal, after which the field is rescaled to the exact power.
 * Turbulence screens sit at slab mid-planes ``z_s = (s - 1/2) dz_s`` and are
-  applied at the end of the step that reaches ``z_s``.
+  applied at the end of step ``floor(z_s/dz + 1/2) - 1`` (the step that
+  reaches z_s, ties rounded up).
 
 All lengths are in metres, powers in W, intensities in W/m^2.
 """
@@ -100,11 +101,12 @@ class Instance:
         return self.length / self.n
 
     def screen_steps(self) -> List[int]:
-        """Step index after which each turbulence screen is applied."""
+        """Step index after which each turbulence screen is applied:
+        floor(z_s/dz + 1/2) - 1 (ties round up)."""
         out = []
         for s in range(1, self.n_screens + 1):
             z_s = (s - 0.5) * self.screen_dz
-            out.append(int(round(z_s / self.dz)) - 1)
+            out.append(int(math.floor(z_s / self.dz + 0.5)) - 1)
         return out
 
 
