@@ -69,8 +69,11 @@ def run_gpu(args):
     out = {}
 
     def make(precision):
+        from paper_2306_15678_amd.tune import tune
         p = Propagator(_desc_list([inst]), precision=precision, max_steps=z_steps,
                        ckpt_every=ckpt, device=dev)
+        # pick the fastest tile variants (setup, not timed)
+        out["tune_fp%d" % precision] = tune(p, reps=30, use_cache=False)[inst.n]
         return p
 
     def fwd_adj(p):
@@ -215,6 +218,8 @@ def main():
                  "speedup_fp32_over_fp64": t64 / t32},
         "forward_only": {"value": g["fwd"]["value"], "ms_per_step": g["fwd"]["s_per_step"] * 1e3},
         "passes_ms": {"row": ps["ms_row"], "col": ps["ms_col"]},
+        "tile_variants": {"fp32": [g["tune_fp32"]["row"], g["tune_fp32"]["col"]],
+                          "fp64": [g["tune_fp64"]["row"], g["tune_fp64"]["col"]]},
         "parity": g["parity"],
     }
     if not args.no_cpu:

@@ -193,14 +193,22 @@ int ssfm_get_grad_theta(ssfm_ctx* ctx, int32_t inst, double* g);
 int ssfm_block_mean(ssfm_ctx* ctx, const double* src, int32_t n, int32_t b,
                     double* dst);
 
+/* FP32 screens evaluate sin/cos with the hardware v_sin/v_cos instructions
+ * after an exact-to-rounding reduction to [-1/2, 1/2] revolutions (0,
+ * default) or with the device math library's sincosf (1).  No effect on
+ * FP64 contexts. */
+int ssfm_set_precise_math(ssfm_ctx* ctx, int32_t enable);
+
 /* Run march steps through captured HIP graphs (1, default) or plain
  * launches (0). */
 int ssfm_use_graphs(ssfm_ctx* ctx, int32_t enable);
 
-/* Number of compiled FFT tile variants for grid size n, and selection of
- * the variant used by this context for that n (autotuner hook). */
-int ssfm_plan_variants(int32_t n, int32_t precision, int32_t* count);
-int ssfm_select_plan(ssfm_ctx* ctx, int32_t n, int32_t variant);
+/* Number of compiled FFT tile variants of the row pass and of the column
+ * pass for grid size n (points per thread, lines per workgroup), and the
+ * selection of the variants this context uses for that n (autotuner hook;
+ * drops the context's captured graphs). */
+int ssfm_plan_variants(int32_t n, int32_t precision, int32_t* n_row, int32_t* n_col);
+int ssfm_select_plan(ssfm_ctx* ctx, int32_t n, int32_t row_variant, int32_t col_variant);
 
 /* Time each pass kernel of one step in isolation with HIP events on the
  * context's stream: reps launches of the forward row pass and of the

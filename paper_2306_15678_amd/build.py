@@ -2,8 +2,9 @@
 
     python -m paper_2306_15678_amd.build
 
-The kernels are compiled in two halves (complex64 and complex128
-instantiations) in parallel with the host code, then linked with hipcc.
+The pass kernels are compiled in four units (row / column x complex64 /
+complex128) in parallel with the pointwise kernels and the host code, then
+linked with hipcc.
 """
 from __future__ import annotations
 
@@ -46,14 +47,12 @@ def build(verbose: bool = False, force: bool = True) -> str:
             return LIB
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
-    jobs = [
-        ([hipcc, f"--offload-arch={ARCH}", *COMMON, *DEVICE, "-DSSFM_INST_F32",
-          "-c", os.path.join(CSRC, "kernels.hip"), "-o", os.path.join(BUILD, "kernels_f32.o")]),
-        ([hipcc, f"--offload-arch={ARCH}", *COMMON, *DEVICE, "-DSSFM_INST_F64",
-          "-c", os.path.join(CSRC, "kernels.hip"), "-o", os.path.join(BUILD, "kernels_f64.o")]),
-        ([hipcc, f"--offload-arch={ARCH}", *COMMON, "-Wall", "-c", os.path.join(CSRC, "ssfm.cpp"),
-          "-o", os.path.join(BUILD, "ssfm.o")]),
-    ]
+    units = ["kernels", "pass_row_f32", "pass_row_f64", "pass_col_f32", "pass_col_f64"]
+    jobs = [[hipcc, f"--offload-arch={ARCH}", *COMMON, *DEVICE, "-c",
+             os.path.join(CSRC, u + ".hip"), "-o", os.path.join(BUILD, u + ".o")] for u in units]
+    jobs.append([hipcc, f"--offload-arch={ARCH}", *COMMON, "-Wall", "-c",
+                 os.path.join(CSRC, "ssfm.cpp"), "-o", os.path.join(BUILD, "ssfm.o")])
+    objs = [os.path.join(BUILD, u + ".o") for u in units] + [os.path.join(BUILD, "ssfm.o")]
     t0 = time.time()
     procs = [subprocess.Popen(j, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
              for j in jobs]
@@ -68,9 +67,7 @@ def build(verbose: bool = False, force: bool = True) -> str:
         msg = "\n".join(" ".join(j) + "\n" + out for j, out in failed)
         raise RuntimeError("libssfm build failed:\n" + msg)
     tmp = LIB + ".tmp"
-    link = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC",
-            os.path.join(BUILD, "kernels_f32.o"), os.path.join(BUILD, "kernels_f64.o"),
-            os.path.join(BUILD, "ssfm.o"), "-o", tmp]
+    link = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(link, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("libssfm link failed:\n" + " ".join(link) + "\n" + r.stdout)

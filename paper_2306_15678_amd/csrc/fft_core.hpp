@@ -18,7 +18,8 @@
 // exactly the thread's own register points, so an FFT needs LDS only
 // between stages, and FFT -> pointwise multiply -> inverse FFT needs no LDS
 // traffic at the junction.  Twiddles come from a table
-// tw[m] = exp(-2 pi i m / N) computed in FP64 on the host and rounded once.
+// tw[m] = exp(-2 pi i m / N) computed in FP64 on the host and rounded once;
+// each thread loads the ones it needs once and keeps them in registers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -232,15 +233,70 @@ struct LdsPointMajor {
   __device__ __forceinline__ void put(int p, cx<R> v) const { base[p * W] = v; }
 };
 
+// ------------------------------------------------------------ twiddles
+// A thread's twiddles for every stage are loaded once, before the first
+// stage (one batch of independent loads), and reused conjugated by the
+// inverse transform.  Stage s (span NS > 1, radix R) needs, for each of
+// its E/R butterflies b and r = 1..R-1, tw[r * (j mod NS) * N/(NS R)]
+// with j = t + T b.
+template <int N, int T, int... Rs>
+constexpr int twiddle_count() {
+  int ns = 1, c = 0;
+  ((c += (ns > 1 ? (N / T / Rs) * (Rs - 1) : 0), ns *= Rs), ...);
+  return c;
+}
+
+template <class P>
+struct TwCount;
+template <int N, int T, int L, int... Rs>
+struct TwCount<Plan<N, T, L, Radices<Rs...>>> {
+  static constexpr int value = twiddle_count<N, T, Rs...>();
+};
+
+template <typename R, int N, int T, int NS, int RAD>
+__device__ __forceinline__ void load_stage_twiddles(cx<R>* w, int t,
+                                                    const cx<R>* __restrict__ tw) {
+  constexpr int E = N / T, NB = E / RAD, TWS = N / (NS * RAD);
+  if constexpr (NS > 1) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int k = (t + T * b) % NS;
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) w[b * (RAD - 1) + r - 1] = tw[r * k * TWS];
+    }
+  }
+}
+
+template <typename R, int N, int T, int NS, int R0, int... Rest>
+__device__ __forceinline__ void load_twiddles_rec(cx<R>* w, int t,
+                                                  const cx<R>* __restrict__ tw) {
+  load_stage_twiddles<R, N, T, NS, R0>(w, t, tw);
+  if constexpr (sizeof...(Rest) > 0) {
+    constexpr int used = (NS > 1) ? (N / T / R0) * (R0 - 1) : 0;
+    load_twiddles_rec<R, N, T, NS * R0, Rest...>(w + used, t, tw);
+  }
+}
+
+template <typename R, int N, int T, int... Rs>
+__device__ __forceinline__ void load_twiddles_impl(cx<R>* w, int t,
+                                                   const cx<R>* __restrict__ tw,
+                                                   Radices<Rs...>) {
+  load_twiddles_rec<R, N, T, 1, Rs...>(w, t, tw);
+}
+
+template <typename R, class P>
+__device__ __forceinline__ void load_twiddles(cx<R>* w, int t, const cx<R>* __restrict__ tw) {
+  load_twiddles_impl<R, P::N, P::T>(w, t, tw, typename P::radices{});
+}
+
 // ---------------------------------------------------------- one stage
 template <typename R, int N, int T, int RAD, int NS, int DIR, bool FIRST,
           bool LAST, class Lds>
 __device__ __forceinline__ void fft_stage(cx<R>* v, int t, const Lds& lds,
-                                          const cx<R>* __restrict__ tw) {
+                                          const cx<R>* w) {
   constexpr int E = N / T;
   constexpr int NB = E / RAD;
   constexpr int STRIDE = N / RAD;
-  constexpr int TWS = N / (NS * RAD);
   static_assert(E % RAD == 0, "radix must divide points per thread");
   cx<R> a[NB][RAD];
 #pragma unroll
@@ -264,9 +320,8 @@ __device__ __forceinline__ void fft_stage(cx<R>* v, int t, const Lds& lds,
     if constexpr (NS > 1) {
 #pragma unroll
       for (int r = 1; r < RAD; ++r) {
-        cx<R> w = tw[r * k * TWS];
-        if constexpr (DIR > 0) w.im = -w.im;
-        a[b][r] = cmul(a[b][r], w);
+        const cx<R> ww = w[b * (RAD - 1) + r - 1];
+        a[b][r] = (DIR > 0) ? cmulc(a[b][r], ww) : cmul(a[b][r], ww);
       }
     }
     dft<RAD, DIR>(a[b]);
@@ -287,27 +342,27 @@ __device__ __forceinline__ void fft_stage(cx<R>* v, int t, const Lds& lds,
 template <typename R, int N, int T, int DIR, int NS, bool FIRST, class Lds,
           int R0, int... Rest>
 __device__ __forceinline__ void fft_stages(cx<R>* v, int t, const Lds& lds,
-                                           const cx<R>* __restrict__ tw) {
+                                           const cx<R>* w) {
   constexpr bool LAST = sizeof...(Rest) == 0;
-  fft_stage<R, N, T, R0, NS, DIR, FIRST, LAST>(v, t, lds, tw);
+  fft_stage<R, N, T, R0, NS, DIR, FIRST, LAST>(v, t, lds, w);
   if constexpr (!LAST) {
-    fft_stages<R, N, T, DIR, NS * R0, false, Lds, Rest...>(v, t, lds, tw);
+    constexpr int used = (NS > 1) ? (N / T / R0) * (R0 - 1) : 0;
+    fft_stages<R, N, T, DIR, NS * R0, false, Lds, Rest...>(v, t, lds, w + used);
   }
 }
 
 template <typename R, int N, int T, int DIR, class Lds, int... Rs>
 __device__ __forceinline__ void fft_line_impl(cx<R>* v, int t, const Lds& lds,
-                                              const cx<R>* __restrict__ tw,
-                                              Radices<Rs...>) {
-  fft_stages<R, N, T, DIR, 1, true, Lds, Rs...>(v, t, lds, tw);
+                                              const cx<R>* w, Radices<Rs...>) {
+  fft_stages<R, N, T, DIR, 1, true, Lds, Rs...>(v, t, lds, w);
 }
 
-// In-register FFT of one line (DIR = -1 forward, +1 inverse, unscaled).
-// On entry and exit v[e] holds point t + T*e.
+// In-register FFT of one line (DIR = -1 forward, +1 inverse, unscaled),
+// with the thread's twiddles preloaded by load_twiddles<R, P>.  On entry and
+// exit v[e] holds point t + T*e.
 template <typename R, class P, int DIR, class Lds>
-__device__ __forceinline__ void fft_line(cx<R>* v, int t, const Lds& lds,
-                                         const cx<R>* __restrict__ tw) {
-  fft_line_impl<R, P::N, P::T, DIR>(v, t, lds, tw, typename P::radices{});
+__device__ __forceinline__ void fft_line(cx<R>* v, int t, const Lds& lds, const cx<R>* w) {
+  fft_line_impl<R, P::N, P::T, DIR>(v, t, lds, w, typename P::radices{});
 }
 
 }  // namespace ssfm

@@ -1,0 +1,301 @@
+// pass_kernels.hpp -- the row and column pass kernels of the march.
+//
+// One z step of the march (Math and Equations, Eq. (1)-(3), (9)) is two
+// passes over the field, each a batch of 1-D lines:
+//   row pass     u <- F_x^-1 P_x F_x [S_{n-1}(u)]   (screen of the previous
+//                                                     step fused on load)
+//   column pass  u <- F_y^-1 P_y F_y u              (FP64 power partials)
+// where P_x P_y = exp(-i (kx^2 + ky^2) dz / 2k0) is the separable
+// diffraction factor and the 1/N of each inverse DFT is folded into P.
+// The field between steps is therefore the pre-screen field V_n; its
+// pending screen is applied by the next row pass, by the loss/cotangent
+// kernel or when the field is read out, so the fields the adjoint needs
+// are the march's own state and recording them costs no extra traffic.
+//
+// Each workgroup owns whole lines: a row workgroup reads and writes LINES
+// contiguous rows; a column workgroup reads W = LINES adjacent columns row
+// by row.  A thread first issues all of its loads (field points, propagator
+// values, twiddles of every stage, turbulence phases) as one batch, then
+// runs FFT -> multiply -> inverse FFT with LDS exchanges between radix
+// stages only.  The field loads and stores are the only HBM traffic:
+// 8 B read + 8 B written per point per pass (complex64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_core.hpp"
+#include "kernels.hpp"
+#include "plans.hpp"
+#include "screen.hpp"
+
+namespace ssfm {
+
+template <typename R>
+__device__ __forceinline__ ScreenConst<R> screen_const(const InstDev& in) {
+  ScreenConst<R> s;
+  s.cK = R(in.cK);
+  s.cM = R(in.cM);
+  s.inv2k1 = R(in.inv2k1);
+#pragma unroll
+  for (int p = 0; p < 8; ++p) s.th[p] = R(in.theta[p]);
+  s.K = in.K;
+  s.terms = in.terms;
+  return s;
+}
+
+// Turbulence plane applied after `step` (nullptr if none).
+template <typename R>
+__device__ __forceinline__ const R* find_plane(const R* screens, const int64_t* steps,
+                                               const InstDev& in, int64_t step) {
+  if (step < 0 || !(in.terms & T_TURB) || in.n_screens <= 0 || screens == nullptr)
+    return nullptr;
+  const int64_t* st = steps + in.steps_off;
+  for (int s = 0; s < in.n_screens; ++s) {
+    if (st[s] == step) return screens + in.screen_off + int64_t(s) * in.n * in.n;
+  }
+  return nullptr;
+}
+
+// Deterministic workgroup reduction of NV doubles (sum or max); the result
+// is valid in thread 0.  red: shared [THREADS/64][NV].
+template <int NV, int THREADS, bool MAX>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], double* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const double o = __shfl_xor(v[k], off, 64);
+      v[k] = MAX ? fmax(v[k], o) : v[k] + o;
+    }
+  }
+  constexpr int NW = (THREADS + 63) / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = red[k];
+      for (int w = 1; w < NW; ++w) s = MAX ? fmax(s, red[w * NV + k]) : s + red[w * NV + k];
+      v[k] = s;
+    }
+  }
+}
+
+template <class P>
+constexpr int tw_regs() {
+  return TwCount<P>::value > 0 ? TwCount<P>::value : 1;
+}
+
+// ------------------------------------------------------------ row pass
+template <typename R, class P, int KIND>
+__global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
+  constexpr int N = P::N, T = P::T, E = P::E;
+  using L = LdsLineMajor<R, N>;
+  __shared__ cx<R> lds_mem[P::LINES * L::LINE];
+  __shared__ double red[((P::THREADS + 63) / 64) * 8];
+
+  const WorkItem w = a.work[blockIdx.x];
+  if (w.inst < 0) return;
+  const InstDev& in = a.inst[w.inst];
+  if constexpr (KIND == ROW_INV) {
+    if (2 * a.pair >= in.n_screens || !(in.terms & T_TURB)) return;
+  }
+  const int line = threadIdx.x / T;
+  const int t = threadIdx.x - line * T;
+  const int64_t row = w.line0 + line;
+  const int64_t base = in.off + row * N;
+  const L lds{lds_mem + line * L::LINE};
+  const cx<R>* tables = static_cast<const cx<R>*>(a.tables);
+  const cx<R>* __restrict__ tw = tables + in.tw_off;
+  const cx<R>* __restrict__ prop = tables + in.prop_off;
+  const cx<R>* __restrict__ src = static_cast<const cx<R>*>(a.src) + base;
+  cx<R>* __restrict__ dst = static_cast<cx<R>*>(a.dst) + base;
+
+  // one batch of loads: field, propagator, twiddles, turbulence phases
+  cx<R> v[E];
+  cx<R> pr[E];
+  cx<R> wt[tw_regs<P>()];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = src[t + T * e];
+  if constexpr (KIND != ROW_INV) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) pr[e] = prop[t + T * e];
+  }
+  load_twiddles<R, P>(wt, t, tw);
+
+  if constexpr (KIND == ROW_FWD) {
+    if (a.step >= 0) {
+      const ScreenConst<R> sc = screen_const<R>(in);
+      const R* plane = find_plane(a.screens, a.screen_steps, in, a.step);
+      if (plane) {
+        const R* prow = plane + row * N;
+        R ph[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) ph[e] = prow[t + T * e];
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = screen_apply(sc, v[e], ph[e]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = screen_apply(sc, v[e], R(0));
+      }
+    }
+  }
+
+  if constexpr (KIND == ROW_INV) {
+    fft_line<R, P, +1>(v, t, lds, wt);
+  } else {
+    fft_line<R, P, -1>(v, t, lds, wt);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = (KIND == ROW_ADJ) ? cmulc(v[e], pr[e]) : cmul(v[e], pr[e]);
+    fft_line<R, P, +1>(v, t, lds, wt);
+  }
+
+  if constexpr (KIND == ROW_ADJ) {
+    if (a.step >= 0) {
+      const ScreenConst<R> sc = screen_const<R>(in);
+      const R* plane = find_plane(a.screens, a.screen_steps, in, a.step);
+      const R* prow = plane ? plane + row * N : nullptr;
+      const cx<R>* __restrict__ sv = static_cast<const cx<R>*>(a.aux) + base;
+      double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const R pt = prow ? prow[t + T * e] : R(0);
+        v[e] = screen_adjoint(sc, sv[t + T * e], v[e], pt, g);
+      }
+      if (in.terms & T_ANSATZ) {
+        block_reduce<8, P::THREADS, false>(g, red);
+        if (threadIdx.x == 0) {
+          double* acc = a.part + int64_t(w.widx) * 8;
+#pragma unroll
+          for (int p = 0; p < 8; ++p) acc[p] += g[p];
+        }
+      }
+    }
+  }
+
+#pragma unroll
+  for (int e = 0; e < E; ++e) dst[t + T * e] = v[e];
+}
+
+// --------------------------------------------------------- column pass
+template <typename R, class P, int KIND>
+__global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
+  constexpr int N = P::N, T = P::T, E = P::E, W = P::LINES;
+  using L = LdsPointMajor<R, W>;
+  __shared__ cx<R> lds_mem[N * W];
+  __shared__ double red[((P::THREADS + 63) / 64) * 2];
+
+  const WorkItem w = a.work[blockIdx.x];
+  if (w.inst < 0) return;
+  const InstDev& in = a.inst[w.inst];
+  if constexpr (KIND == COL_INV) {
+    if (2 * a.pair >= in.n_screens || !(in.terms & T_TURB)) return;
+  }
+  const int c = threadIdx.x % W;
+  const int t = threadIdx.x / W;
+  const int64_t col = w.line0 + c;
+  const int64_t base = in.off + col;
+  const L lds{lds_mem + c};
+  const cx<R>* tables = static_cast<const cx<R>*>(a.tables);
+  const cx<R>* __restrict__ tw = tables + in.tw_off;
+  const cx<R>* __restrict__ prop = tables + in.prop_off;
+  const cx<R>* __restrict__ src = static_cast<const cx<R>*>(a.src) + base;
+
+  cx<R> v[E];
+  cx<R> pr[E];
+  cx<R> wt[tw_regs<P>()];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = src[int64_t(t + T * e) * N];
+  if constexpr (KIND != COL_INV) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) pr[e] = prop[t + T * e];
+  }
+  load_twiddles<R, P>(wt, t, tw);
+
+  if constexpr (KIND == COL_INV) {
+    fft_line<R, P, +1>(v, t, lds, wt);
+  } else {
+    fft_line<R, P, -1>(v, t, lds, wt);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = (KIND == COL_ADJ) ? cmulc(v[e], pr[e]) : cmul(v[e], pr[e]);
+    fft_line<R, P, +1>(v, t, lds, wt);
+  }
+
+  if constexpr (KIND == COL_INV) {
+    // screen pair: real part -> plane 2p, imaginary part -> plane 2p+1
+    R* pre = a.planes_out + in.screen_off + int64_t(2 * a.pair) * N * N + col;
+    const bool has_im = 2 * a.pair + 1 < in.n_screens;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      pre[int64_t(t + T * e) * N] = v[e].re;
+      if (has_im) pre[int64_t(N) * N + int64_t(t + T * e) * N] = v[e].im;
+    }
+    return;
+  } else {
+    cx<R>* __restrict__ dst = static_cast<cx<R>*>(a.dst) + base;
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[int64_t(t + T * e) * N] = v[e];
+  }
+
+  if constexpr (KIND == COL_FWD) {
+    if (a.part != nullptr) {
+      const ScreenConst<R> sc = screen_const<R>(in);
+      double s[1] = {0.0}, m[1] = {0.0};
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const R x = v[e].re * v[e].re + v[e].im * v[e].im;
+        const double xa = double(x) * double(screen_amp2(sc, x));
+        s[0] += xa;
+        m[0] = fmax(m[0], xa);
+      }
+      block_reduce<1, P::THREADS, false>(s, red);
+      __syncthreads();
+      block_reduce<1, P::THREADS, true>(m, red + ((P::THREADS + 63) / 64));
+      if (threadIdx.x == 0) {
+        a.part[int64_t(w.widx) * 2 + 0] = s[0];
+        a.part[int64_t(w.widx) * 2 + 1] = m[0];
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------- launch
+template <typename R, class P, int KIND>
+hipError_t launch_one(int n_blocks, const PassArgs<R>& a, hipStream_t s) {
+  if constexpr (KIND >= COL_FWD) {
+    hipLaunchKernelGGL((k_col<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_row<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename R, int KIND>
+hipError_t launch_row_kind(int n, int v, int nb, const PassArgs<R>& a, hipStream_t s) {
+#define SSFM_RCASE(NN, VV, ...) \
+  if (n == NN && v == VV) return launch_one<R, typename RowPlanSel<NN, VV>::P, KIND>(nb, a, s);
+  SSFM_ROW_PLANS(SSFM_RCASE)
+#undef SSFM_RCASE
+  return hipErrorInvalidValue;
+}
+
+template <typename R, int KIND>
+hipError_t launch_col_kind(int n, int v, int nb, const PassArgs<R>& a, hipStream_t s) {
+#define SSFM_CCASE(NN, VV, ...) \
+  if (n == NN && v == VV) return launch_one<R, typename ColPlanSel<NN, VV>::P, KIND>(nb, a, s);
+  SSFM_COL_PLANS(SSFM_CCASE)
+#undef SSFM_CCASE
+  return hipErrorInvalidValue;
+}
+
+// Per-unit entry points (defined in pass_{row,col}_{f32,f64}.hip).
+template <typename R>
+hipError_t launch_row(int kind, int n, int v, int nb, const PassArgs<R>& a, hipStream_t s);
+template <typename R>
+hipError_t launch_col(int kind, int n, int v, int nb, const PassArgs<R>& a, hipStream_t s);
+
+}  // namespace ssfm

@@ -28,7 +28,8 @@ enum : unsigned {
   T_MPA = 2u,
   T_PLASMA = 4u,
   T_ANSATZ = 8u,
-  T_TURB = 16u
+  T_TURB = 16u,
+  T_PRECISE = 1u << 8  // FP32: library sincosf instead of v_sin/v_cos
 };
 
 template <typename R>
@@ -46,12 +47,28 @@ __device__ __forceinline__ R ipow(R x, int m) {
   return r;
 }
 
-__device__ __forceinline__ float fast_log2(float x) { return __log2f(x); }
+// FP32: hardware transcendentals (v_log_f32, v_exp_f32, v_rcp_f32 and
+// v_sin_f32 / v_cos_f32, which take their argument in revolutions).  The
+// phase is reduced to [-1/2, 1/2] revolutions first, so the hardware sine
+// sees a small argument; the reduction costs one multiply and one rint.
+// FP64 uses the device math library throughout.
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ double fast_log2(double x) { return log2(x); }
-__device__ __forceinline__ float fast_exp2(float x) { return exp2f(x); }
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ double fast_exp2(double x) { return exp2(x); }
-__device__ __forceinline__ void sin_cos(float a, float* s, float* c) { sincosf(a, s, c); }
-__device__ __forceinline__ void sin_cos(double a, double* s, double* c) { sincos(a, s, c); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ void sin_cos(float a, float* s, float* c, bool precise) {
+  if (precise) {
+    sincosf(a, s, c);
+    return;
+  }
+  float r = a * 0.15915494309189533577f;  // radians -> revolutions
+  r -= rintf(r);
+  *s = __builtin_amdgcn_sinf(r);
+  *c = __builtin_amdgcn_cosf(r);
+}
+__device__ __forceinline__ void sin_cos(double a, double* s, double* c, bool) { sincos(a, s, c); }
 
 // ln A and Phi (without turbulence) at x.
 template <typename R>
@@ -63,14 +80,15 @@ __device__ __forceinline__ void screen_eval(const ScreenConst<R>& s, R x,
   R xk1 = R(0);
   if (tm & (T_MPA | T_PLASMA)) xk1 = ipow(x, s.K - 1);
   if (tm & T_KERR) phi += s.cK * x;
-  if (tm & T_PLASMA) phi -= s.cK * x * xk1 / (R(1) + xk1);
+  // x^K/(1+x^(K-1)) written as x (1 - 1/(1+x^(K-1))): finite for any x
+  if (tm & T_PLASMA) phi -= s.cK * x * (R(1) - rcp(R(1) + xk1));
   if (tm & T_MPA) {
     // ln A = -log2(1 + cM x^(K-1)) ln2 / (2(K-1))
     log_a -= fast_log2(R(1) + s.cM * xk1) * (R(0.69314718055994530942) * s.inv2k1);
   }
   if (tm & T_ANSATZ) {
     const R x2 = x * x, x3 = x2 * x, x4 = x2 * x2;
-    const R inv = R(1) / (R(1) + x4);
+    const R inv = rcp(R(1) + x4);
     const R re = (s.th[0] * x + s.th[1] * x2 + s.th[2] * x3 + s.th[3] * x4) * inv;
     const R im = (s.th[4] * x + s.th[5] * x2 + s.th[6] * x3 + s.th[7] * x4) * inv;
     phi += s.cK * re;
@@ -89,8 +107,8 @@ __device__ __forceinline__ R screen_amp2(const ScreenConst<R>& s, R x) {
   }
   if (tm & T_ANSATZ) {
     const R x2 = x * x, x3 = x2 * x, x4 = x2 * x2;
-    const R im = (s.th[4] * x + s.th[5] * x2 + s.th[6] * x3 + s.th[7] * x4) /
-                 (R(1) + x4);
+    const R im = (s.th[4] * x + s.th[5] * x2 + s.th[6] * x3 + s.th[7] * x4) *
+                 rcp(R(1) + x4);
     l2 -= R(2) * s.cK * im * R(1.44269504088896340736);
   }
   if (l2 == R(0)) return R(1);
@@ -107,7 +125,7 @@ __device__ __forceinline__ cx<R> screen_apply(const ScreenConst<R>& s, cx<R> u,
   phi += phi_t;
   const R a = (log_a == R(0)) ? R(1) : fast_exp2(log_a * R(1.44269504088896340736));
   R sn, cs;
-  sin_cos(phi, &sn, &cs);
+  sin_cos(phi, &sn, &cs, (s.terms & T_PRECISE) != 0);
   return {a * (u.re * cs - u.im * sn), a * (u.re * sn + u.im * cs)};
 }
 
@@ -121,7 +139,7 @@ __device__ __forceinline__ cx<R> screen_adjoint(const ScreenConst<R>& s,
   const unsigned tm = s.terms;
   if (phi_t != R(0)) {  // lam <- conj(T) lam
     R sn, cs;
-    sin_cos(phi_t, &sn, &cs);
+    sin_cos(phi_t, &sn, &cs, (tm & T_PRECISE) != 0);
     lam = {lam.re * cs + lam.im * sn, lam.im * cs - lam.re * sn};
   }
   const R x = v.re * v.re + v.im * v.im;
@@ -136,19 +154,21 @@ __device__ __forceinline__ cx<R> screen_adjoint(const ScreenConst<R>& s,
     dphi += s.cK;
   }
   if (tm & T_PLASMA) {
-    const R d = R(1) + xk1;
-    phi -= s.cK * x * xk1 / d;
-    dphi -= s.cK * xk1 * (R(s.K) + xk1) / (d * d);
+    // with id = 1/(1+x^(K-1)): x^(K-1) id = 1 - id (no overflow at large x)
+    const R id = rcp(R(1) + xk1);
+    const R sat = R(1) - id;
+    phi -= s.cK * x * sat;
+    dphi -= s.cK * sat * (R(s.K) * id + sat);
   }
   if (tm & T_MPA) {
     const R q = R(1) + s.cM * xk1;
     log_a -= fast_log2(q) * (R(0.69314718055994530942) * s.inv2k1);
-    dla -= s.cM * xk2 / (R(2) * q);
+    dla -= s.cM * xk2 * R(0.5) * rcp(q);
   }
   R bx[4] = {R(0), R(0), R(0), R(0)};
   if (tm & T_ANSATZ) {
     const R x2 = x * x, x3 = x2 * x, x4 = x2 * x2;
-    const R inv = R(1) / (R(1) + x4);
+    const R inv = rcp(R(1) + x4);
     const R gre = s.th[0] * x + s.th[1] * x2 + s.th[2] * x3 + s.th[3] * x4;
     const R gim = s.th[4] * x + s.th[5] * x2 + s.th[6] * x3 + s.th[7] * x4;
     const R dgre = s.th[0] + R(2) * s.th[1] * x + R(3) * s.th[2] * x2 + R(4) * s.th[3] * x3;
@@ -166,7 +186,7 @@ __device__ __forceinline__ cx<R> screen_adjoint(const ScreenConst<R>& s,
   }
   const R a = (log_a == R(0)) ? R(1) : fast_exp2(log_a * R(1.44269504088896340736));
   R sn, cs;
-  sin_cos(phi, &sn, &cs);
+  sin_cos(phi, &sn, &cs, (tm & T_PRECISE) != 0);
   const cx<R> e = {a * cs, a * sn};
   // 1 + x conj(g), g = dla + i dphi
   const cx<R> one_xg = {R(1) + x * dla, -x * dphi};

@@ -803,11 +803,11 @@ int do_set_field(ssfm_ctx* c, int b, const void* src, int32_t where) {
   return SSFM_OK;
 }
 
-int do_select(ssfm_ctx* c, int32_t n, int32_t variant) {
+int do_select(ssfm_ctx* c, int32_t n, int32_t rv, int32_t cv) {
   const int rc = plan_count(false, n), cc = plan_count(true, n);
   if (rc == 0) return fail(SSFM_EUNSUPPORTED, "grid size %d not supported", n);
-  if (variant < 0 || variant >= rc * cc)
-    return fail(SSFM_EINVAL, "variant %d out of range [0, %d)", variant, rc * cc);
+  if (rv < 0 || rv >= rc || cv < 0 || cv >= cc)
+    return fail(SSFM_EINVAL, "variant (%d, %d) out of range [0, %d) x [0, %d)", rv, cv, rc, cc);
   bool found = false;
   VariantMap vm;
   for (auto& g : c->groups) {
@@ -815,7 +815,7 @@ int do_select(ssfm_ctx* c, int32_t n, int32_t variant) {
     if (g.n == n) found = true;
   }
   if (!found) return fail(SSFM_EINVAL, "no instance with n=%d in this context", n);
-  vm[n] = {variant / cc, variant % cc};
+  vm[n] = {rv, cv};
   // rebuild work lists; the layout's partial arrays are already sized for
   // the variant with the most work items, so offsets stay valid
   Layout L2;
@@ -1088,23 +1088,36 @@ int ssfm_block_mean(ssfm_ctx* c, const double* src, int32_t n, int32_t b, double
   return SSFM_OK;
 }
 
+int ssfm_set_precise_math(ssfm_ctx* c, int32_t enable) {
+  if (int r = check_ctx(c)) return r;
+  for (auto& in : c->inst) {
+    if (enable) in.terms |= (1u << 8);
+    else in.terms &= ~(1u << 8);
+  }
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.inst, c->inst.data(), sizeof(InstDev) * c->inst.size(),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return SSFM_OK;
+}
+
 int ssfm_use_graphs(ssfm_ctx* c, int32_t enable) {
   if (int r = check_ctx(c)) return r;
   c->use_graphs = enable != 0;
   return SSFM_OK;
 }
 
-int ssfm_plan_variants(int32_t n, int32_t precision, int32_t* count) {
-  if (!count) return fail(SSFM_EINVAL, "count is NULL");
+int ssfm_plan_variants(int32_t n, int32_t precision, int32_t* n_row, int32_t* n_col) {
+  if (!n_row || !n_col) return fail(SSFM_EINVAL, "n_row/n_col is NULL");
   if (precision != SSFM_FP32 && precision != SSFM_FP64) return fail(SSFM_EINVAL, "precision");
-  *count = plan_count(false, n) * plan_count(true, n);
-  if (*count == 0) return fail(SSFM_EUNSUPPORTED, "grid size %d not supported", n);
+  *n_row = plan_count(false, n);
+  *n_col = plan_count(true, n);
+  if (*n_row == 0 || *n_col == 0) return fail(SSFM_EUNSUPPORTED, "grid size %d not supported", n);
   return SSFM_OK;
 }
 
-int ssfm_select_plan(ssfm_ctx* c, int32_t n, int32_t variant) {
+int ssfm_select_plan(ssfm_ctx* c, int32_t n, int32_t row_variant, int32_t col_variant) {
   if (int r = check_ctx(c)) return r;
-  return do_select(c, n, variant);
+  return do_select(c, n, row_variant, col_variant);
 }
 
 int ssfm_time_passes(ssfm_ctx* c, int32_t reps, double* ms_row, double* ms_col,

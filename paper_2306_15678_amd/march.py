@@ -182,11 +182,14 @@ class Propagator:
         return pw, pk
 
     # ------------------------------------------------------------- tuning
+    def set_precise_math(self, enable: bool) -> None:
+        L.call("ssfm_set_precise_math", self.ctx, 1 if enable else 0)
+
     def use_graphs(self, enable: bool) -> None:
         L.call("ssfm_use_graphs", self.ctx, 1 if enable else 0)
 
-    def select_plan(self, n: int, variant: int) -> None:
-        L.call("ssfm_select_plan", self.ctx, n, variant)
+    def select_plan(self, n: int, row_variant: int, col_variant: int) -> None:
+        L.call("ssfm_select_plan", self.ctx, n, row_variant, col_variant)
 
     def time_passes(self, reps: int = 20):
         """(ms_row, ms_col, bytes_row, bytes_col) per launch of one pass."""
@@ -203,7 +206,8 @@ class Propagator:
         return out
 
 
-def plan_variants(n: int, precision: int = 32) -> int:
-    c = ctypes.c_int32()
-    L.call("ssfm_plan_variants", n, precision, ctypes.byref(c))
-    return c.value
+def plan_variants(n: int, precision: int = 32) -> Tuple[int, int]:
+    """(row variants, column variants) compiled for grid size n."""
+    r, c = ctypes.c_int32(), ctypes.c_int32()
+    L.call("ssfm_plan_variants", n, precision, ctypes.byref(r), ctypes.byref(c))
+    return r.value, c.value

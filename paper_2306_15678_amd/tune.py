@@ -1,0 +1,87 @@
+"""Autotuner of the FFT tile variants (points per thread, lines per
+workgroup) of the row and column passes.
+
+For every grid size present in a ``Propagator`` it times each compiled
+variant of the forward row pass and of the forward column pass with the
+library's HIP-event timing hook (``ssfm_time_passes``: launches on the
+context's stream), keeps the fastest of each and selects them.  Results are
+cached in a JSON file keyed by device name, grid size and precision
+(``SSFM_TUNE_CACHE``, default ``~/.cache/ssfm_tune.json``).
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict
+
+import torch
+
+from .march import Propagator, plan_variants
+
+
+def _cache_path() -> str:
+    return os.environ.get("SSFM_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "ssfm_tune.json"))
+
+
+def _key(n: int, precision: int) -> str:
+    name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+    return f"{name}|n={n}|fp{precision}"
+
+
+def load_cache() -> Dict:
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(d: Dict) -> None:
+    path = _cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(d, f, indent=1)
+    except OSError:
+        pass
+
+
+def tune(prop: Propagator, reps: int = 50, use_cache: bool = True,
+         verbose: bool = False) -> Dict[int, Dict]:
+    """Select the fastest row and column variants for each grid size of
+    ``prop`` and return the timings.  The timing launches advance the
+    context's fields: call before ``set_field``."""
+    cache = load_cache() if use_cache else {}
+    out = {}
+    for n in sorted({d.n for d in prop.descs}):
+        key = _key(n, prop.precision)
+        if use_cache and key in cache:
+            best = cache[key]
+            prop.select_plan(n, best["row"], best["col"])
+            out[n] = best
+            continue
+        n_row, n_col = plan_variants(n, prop.precision)
+        rows, cols = [], []
+        # rows vary with the column variant fixed, then the other way round
+        for v in range(n_row):
+            prop.select_plan(n, v, 0)
+            ms_row, _, _, _ = prop.time_passes(reps)
+            rows.append((ms_row, v))
+        for v in range(n_col):
+            prop.select_plan(n, 0, v)
+            _, ms_col, _, _ = prop.time_passes(reps)
+            cols.append((ms_col, v))
+        br, bc = min(rows)[1], min(cols)[1]
+        prop.select_plan(n, br, bc)
+        best = {"row": br, "col": bc, "ms_row": min(rows)[0], "ms_col": min(cols)[0],
+                "rows_ms": [r[0] for r in rows], "cols_ms": [c[0] for c in cols]}
+        if verbose:
+            print(f"tune n={n} fp{prop.precision}: rows(us)="
+                  f"{[round(r[0] * 1e3, 2) for r in rows]} cols(us)="
+                  f"{[round(c[0] * 1e3, 2) for c in cols]} -> row {br}, col {bc}", flush=True)
+        cache[key] = best
+        out[n] = best
+    if use_cache:
+        save_cache(cache)
+    return out

@@ -11,7 +11,12 @@ therefore stated relative to a floor measured on the oracle itself:
 * ``step32`` / ``step64``: the same, but a perturbation of size
   eps sqrt(4 log2 N + 4) injected at every step (the expected relative
   rounding of one FP32/FP64 step: four length-N FFTs plus pointwise
-  multiplies), maximum over two noise seeds.
+  multiplies), maximum over two noise seeds;
+* ``peer32``: rel L2 between the oracle and an independent complex64
+  implementation of the same discrete map (torch on the CPU, normalised
+  intensity x = I/I_a, FP32 tables, FFTs and screen).  FP32 rounding of
+  tables, twiddles and coefficients acts coherently from step to step, which
+  the random models above do not capture; this peer measures it directly.
 
 Writes tests/golden/floor_<name>.json with the field and fluence floors at
 the listed step counts, and the oracle's own samples of the reference run at
@@ -92,6 +97,11 @@ def floors(inst, n_steps, every, screens=None):
                     wmax[k] = max(wmax[k], M.rel_l2(np.abs(u) ** 2, np.abs(ref[marks[k]]) ** 2))
                     k += 1
         out[name] = {"field": fmax.tolist(), "fluence": wmax.tolist()}
+    if not screens and not (inst.medium.terms & W.TERM_ANSATZ):
+        peer = peer32(inst, marks)
+        out["peer32"] = {
+            "field": [M.rel_l2(peer[m], ref[m]) for m in marks],
+            "fluence": [M.rel_l2(np.abs(peer[m]) ** 2, np.abs(ref[m]) ** 2) for m in marks]}
     return out
 
 
@@ -103,6 +113,37 @@ def _quarters(marks):
         m = min(marks, key=lambda v: abs(v - q * last))
         if m not in out:
             out.append(m)
+    return out
+
+
+def peer32(inst, marks):
+    """complex64 march of the same map (torch CPU), normalised units."""
+    import torch
+    m = inst.medium
+    n = inst.n
+    k0 = 2.0 * math.pi / m.wavelength
+    k = 2.0 * math.pi * np.fft.fftfreq(n, d=inst.length / n)
+    prop = np.exp(-1j * (k[None, :] ** 2 + k[:, None] ** 2) * inst.dz / (2 * k0))
+    P = torch.from_numpy(prop.astype(np.complex64))
+    cK = torch.tensor(k0 * m.n2 * m.i_ref * inst.dz, dtype=torch.float32)
+    K = m.mpa_order
+    cM = torch.tensor((K - 1) * m.beta_k * m.i_ref ** (K - 1) * inst.dz, dtype=torch.float32)
+    u = torch.from_numpy((W.initial_field(inst) / math.sqrt(m.i_ref)).astype(np.complex64))
+    out = {}
+    for step in range(1, marks[-1] + 1):
+        v = torch.fft.ifft2(P * torch.fft.fft2(u))
+        x = (v.real ** 2 + v.imag ** 2)
+        ph = torch.zeros_like(x)
+        la = torch.zeros_like(x)
+        if m.terms & W.TERM_KERR:
+            ph = ph + cK * x
+        if m.terms & W.TERM_PLASMA:
+            ph = ph - cK * x ** K / (1 + x ** (K - 1))
+        if m.terms & W.TERM_MPA:
+            la = la - torch.log(1 + cM * x ** (K - 1)) / (2 * (K - 1))
+        u = v * torch.exp(la) * torch.polar(torch.ones_like(ph), ph)
+        if step in marks:
+            out[step] = u.numpy().astype(np.complex128) * math.sqrt(m.i_ref)
     return out
 
 
@@ -126,7 +167,7 @@ def main():
     path = os.path.join(HERE, f"floor_{args.config}.json")
     with open(path, "w") as f:
         json.dump(res, f, indent=1)
-    for k in ("in64", "in32", "step64", "step32"):
+    for k in ("in64", "in32", "step64", "step32", "peer32"):
         print(k, "field", ["%.1e" % x for x in res[k]["field"]])
         print(k, "fluence", ["%.1e" % x for x in res[k]["fluence"]])
 

@@ -100,7 +100,8 @@ def test_null_context_is_rejected():
 
 
 def test_plan_variant_counts():
-    c = ctypes.c_int32()
+    r, c = ctypes.c_int32(), ctypes.c_int32()
     for n in (128, 256, 512, 768, 1024, 2048, 4096):
-        assert L.lib().ssfm_plan_variants(n, 32, ctypes.byref(c)) == 0 and c.value >= 1
-    assert L.lib().ssfm_plan_variants(100, 32, ctypes.byref(c)) == L.EUNSUPPORTED
+        assert L.lib().ssfm_plan_variants(n, 32, ctypes.byref(r), ctypes.byref(c)) == 0
+        assert r.value >= 2 and c.value >= 2
+    assert L.lib().ssfm_plan_variants(100, 32, ctypes.byref(r), ctypes.byref(c)) == L.EUNSUPPORTED

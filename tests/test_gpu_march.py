@@ -30,17 +30,18 @@ def _report(name, **vals):
 
 
 # ------------------------------------------------------------------ C1
-# Rounding floors of this march (tests/golden/floor_c1.json, written by
-# tests/golden/calibrate_floor.py c1 from the oracle alone): the rel L2 drift
-# of the FP64 oracle itself under per-step perturbations of one FP32 / FP64
-# step's rounding size.  The beam collapses near step 110 (Kerr only, no
-# arrest), after which the march is chaotic and the floor grows ~1000x.
-#                  step 100 field / fluence      step 200 field / fluence
-#   FP64 floor     1.8e-14 / 2.6e-14              2.7e-11 / 5.0e-12
-#   FP32 floor     7.0e-6  / 1.0e-5               1.2e-2  / 2.2e-3
-# Tolerance: 10x the floor.
+# Rounding floors of this march, from tests/golden/floor_c1.json (written by
+# tests/golden/calibrate_floor.py c1, which runs the oracle and an
+# independent complex64 peer of the same map on the CPU).  The beam
+# collapses near step 110 (Kerr only, no arrest); after that the march is
+# chaotic and every floor grows ~1000x.
+#                            step 100 field / fluence    step 200 field / fluence
+#   FP64 per-step rounding   1.8e-14 / 2.6e-14             2.7e-11 / 5.0e-12
+#   FP32 per-step rounding   7.0e-6  / 1.0e-5              1.2e-2  / 2.2e-3
+#   FP32 peer vs oracle      5.0e-5  / 7.3e-5              4.4e-2  / 8.2e-3
+# Tolerance: FP64 10x its floor; FP32 5x the larger FP32 floor (the peer).
 C1_TOL = {64: {100: (2e-13, 3e-13), 200: (3e-10, 5e-11)},
-          32: {100: (7e-5, 1e-4), 200: (1.2e-1, 2.2e-2)}}
+          32: {100: (2.5e-4, 3.7e-4), 200: (2.2e-1, 4.1e-2)}}
 
 
 @pytest.mark.parametrize("precision", [64, 32])
@@ -286,3 +287,27 @@ def test_autograd_function_matches_oracle_gradient():
     terr = float(np.max(np.abs(tth.grad.cpu().numpy() - g_th)) / np.max(np.abs(g_th)))
     _report("autograd fp64", loss=lerr, g_u0=ferr, g_theta=terr)
     assert lerr < 1e-10 and ferr < 1e-10 and terr < 1e-10
+
+
+@pytest.mark.parametrize("n", [128, 256, 512, 768, 1024, 2048, 4096])
+def test_every_tile_variant_matches_oracle(n):
+    """Each compiled row and column variant (points per thread, lines per
+    workgroup, radix plan) computes the same march: FP64 kernels against the
+    oracle to rounding, 3 steps with every screen term."""
+    from paper_2306_15678_amd.march import plan_variants
+    terms = W.KPM | W.TERM_ANSATZ
+    theta = tuple(np.array(W.THETA0) + W.random_theta(n + 1, 0.2))
+    inst = _strong(n, terms, theta=theta, n_steps=3)
+    u0 = W.initial_field(inst)
+    ref = M.march(u0, inst)
+    n_row, n_col = plan_variants(n, 64)
+    combos = [(r, 0) for r in range(n_row)] + [(0, c) for c in range(1, n_col)]
+    p = _prop([inst], 64)
+    p.set_theta(0, theta)
+    for r, c in combos:
+        p.select_plan(n, r, c)
+        p.set_field(0, u0)
+        p.propagate(inst.n_steps)
+        err = M.rel_l2(p.field(0), ref.field)
+        _report(f"variant n={n} row={r} col={c}", field=err)
+        assert err < 1e-11, (r, c)
