@@ -106,42 +106,57 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
   }
   const int line = threadIdx.x / T;
   const int t = threadIdx.x - line * T;
-  const int64_t row = w.line0 + line;
-  const int64_t base = in.off + row * N;
+  const int row = w.line0 + line;
+  // uniform base of this workgroup's rows; per-thread 32-bit offsets
+  const int64_t wbase = in.off + int64_t(w.line0) * N;
+  const uint32_t toff = uint32_t(line) * N + uint32_t(t);
   const L lds{lds_mem + line * L::LINE};
   const cx<R>* tables = static_cast<const cx<R>*>(a.tables);
   const cx<R>* __restrict__ tw = tables + in.tw_off;
   const cx<R>* __restrict__ prop = tables + in.prop_off;
-  const cx<R>* __restrict__ src = static_cast<const cx<R>*>(a.src) + base;
-  cx<R>* __restrict__ dst = static_cast<cx<R>*>(a.dst) + base;
+  const cx<R>* __restrict__ src = static_cast<const cx<R>*>(a.src) + wbase;
+  cx<R>* __restrict__ dst = static_cast<cx<R>*>(a.dst) + wbase;
 
-  // one batch of loads: field, propagator, twiddles, turbulence phases
+  // one batch of loads: field, propagator, twiddles (and, for the adjoint,
+  // the stored pre-screen field and turbulence phases)
   cx<R> v[E];
   cx<R> pr[E];
   cx<R> wt[tw_regs<P>()];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = src[t + T * e];
+  for (int e = 0; e < E; ++e) v[e] = src[toff + uint32_t(T * e)];
   if constexpr (KIND != ROW_INV) {
 #pragma unroll
     for (int e = 0; e < E; ++e) pr[e] = prop[t + T * e];
   }
   load_twiddles<R, P>(wt, t, tw);
+  cx<R> sv[KIND == ROW_ADJ ? E : 1];
+  R ph[(KIND == ROW_ADJ || KIND == ROW_FWD) ? E : 1];
+  const R* plane = nullptr;
+  if constexpr (KIND == ROW_ADJ || KIND == ROW_FWD) {
+    plane = find_plane(a.screens, a.screen_steps, in, a.step);
+    if (plane) {
+      const R* pw = plane + int64_t(w.line0) * N;
+#pragma unroll
+      for (int e = 0; e < E; ++e) ph[e] = pw[toff + uint32_t(T * e)];
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) ph[e] = R(0);
+    }
+  }
+  if constexpr (KIND == ROW_ADJ) {
+    if (a.step >= 0) {
+      const cx<R>* __restrict__ svp = static_cast<const cx<R>*>(a.aux) + wbase;
+#pragma unroll
+      for (int e = 0; e < E; ++e) sv[e] = svp[toff + uint32_t(T * e)];
+    }
+  }
+  (void)row;
 
   if constexpr (KIND == ROW_FWD) {
     if (a.step >= 0) {
       const ScreenConst<R> sc = screen_const<R>(in);
-      const R* plane = find_plane(a.screens, a.screen_steps, in, a.step);
-      if (plane) {
-        const R* prow = plane + row * N;
-        R ph[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) ph[e] = prow[t + T * e];
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = screen_apply(sc, v[e], ph[e]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = screen_apply(sc, v[e], R(0));
-      }
+      for (int e = 0; e < E; ++e) v[e] = screen_apply(sc, v[e], ph[e]);
     }
   }
 
@@ -157,15 +172,9 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
   if constexpr (KIND == ROW_ADJ) {
     if (a.step >= 0) {
       const ScreenConst<R> sc = screen_const<R>(in);
-      const R* plane = find_plane(a.screens, a.screen_steps, in, a.step);
-      const R* prow = plane ? plane + row * N : nullptr;
-      const cx<R>* __restrict__ sv = static_cast<const cx<R>*>(a.aux) + base;
       double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const R pt = prow ? prow[t + T * e] : R(0);
-        v[e] = screen_adjoint(sc, sv[t + T * e], v[e], pt, g);
-      }
+      for (int e = 0; e < E; ++e) v[e] = screen_adjoint(sc, sv[e], v[e], ph[e], g);
       if (in.terms & T_ANSATZ) {
         block_reduce<8, P::THREADS, false>(g, red);
         if (threadIdx.x == 0) {
@@ -178,7 +187,7 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
   }
 
 #pragma unroll
-  for (int e = 0; e < E; ++e) dst[t + T * e] = v[e];
+  for (int e = 0; e < E; ++e) dst[toff + uint32_t(T * e)] = v[e];
 }
 
 // --------------------------------------------------------- column pass
@@ -197,19 +206,21 @@ __global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
   }
   const int c = threadIdx.x % W;
   const int t = threadIdx.x / W;
-  const int64_t col = w.line0 + c;
-  const int64_t base = in.off + col;
+  // uniform base (first column of the tile); per-thread 32-bit offsets
+  const int64_t wbase = in.off + w.line0;
+  const uint32_t toff = uint32_t(t) * N + uint32_t(c);
+  constexpr uint32_t ESTRIDE = uint32_t(T) * N;
   const L lds{lds_mem + c};
   const cx<R>* tables = static_cast<const cx<R>*>(a.tables);
   const cx<R>* __restrict__ tw = tables + in.tw_off;
   const cx<R>* __restrict__ prop = tables + in.prop_off;
-  const cx<R>* __restrict__ src = static_cast<const cx<R>*>(a.src) + base;
+  const cx<R>* __restrict__ src = static_cast<const cx<R>*>(a.src) + wbase;
 
   cx<R> v[E];
   cx<R> pr[E];
   cx<R> wt[tw_regs<P>()];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = src[int64_t(t + T * e) * N];
+  for (int e = 0; e < E; ++e) v[e] = src[toff + ESTRIDE * e];
   if constexpr (KIND != COL_INV) {
 #pragma unroll
     for (int e = 0; e < E; ++e) pr[e] = prop[t + T * e];
@@ -227,18 +238,19 @@ __global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
 
   if constexpr (KIND == COL_INV) {
     // screen pair: real part -> plane 2p, imaginary part -> plane 2p+1
-    R* pre = a.planes_out + in.screen_off + int64_t(2 * a.pair) * N * N + col;
+    R* pre = a.planes_out + in.screen_off + int64_t(2 * a.pair) * N * N + w.line0;
+    R* pim = pre + int64_t(N) * N;
     const bool has_im = 2 * a.pair + 1 < in.n_screens;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      pre[int64_t(t + T * e) * N] = v[e].re;
-      if (has_im) pre[int64_t(N) * N + int64_t(t + T * e) * N] = v[e].im;
+      pre[toff + ESTRIDE * e] = v[e].re;
+      if (has_im) pim[toff + ESTRIDE * e] = v[e].im;
     }
     return;
   } else {
-    cx<R>* __restrict__ dst = static_cast<cx<R>*>(a.dst) + base;
+    cx<R>* __restrict__ dst = static_cast<cx<R>*>(a.dst) + wbase;
 #pragma unroll
-    for (int e = 0; e < E; ++e) dst[int64_t(t + T * e) * N] = v[e];
+    for (int e = 0; e < E; ++e) dst[toff + ESTRIDE * e] = v[e];
   }
 
   if constexpr (KIND == COL_FWD) {

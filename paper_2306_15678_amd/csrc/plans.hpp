@@ -19,12 +19,15 @@ namespace ssfm {
   X(256, 1, 32, 8, 8, 8, 4)            \
   X(512, 0, 64, 4, 8, 8, 8)            \
   X(512, 1, 32, 8, 16, 16, 2)          \
+  X(512, 2, 64, 1, 8, 8, 8)            \
   X(768, 0, 32, 8, 8, 8, 4, 3)         \
   X(768, 1, 64, 4, 4, 4, 4, 4, 3)      \
   X(1024, 0, 64, 4, 16, 8, 8)          \
   X(1024, 1, 128, 2, 8, 8, 4, 4)       \
   X(1024, 2, 256, 1, 4, 4, 4, 4, 4)    \
   X(1024, 3, 64, 2, 16, 8, 8)          \
+  X(1024, 4, 64, 1, 16, 8, 8)          \
+  X(1024, 5, 128, 1, 8, 8, 4, 4)       \
   X(2048, 0, 128, 2, 16, 16, 8)        \
   X(2048, 1, 256, 1, 8, 8, 8, 4)       \
   X(4096, 0, 256, 1, 16, 16, 16)       \

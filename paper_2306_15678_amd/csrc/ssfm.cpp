@@ -87,7 +87,7 @@ int validate_desc(const ssfm_instance_desc* d, int32_t n_inst, int32_t precision
 // Device-side layout of everything a context keeps in the workspace.
 struct Layout {
   size_t inst, steps, work, wbegin_row, wbegin_col, tables;
-  size_t S, Wk, Lam, ckpt, stack, screens, stage, diag_part, diag, theta_acc,
+  size_t S, Wk, Wk2, Lam, ckpt, stack, screens, stage, diag_part, diag, theta_acc,
       theta_out, seed_loss, seed_theta, scal, sumsq_part;
   size_t total;
   int64_t field_elems;  // sum n^2
@@ -132,6 +132,9 @@ struct ssfm_ctx {
   bool rec_valid = false, seeded = false, grads_valid = false;
   bool use_graphs = true;
   std::map<std::tuple<int, int64_t, int64_t>, hipGraphExec_t> graphs;
+  // second stream (default priority) and events for the overlapped backward
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   template <typename T>
   T* at(size_t off) const {
@@ -142,6 +145,9 @@ struct ssfm_ctx {
   }
   ~ssfm_ctx() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (aux) (void)hipStreamDestroy(aux);
   }
 };
 
@@ -317,9 +323,13 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
   l.tables = take(el * te);
   l.S = take(el * fe);
   l.Wk = take(el * fe);
+  // with more than one segment, the recompute of the next segment runs
+  // beside the adjoint of the current one: a second work buffer and a
+  // second bank of segment slots
+  l.Wk2 = take(l.n_ckpt > 1 ? el * fe : 0);
   l.Lam = take(max_steps > 0 ? el * fe : 0);
   l.ckpt = take(el * fe * l.n_ckpt);
-  l.stack = take(el * fe * l.n_stack);
+  l.stack = take(el * fe * l.n_stack * (l.n_ckpt > 1 ? 2 : 1));
   l.screens = take(rel * se);
   l.stage = take(16 * size_t(max_n) * max_n);
   l.diag_part = take(sizeof(double) * 2 * kDiagChunk * nc_max);
@@ -397,30 +407,33 @@ PassArgs<R> base_args(ssfm_ctx* c) {
 }
 
 template <typename R>
-int run_pass(ssfm_ctx* c, int kind, PassArgs<R> a) {
+int run_pass(ssfm_ctx* c, int kind, PassArgs<R> a, hipStream_t st = nullptr) {
   const bool col = kind >= COL_FWD;
+  if (!st) st = c->stream;
   for (auto& g : c->groups) {
     a.work = c->at<WorkItem>(c->L.work) + (col ? g.col_work_off : g.row_work_off);
     const int nb = col ? g.col_blocks : g.row_blocks;
     const int v = col ? g.col_var : g.row_var;
-    HIP_TRY(launch_pass<R>(kind, g.n, v, nb, a, c->stream));
+    HIP_TRY(launch_pass<R>(kind, g.n, v, nb, a, st));
   }
   return SSFM_OK;
 }
 
-// One forward step: src (s_n) -> Wk -> dst (s_{n+1}).
+// One forward step: src (s_n) -> work -> dst (s_{n+1}), on stream st.
 template <typename R>
-int fwd_step(ssfm_ctx* c, const void* src, void* dst, int64_t pending_step, double* part) {
+int fwd_step(ssfm_ctx* c, const void* src, void* dst, int64_t pending_step, double* part,
+             void* work = nullptr, hipStream_t st = nullptr) {
+  if (!work) work = c->field(c->L.Wk);
   PassArgs<R> a = base_args<R>(c);
   a.src = src;
-  a.dst = c->field(c->L.Wk);
+  a.dst = work;
   a.step = pending_step;
-  if (int r = run_pass<R>(c, ROW_FWD, a)) return r;
+  if (int r = run_pass<R>(c, ROW_FWD, a, st)) return r;
   PassArgs<R> b = base_args<R>(c);
-  b.src = c->field(c->L.Wk);
+  b.src = work;
   b.dst = dst;
   b.part = part;
-  return run_pass<R>(c, COL_FWD, b);
+  return run_pass<R>(c, COL_FWD, b, st);
 }
 
 // One adjoint step: Lam -> Wk (columns) -> Lam (rows + adjoint screen with
@@ -585,32 +598,55 @@ int do_record(ssfm_ctx* c, int64_t n) {
   return SSFM_OK;
 }
 
+// Backward over the recorded march, segment by segment from the last.  With
+// more than one segment, segment k-1 is recomputed from its checkpoint on
+// the auxiliary stream (into the other bank of segment slots, with its own
+// work buffer) while the adjoint of segment k runs on the main stream; the
+// two chains join before the adjoint of segment k-1.
 template <typename R>
 int enqueue_backward(ssfm_ctx* c) {
   const int64_t n = c->rec_steps, step0 = c->rec_step0;
   const int64_t M = std::min<int64_t>(std::max<int32_t>(c->ckpt_every, 1), n);
   const int64_t n_seg = (n + M - 1) / M;
   const bool stored = n <= M;
-  HIP_TRY(launch_fill_f64(c->at<double>(c->L.theta_acc), 8 * c->L.n_widx_rows, 0.0, c->stream));
-  for (int64_t k = n_seg - 1; k >= 0; --k) {
+  const int64_t bank = c->L.n_stack;
+  auto slot = [&](int64_t k, int64_t i) -> void* {  // slot i of segment k's bank
+    return c->field(c->L.stack, (stored ? 0 : (k % 2) * bank) + i);
+  };
+  auto sv = [&](int64_t k, int64_t i) -> void* {  // s_{kM+i}
+    if (i == 0) return c->field(c->L.ckpt, k);
+    return slot(k, i - 1);
+  };
+  auto recompute = [&](int64_t k, void* work, hipStream_t st) -> int {
     const int64_t s0 = k * M;
     const int64_t len = std::min<int64_t>(M, n - s0);
-    auto sv = [&](int64_t i) -> void* {  // s_{s0+i}
-      if (i == 0) return c->field(c->L.ckpt, k);
-      return c->field(c->L.stack, i - 1);
-    };
-    if (!stored) {
-      for (int64_t i = 0; i + 1 < len; ++i) {
-        const int64_t g = s0 + i;
-        const int64_t pend = (g == 0) ? -1 : step0 + g - 1;
-        if (int r = fwd_step<R>(c, sv(i), c->field(c->L.stack, i), pend, nullptr)) return r;
-      }
+    for (int64_t i = 0; i + 1 < len; ++i) {
+      const int64_t g = s0 + i;
+      const int64_t pend = (g == 0) ? -1 : step0 + g - 1;
+      if (int r = fwd_step<R>(c, sv(k, i), slot(k, i), pend, nullptr, work, st)) return r;
     }
+    return SSFM_OK;
+  };
+  HIP_TRY(launch_fill_f64(c->at<double>(c->L.theta_acc), 8 * c->L.n_widx_rows, 0.0, c->stream));
+  if (!stored) {
+    if (int r = recompute(n_seg - 1, c->field(c->L.Wk), c->stream)) return r;
+  }
+  for (int64_t k = n_seg - 1; k >= 0; --k) {
+    const bool overlap = !stored && k >= 1;
+    if (overlap) {
+      HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
+      HIP_TRY(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+      if (int r = recompute(k - 1, c->field(c->L.Wk2), c->aux)) return r;
+      HIP_TRY(hipEventRecord(c->ev_join, c->aux));
+    }
+    const int64_t s0 = k * M;
+    const int64_t len = std::min<int64_t>(M, n - s0);
     for (int64_t i = len - 1; i >= 0; --i) {
       const int64_t g = s0 + i;
       const int64_t pend = (g == 0) ? -1 : step0 + g - 1;
-      if (int r = adj_step<R>(c, sv(i), pend)) return r;
+      if (int r = adj_step<R>(c, sv(k, i), pend)) return r;
     }
+    if (overlap) HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join, 0));
   }
   HIP_TRY(launch_reduce_rows(c->at<double>(c->L.theta_acc), 8, c->at<int32_t>(c->L.wbegin_row),
                              int(c->desc.size()), c->at<double>(c->L.theta_out), c->stream));
@@ -904,6 +940,9 @@ int ssfm_create(const ssfm_instance_desc* desc, int32_t n_inst, int32_t precisio
   if (ws_bytes < c->L.total)
     return fail(SSFM_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, c->L.total);
   c->ws = static_cast<char*>(workspace);
+  HIP_TRY(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
   int r = SSFM_DISPATCH(c, upload_plan, c.get());
   if (r) return r;
   *out = c.release();

@@ -226,13 +226,17 @@ def test_gradient_matches_oracle(precision, ckpt, turb):
     assert lerr < tol and ferr < tol and terr < tol
 
 
-def test_checkpointed_and_stored_adjoints_are_bitwise_equal():
+@pytest.mark.parametrize("graphs", [True, False])
+def test_checkpointed_and_stored_adjoints_are_bitwise_equal(graphs):
+    """3 segments (recompute of the next segment overlapped with the adjoint
+    of the current one on a second stream) against all steps stored."""
     inst = _grad_case()
     u0 = W.initial_field(inst)
     target = W.synthetic_target(inst, 5)
     res = []
     for ckpt in (3, 100):
         p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=ckpt)
+        p.use_graphs(graphs)
         p.set_field(0, u0)
         p.set_theta(0, inst.theta)
         p.forward_record(inst.n_steps)
