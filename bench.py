@@ -112,6 +112,34 @@ def run_gpu(args):
     return out
 
 
+def run_batched(args):
+    """Forward march of the 64 uneven beams with turbulence screens
+    (n in {256, 512, 768, 1024}, 2000 steps), one context, graph-captured."""
+    import torch
+
+    import workloads as W
+    from paper_2306_15678_amd.march import Propagator
+    from paper_2306_15678_amd.tune import tune
+
+    insts = W.config3()
+    p = Propagator(_desc_list(insts), precision=32, device=torch.device("cuda", 0))
+    tune(p, reps=10, use_cache=False)
+    p.gen_screens()
+    fields = [torch.from_numpy(W.initial_field(i)).to("cuda") for i in insts]
+
+    def fwd():
+        for b, u in enumerate(fields):
+            p.set_field(b, u)
+        p.propagate(insts[0].n_steps)
+
+    t = _timed(fwd, max(1, args.steps // 5), 1, p.synchronize)
+    ms_row, ms_col, b_row, b_col = p.time_passes(reps=20)
+    gp = float(sum(i.n * i.n for i in insts)) * insts[0].n_steps
+    p.close()
+    return {"s_per_step": t, "value": gp / t, "ms_row": ms_row, "ms_col": ms_col,
+            "bytes_pass": b_row}
+
+
 def parity_vs_stored(inst, power, peak, fluence, field):
     """Compare with the oracle's samples of this workload (written by
     tests/golden/calibrate_floor.py c2); None if the fixture is absent."""
@@ -170,6 +198,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--ckpt-every", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the march of one beam or a "
@@ -222,6 +251,18 @@ def main():
                           "fp64": [g["tune_fp64"]["row"], g["tune_fp64"]["col"]]},
         "parity": g["parity"],
     }
+    if not args.no_batched:
+        bt = run_batched(args)
+        dom_ms = max(bt["ms_row"], bt["ms_col"])
+        line["batched_forward"] = {
+            "workload": "64 beams, n in {256,512,768,1024}, 20 Kolmogorov screens each, "
+                        "Kerr+MPA+plasma, 2000 z steps, complex64, forward",
+            "value": bt["value"], "unit": "grid-point·steps/s",
+            "ms_per_march": bt["s_per_step"] * 1e3,
+            "passes_ms": {"row": bt["ms_row"], "col": bt["ms_col"]},
+            "dominant_pass_GBps": bt["bytes_pass"] / (dom_ms * 1e-3) / 1e9,
+            "dominant_pass_frac": bt["bytes_pass"] / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -24,6 +24,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 namespace ssfm {
 
 template <typename R>
@@ -188,6 +190,69 @@ __device__ __forceinline__ void dft16(cx<R>* v) {
 #undef SSFM_SWAP
 }
 
+// cos(e pi / 16) and sin(e pi / 16) for integer e (exact table of the
+// first octant, extended by symmetry).
+constexpr double kCos16[9] = {1.0,
+                              0.98078528040323044913,
+                              0.92387953251128675613,
+                              0.83146961230254523708,
+                              0.70710678118654752440,
+                              0.55557023301960222474,
+                              0.38268343236508977173,
+                              0.19509032201612826785,
+                              0.0};
+constexpr double cos16(int e) {
+  e = ((e % 32) + 32) % 32;
+  if (e <= 8) return kCos16[e];
+  if (e <= 16) return -kCos16[16 - e];
+  if (e <= 24) return -kCos16[e - 16];
+  return kCos16[32 - e];
+}
+constexpr double sin16(int e) { return cos16(8 - e); }
+
+// multiply by exp(dir 2 pi i e / 32)
+template <int DIR, int EXP, typename R>
+__device__ __forceinline__ cx<R> rot_32(cx<R> a) {
+  constexpr int e = ((EXP % 32) + 32) % 32;
+  if constexpr (e == 0) return a;
+  else if constexpr (e == 8) return rot_q<DIR>(a);
+  else if constexpr (e == 16) return cx<R>{-a.re, -a.im};
+  else if constexpr (e == 24) return rot_q<-DIR>(a);
+  else if constexpr (e == 4) return rot_8<DIR>(a);
+  else if constexpr (e == 12) return rot_38<DIR>(a);
+  else return cmul(a, cx<R>{R(cos16(e)), R(DIR * sin16(e))});
+}
+
+// 32 = 4 x 8: inner DFT8 over n2 (points n1 + 4 n2), twiddle w32^(n1 k2),
+// outer DFT4 over n1; output index k2 + 8 k1.
+template <int DIR, int N1, int K2, typename R>
+__device__ __forceinline__ void dft32_tw(cx<R>* v) {
+  v[N1 + 4 * K2] = rot_32<DIR, N1 * K2>(v[N1 + 4 * K2]);
+}
+
+template <int DIR, typename R>
+__device__ __forceinline__ void dft32(cx<R>* v) {
+  cx<R> t[32];
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) {
+    cx<R> g[8];
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) g[n2] = v[n1 + 4 * n2];
+    dft8<DIR>(g);
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) t[n1 + 4 * k2] = g[k2];
+  }
+  [&]<int... I>(std::integer_sequence<int, I...>) {
+    ((dft32_tw<DIR, I / 8, I % 8>(t)), ...);
+  }(std::make_integer_sequence<int, 32>{});
+#pragma unroll
+  for (int k2 = 0; k2 < 8; ++k2) {
+    dft4_<DIR>(t[4 * k2], t[4 * k2 + 1], t[4 * k2 + 2], t[4 * k2 + 3]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) v[k2 + 8 * k1] = t[4 * k2 + k1];
+  }
+}
+
 template <int RAD, int DIR, typename R>
 __device__ __forceinline__ void dft(cx<R>* v) {
   if constexpr (RAD == 2) dft2<DIR>(v);
@@ -195,6 +260,7 @@ __device__ __forceinline__ void dft(cx<R>* v) {
   else if constexpr (RAD == 4) dft4<DIR>(v);
   else if constexpr (RAD == 8) dft8<DIR>(v);
   else if constexpr (RAD == 16) dft16<DIR>(v);
+  else if constexpr (RAD == 32) dft32<DIR>(v);
   else static_assert(RAD == 2, "unsupported radix");
 }
 
@@ -202,14 +268,17 @@ __device__ __forceinline__ void dft(cx<R>* v) {
 template <int... Rs>
 struct Radices {};
 
-// N points per line, T threads per line, LINES lines per workgroup.
-template <int N_, int T_, int LINES_, class Rad>
+// N points per line, T threads per line, LINES lines per workgroup; column
+// tiles pad their LDS by B slots every A points (see LdsPointMajor).
+template <int N_, int T_, int LINES_, class Rad, int PA_ = 32, int PB_ = 0>
 struct Plan {
   static constexpr int N = N_;
   static constexpr int T = T_;
   static constexpr int LINES = LINES_;
   static constexpr int E = N_ / T_;
   static constexpr int THREADS = T_ * LINES_;
+  static constexpr int PA = PA_;
+  static constexpr int PB = PB_;
   using radices = Rad;
   static_assert(N_ % T_ == 0, "T must divide N");
 };
@@ -225,12 +294,15 @@ struct LdsLineMajor {
   __device__ __forceinline__ void put(int p, cx<R> v) const { base[p + (p >> 5)] = v; }
 };
 
-// Column tiles: point-major, the W columns of a point adjacent.
-template <typename R, int W>
+// Column tiles: point-major, the W columns of a point adjacent, B padding
+// slots after every A points.
+template <typename R, int W, int A, int B>
 struct LdsPointMajor {
+  static constexpr int size(int n) { return n * W + (n / A) * B; }
   cx<R>* base;  // already offset by the column index
-  __device__ __forceinline__ cx<R> get(int p) const { return base[p * W]; }
-  __device__ __forceinline__ void put(int p, cx<R> v) const { base[p * W] = v; }
+  __device__ __forceinline__ int idx(int p) const { return p * W + (p / A) * B; }
+  __device__ __forceinline__ cx<R> get(int p) const { return base[idx(p)]; }
+  __device__ __forceinline__ void put(int p, cx<R> v) const { base[idx(p)] = v; }
 };
 
 // ------------------------------------------------------------ twiddles
@@ -248,8 +320,8 @@ constexpr int twiddle_count() {
 
 template <class P>
 struct TwCount;
-template <int N, int T, int L, int... Rs>
-struct TwCount<Plan<N, T, L, Radices<Rs...>>> {
+template <int N, int T, int L, int... Rs, int A, int B>
+struct TwCount<Plan<N, T, L, Radices<Rs...>, A, B>> {
   static constexpr int value = twiddle_count<N, T, Rs...>();
 };
 

@@ -30,7 +30,8 @@ static void fill_info(bool fp64, PlanInfo* o) {
   o->threads = P::THREADS;
   o->lines = P::LINES;
   o->t = P::T;
-  o->lds = COLUMN ? el * P::N * P::LINES : el * P::LINES * LdsLineMajor<float, P::N>::LINE;
+  o->lds = COLUMN ? el * LdsPointMajor<float, P::LINES, P::PA, P::PB>::size(P::N)
+                  : el * P::LINES * LdsLineMajor<float, P::N>::LINE;
 }
 
 bool plan_info(bool column, int n, int v, bool fp64, PlanInfo* o) {

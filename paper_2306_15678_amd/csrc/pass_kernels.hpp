@@ -194,8 +194,8 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
 template <typename R, class P, int KIND>
 __global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
   constexpr int N = P::N, T = P::T, E = P::E, W = P::LINES;
-  using L = LdsPointMajor<R, W>;
-  __shared__ cx<R> lds_mem[N * W];
+  using L = LdsPointMajor<R, W, P::PA, P::PB>;
+  __shared__ cx<R> lds_mem[L::size(N)];
   __shared__ double red[((P::THREADS + 63) / 64) * 2];
 
   const WorkItem w = a.work[blockIdx.x];

@@ -1,9 +1,13 @@
 // plans.hpp -- compiled FFT tile variants of the row and column passes.
 //
-// X(N, variant, T, LINES, radices...): T threads per line, LINES lines per
-// workgroup (rows: LINES consecutive rows; columns: LINES adjacent columns,
-// read as LINES * sizeof(complex) contiguous bytes per row), radix plan in
-// stage order.  Variant 0 is the default; the autotuner picks among the
+// Rows: X(N, variant, T, LINES, radices...); columns: X(N, variant, T, W,
+// A, B, radices...).  T threads per line, LINES lines per workgroup (rows:
+// LINES consecutive rows; columns: W adjacent columns, read as
+// W * sizeof(complex) contiguous bytes per row), radix plan in stage order.
+// Column tiles keep point p of column c at LDS slot p W + c + (p / A) B:
+// the padding (A, B) is chosen per plan to spread the stage exchanges over
+// the LDS banks (64 banks of 4 bytes; a wave64 64-bit access served 32
+// lanes at a time).  Variant 0 is the default; the autotuner picks among the
 // others per grid size.  E = N/T points per thread: 16 keeps more work per
 // thread, 8 and 4 give 2x / 4x more wavefronts for latency hiding.
 #pragma once
@@ -28,29 +32,31 @@ namespace ssfm {
   X(1024, 3, 64, 2, 16, 8, 8)          \
   X(1024, 4, 64, 1, 16, 8, 8)          \
   X(1024, 5, 128, 1, 8, 8, 4, 4)       \
+  X(1024, 6, 32, 2, 32, 32)            \
   X(2048, 0, 128, 2, 16, 16, 8)        \
   X(2048, 1, 256, 1, 8, 8, 8, 4)       \
   X(4096, 0, 256, 1, 16, 16, 16)       \
   X(4096, 1, 512, 1, 8, 8, 8, 8)
 
 #define SSFM_COL_PLANS(X)              \
-  X(128, 0, 8, 32, 16, 8)              \
-  X(128, 1, 16, 16, 8, 4, 4)           \
-  X(256, 0, 16, 16, 16, 16)            \
-  X(256, 1, 32, 8, 8, 8, 4)            \
-  X(512, 0, 64, 4, 8, 8, 8)            \
-  X(512, 1, 32, 8, 16, 16, 2)          \
-  X(768, 0, 32, 8, 8, 8, 4, 3)         \
-  X(768, 1, 64, 4, 4, 4, 4, 4, 3)      \
-  X(1024, 0, 64, 4, 16, 8, 8)          \
-  X(1024, 1, 128, 2, 8, 8, 4, 4)       \
-  X(1024, 2, 128, 4, 8, 8, 4, 4)       \
-  X(1024, 3, 256, 2, 4, 4, 4, 4, 4)    \
-  X(1024, 4, 64, 8, 16, 8, 8)          \
-  X(2048, 0, 128, 2, 16, 16, 8)        \
-  X(2048, 1, 256, 2, 8, 8, 8, 4)       \
-  X(4096, 0, 256, 2, 16, 16, 16)       \
-  X(4096, 1, 512, 2, 8, 8, 8, 8)
+  X(128, 0, 8, 32, 1, 0, 16, 8) \
+  X(128, 1, 16, 16, 2, 4, 8, 4, 4) \
+  X(256, 0, 16, 16, 2, 2, 16, 16) \
+  X(256, 1, 32, 8, 4, 4, 8, 8, 4) \
+  X(512, 0, 64, 4, 8, 4, 8, 8, 8) \
+  X(512, 1, 32, 8, 4, 2, 16, 16, 2) \
+  X(768, 0, 32, 8, 4, 4, 8, 8, 4, 3) \
+  X(768, 1, 64, 4, 8, 4, 4, 4, 4, 4, 3) \
+  X(1024, 0, 64, 4, 8, 2, 16, 8, 8) \
+  X(1024, 1, 128, 2, 16, 2, 8, 8, 4, 4) \
+  X(1024, 2, 128, 4, 8, 4, 8, 8, 4, 4) \
+  X(1024, 3, 256, 2, 16, 6, 4, 4, 4, 4, 4) \
+  X(1024, 4, 64, 8, 4, 2, 16, 8, 8) \
+  X(1024, 5, 32, 8, 4, 1, 32, 32) \
+  X(2048, 0, 128, 2, 16, 2, 16, 16, 8) \
+  X(2048, 1, 256, 2, 16, 2, 8, 8, 8, 4) \
+  X(4096, 0, 256, 2, 16, 2, 16, 16, 16) \
+  X(4096, 1, 512, 2, 16, 2, 8, 8, 8, 8)
 
 template <int N, int V>
 struct RowPlanSel;
@@ -59,8 +65,8 @@ struct ColPlanSel;
 
 #define SSFM_DEF_ROW(NN, VV, TT, LL, ...) \
   template <> struct RowPlanSel<NN, VV> { using P = Plan<NN, TT, LL, Radices<__VA_ARGS__>>; };
-#define SSFM_DEF_COL(NN, VV, TT, LL, ...) \
-  template <> struct ColPlanSel<NN, VV> { using P = Plan<NN, TT, LL, Radices<__VA_ARGS__>>; };
+#define SSFM_DEF_COL(NN, VV, TT, LL, AA, BB, ...) \
+  template <> struct ColPlanSel<NN, VV> { using P = Plan<NN, TT, LL, Radices<__VA_ARGS__>, AA, BB>; };
 SSFM_ROW_PLANS(SSFM_DEF_ROW)
 SSFM_COL_PLANS(SSFM_DEF_COL)
 #undef SSFM_DEF_ROW

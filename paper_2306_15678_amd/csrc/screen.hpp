@@ -40,8 +40,18 @@ struct ScreenConst {
   unsigned terms;
 };
 
+// x^m for the multiphoton exponents; K = 8 (m = 7, 6) is the air model and
+// takes a short multiply chain (uniform branch), other orders the loop.
 template <typename R>
 __device__ __forceinline__ R ipow(R x, int m) {
+  if (m == 7) {
+    const R x2 = x * x, x4 = x2 * x2;
+    return x4 * x2 * x;
+  }
+  if (m == 6) {
+    const R x2 = x * x;
+    return x2 * x2 * x2;
+  }
   R r = R(1);
   for (int i = 0; i < m; ++i) r *= x;
   return r;

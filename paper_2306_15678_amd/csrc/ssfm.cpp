@@ -135,6 +135,11 @@ struct ssfm_ctx {
   // second stream (default priority) and events for the overlapped backward
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // per-chain streams and events for running the grid-size groups of one
+  // pass concurrently ([0]: main chain, [1]: auxiliary chain)
+  std::vector<hipStream_t> gstream[2];
+  std::vector<hipEvent_t> gjoin[2];
+  hipEvent_t gfork[2] = {nullptr, nullptr};
 
   template <typename T>
   T* at(size_t off) const {
@@ -148,6 +153,11 @@ struct ssfm_ctx {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (aux) (void)hipStreamDestroy(aux);
+    for (int k = 0; k < 2; ++k) {
+      for (auto s : gstream[k]) (void)hipStreamDestroy(s);
+      for (auto e : gjoin[k]) (void)hipEventDestroy(e);
+      if (gfork[k]) (void)hipEventDestroy(gfork[k]);
+    }
   }
 };
 
@@ -406,15 +416,34 @@ PassArgs<R> base_args(ssfm_ctx* c) {
   return a;
 }
 
+// One pass over every beam: one launch per grid-size group.  With several
+// groups the launches run concurrently (group g > 0 on its own stream,
+// forked from and joined back to st), so their ramps and tails overlap.
 template <typename R>
 int run_pass(ssfm_ctx* c, int kind, PassArgs<R> a, hipStream_t st = nullptr) {
   const bool col = kind >= COL_FWD;
   if (!st) st = c->stream;
-  for (auto& g : c->groups) {
+  const int chain = (st == c->aux) ? 1 : 0;
+  const size_t ng = c->groups.size();
+  const bool fork = ng > 1 && c->gstream[chain].size() + 1 >= ng;
+  if (fork) {
+    HIP_TRY(hipEventRecord(c->gfork[chain], st));
+    for (size_t g = 1; g < ng; ++g)
+      HIP_TRY(hipStreamWaitEvent(c->gstream[chain][g - 1], c->gfork[chain], 0));
+  }
+  for (size_t gi = 0; gi < ng; ++gi) {
+    const Group& g = c->groups[gi];
     a.work = c->at<WorkItem>(c->L.work) + (col ? g.col_work_off : g.row_work_off);
     const int nb = col ? g.col_blocks : g.row_blocks;
     const int v = col ? g.col_var : g.row_var;
-    HIP_TRY(launch_pass<R>(kind, g.n, v, nb, a, st));
+    hipStream_t sg = (fork && gi > 0) ? c->gstream[chain][gi - 1] : st;
+    HIP_TRY(launch_pass<R>(kind, g.n, v, nb, a, sg));
+  }
+  if (fork) {
+    for (size_t g = 1; g < ng; ++g) {
+      HIP_TRY(hipEventRecord(c->gjoin[chain][g - 1], c->gstream[chain][g - 1]));
+      HIP_TRY(hipStreamWaitEvent(st, c->gjoin[chain][g - 1], 0));
+    }
   }
   return SSFM_OK;
 }
@@ -943,6 +972,17 @@ int ssfm_create(const ssfm_instance_desc* desc, int32_t n_inst, int32_t precisio
   HIP_TRY(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  for (int k = 0; k < 2; ++k) {
+    HIP_TRY(hipEventCreateWithFlags(&c->gfork[k], hipEventDisableTiming));
+    for (size_t g = 1; g < c->groups.size(); ++g) {
+      hipStream_t sg;
+      hipEvent_t ej;
+      HIP_TRY(hipStreamCreateWithFlags(&sg, hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&ej, hipEventDisableTiming));
+      c->gstream[k].push_back(sg);
+      c->gjoin[k].push_back(ej);
+    }
+  }
   int r = SSFM_DISPATCH(c, upload_plan, c.get());
   if (r) return r;
   *out = c.release();

@@ -97,12 +97,26 @@ def floors(inst, n_steps, every, screens=None):
                     wmax[k] = max(wmax[k], M.rel_l2(np.abs(u) ** 2, np.abs(ref[marks[k]]) ** 2))
                     k += 1
         out[name] = {"field": fmax.tolist(), "fluence": wmax.tolist()}
-    if not screens and not (inst.medium.terms & W.TERM_ANSATZ):
-        peer = peer32(inst, marks)
-        out["peer32"] = {
-            "field": [M.rel_l2(peer[m], ref[m]) for m in marks],
-            "fluence": [M.rel_l2(np.abs(peer[m]) ** 2, np.abs(ref[m]) ** 2) for m in marks]}
+    out["peer32"] = peer_floors(inst, marks, screens, ref, power, peak)
     return out
+
+
+def peer_floors(inst, marks, screens, ref, power, peak):
+    """Field, fluence, block-fluence and diagnostic floors of the complex64
+    peer against the oracle reference."""
+    peer = peer32(inst, marks, screens)
+    pp = np.array(peer["diag"]["power"])
+    pk = np.array(peer["diag"]["peak"])
+    b = max(1, inst.n // 32)
+    return {
+        "field": [M.rel_l2(peer[m], ref[m]) for m in marks],
+        "fluence": [M.rel_l2(np.abs(peer[m]) ** 2, np.abs(ref[m]) ** 2) for m in marks],
+        "block_fluence": [M.rel_l2(M.block_mean(np.abs(peer[m]) ** 2, b),
+                                   M.block_mean(np.abs(ref[m]) ** 2, b)) for m in marks],
+        # largest relative difference of power / peak over steps 1..m
+        "power": [float(np.max(np.abs(pp[:m] / np.array(power[:m]) - 1))) for m in marks],
+        "peak": [float(np.max(np.abs(pk[:m] / np.array(peak[:m]) - 1))) for m in marks],
+    }
 
 
 def _quarters(marks):
@@ -116,10 +130,11 @@ def _quarters(marks):
     return out
 
 
-def peer32(inst, marks):
+def peer32(inst, marks, screens=None):
     """complex64 march of the same map (torch CPU), normalised units."""
     import torch
     m = inst.medium
+    th = [float(v) for v in (inst.theta or (0.0,) * 8)]
     n = inst.n
     k0 = 2.0 * math.pi / m.wavelength
     k = 2.0 * math.pi * np.fft.fftfreq(n, d=inst.length / n)
@@ -130,6 +145,8 @@ def peer32(inst, marks):
     cM = torch.tensor((K - 1) * m.beta_k * m.i_ref ** (K - 1) * inst.dz, dtype=torch.float32)
     u = torch.from_numpy((W.initial_field(inst) / math.sqrt(m.i_ref)).astype(np.complex64))
     out = {}
+    diag = {"power": [], "peak": []}
+    dx2 = (inst.length / n) ** 2
     for step in range(1, marks[-1] + 1):
         v = torch.fft.ifft2(P * torch.fft.fft2(u))
         x = (v.real ** 2 + v.imag ** 2)
@@ -141,9 +158,81 @@ def peer32(inst, marks):
             ph = ph - cK * x ** K / (1 + x ** (K - 1))
         if m.terms & W.TERM_MPA:
             la = la - torch.log(1 + cM * x ** (K - 1)) / (2 * (K - 1))
+        if m.terms & W.TERM_ANSATZ:
+            den = 1 + x ** 4
+            ph = ph + cK * sum(th[q - 1] * x ** q for q in range(1, 5)) / den
+            la = la - cK * sum(th[3 + q] * x ** q for q in range(1, 5)) / den
+        if screens and (step - 1) in screens:
+            ph = ph + torch.from_numpy(screens[step - 1].astype(np.float32))
         u = v * torch.exp(la) * torch.polar(torch.ones_like(ph), ph)
+        inten = (u.real.double() ** 2 + u.imag.double() ** 2) * m.i_ref
+        diag["power"].append(float(inten.sum()) * dx2)
+        diag["peak"].append(float(inten.max()))
         if step in marks:
             out[step] = u.numpy().astype(np.complex128) * math.sqrt(m.i_ref)
+    out["diag"] = diag
+    return out
+
+
+def peer32_loss(inst, steps, target):
+    """complex64 peer of march + fluence loss (torch CPU) with its gradient
+    by reverse autodiff: (loss, dL/dU0 [SI], dL/dtheta)."""
+    import torch
+    m = inst.medium
+    n = inst.n
+    k0 = 2.0 * math.pi / m.wavelength
+    k = 2.0 * math.pi * np.fft.fftfreq(n, d=inst.length / n)
+    prop = np.exp(-1j * (k[None, :] ** 2 + k[:, None] ** 2) * inst.dz / (2 * k0))
+    P = torch.from_numpy(prop.astype(np.complex64))
+    cK = float(k0 * m.n2 * m.i_ref * inst.dz)
+    K = m.mpa_order
+    cM = float((K - 1) * m.beta_k * m.i_ref ** (K - 1) * inst.dz)
+    sa = math.sqrt(m.i_ref)
+    u0 = torch.from_numpy((W.initial_field(inst) / sa).astype(np.complex64)).requires_grad_(True)
+    th = torch.tensor([float(v) for v in (inst.theta or (0.0,) * 8)], dtype=torch.float32,
+                      requires_grad=True)
+    u = u0
+    for _ in range(steps):
+        v = torch.fft.ifft2(P * torch.fft.fft2(u))
+        x = v.real ** 2 + v.imag ** 2
+        ph = torch.zeros_like(x)
+        la = torch.zeros_like(x)
+        if m.terms & W.TERM_KERR:
+            ph = ph + cK * x
+        if m.terms & W.TERM_PLASMA:
+            ph = ph - cK * x ** K / (1 + x ** (K - 1))
+        if m.terms & W.TERM_MPA:
+            la = la - torch.log(1 + cM * x ** (K - 1)) / (2 * (K - 1))
+        if m.terms & W.TERM_ANSATZ:
+            den = 1 + x ** 4
+            ph = ph + cK * sum(th[q - 1] * x ** q for q in range(1, 5)) / den
+            la = la - cK * sum(th[3 + q] * x ** q for q in range(1, 5)) / den
+        u = v * torch.exp(la) * torch.polar(torch.ones_like(ph), ph)
+    tg = torch.from_numpy((target / m.i_ref).astype(np.float32))
+    inten = u.real ** 2 + u.imag ** 2
+    loss = ((inten - tg) ** 2).sum() / (tg ** 2).sum()
+    loss.backward()
+    return (float(loss), u0.grad.numpy().astype(np.complex128) / sa,
+            th.grad.numpy().astype(np.float64))
+
+
+def gradient_floors(inst, marks, target):
+    """Floors of (loss, dL/dU0, dL/dtheta) against the FP64 oracle: the
+    oracle itself from an input perturbed by 2^-53 and the complex64 peer."""
+    u0 = W.initial_field(inst)
+    rng = np.random.default_rng(54321)
+    pert = u0 * (1 + 2.0 ** -53 * _eta(rng, u0.shape))
+    out = {"steps": marks, "in64": [], "peer32": []}
+
+    def cot(u):
+        return M.fluence_loss(u, target)
+    for m in marks:
+        l0, g0, t0 = M.gradient(u0, inst, n_steps=m, cotangent=cot)
+        l1, g1, t1 = M.gradient(pert, inst, n_steps=m, cotangent=cot)
+        l2, g2, t2 = peer32_loss(inst, m, target)
+        tn = np.max(np.abs(t0))
+        out["in64"].append([abs(l1 / l0 - 1), M.rel_l2(g1, g0), float(np.max(np.abs(t1 - t0)) / tn)])
+        out["peer32"].append([abs(l2 / l0 - 1), M.rel_l2(g2, g0), float(np.max(np.abs(t2 - t0)) / tn)])
     return out
 
 
@@ -155,16 +244,53 @@ def _shift(screens, offset):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["c1", "c2"])
+    ap.add_argument("config", help="c1, c2, c3:<beam> or c4")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--every", type=int, default=20)
+    ap.add_argument("--peer-only", action="store_true",
+                    help="recompute only the complex64-peer floors into the existing file")
+    ap.add_argument("--floors-only", action="store_true",
+                    help="omit the reference samples (the test runs the oracle itself)")
     args = ap.parse_args()
-    inst = {"c1": W.config1, "c2": W.config2}[args.config]()[0]
+    screens = None
+    if args.config.startswith("c3:"):
+        from oracle import turbulence as T
+        inst = W.config3()[int(args.config[3:])]
+        screens = T.instance_screens(inst)
+    else:
+        inst = {"c1": W.config1, "c2": W.config2, "c4": W.config4,
+                "c5": W.config5}[args.config]()[0]
     n_steps = args.steps or inst.n_steps
-    res = floors(inst, n_steps, args.every)
+    path = os.path.join(HERE, "floor_%s.json" % args.config.replace(":", "_"))
+    if args.peer_only:
+        res = json.load(open(path))
+        marks = res["steps"]
+        u = W.initial_field(inst)
+        ref, power, peak, done = {}, [], [], 0
+        for m in marks:
+            r = M.march(u, inst, n_steps=m - done, screens=_shift(screens, done))
+            u = r.field
+            power += r.power.tolist()
+            peak += r.peak.tolist()
+            done = m
+            ref[m] = u
+        res["peer32"] = peer_floors(inst, marks, screens, ref, power, peak)
+        with open(path, "w") as f:
+            json.dump(res, f, indent=1)
+        for k, v in res["peer32"].items():
+            print("peer32", k, ["%.1e" % x for x in v])
+        return
+    res = floors(inst, n_steps, args.every, screens)
+    if args.config == "c4":
+        res["gradient"] = gradient_floors(inst, [100, res["steps"][-1]],
+                                          W.synthetic_target(inst, 44))
+        for k in ("in64", "peer32"):
+            print("gradient", k, [["%.1e" % v for v in row] for row in res["gradient"][k]])
+    if args.floors_only:
+        res.pop("reference")
+        res.pop("sample_points")
     res["config"] = args.config
     res["n"] = inst.n
-    path = os.path.join(HERE, f"floor_{args.config}.json")
     with open(path, "w") as f:
         json.dump(res, f, indent=1)
     for k in ("in64", "in32", "step64", "step32", "peer32"):

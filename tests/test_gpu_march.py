@@ -315,3 +315,323 @@ def test_every_tile_variant_matches_oracle(n):
         err = M.rel_l2(p.field(0), ref.field)
         _report(f"variant n={n} row={r} col={c}", field=err)
         assert err < 1e-11, (r, c)
+
+
+# ---------------------------------------------------------- config 3
+# 64 uneven beams (n in {256, 512, 768, 1024}) with 20 Kolmogorov screens
+# each, marched together in one context.  Checked on one beam of each size
+# (indices 0, 1, 5, 10) over the first 100 steps (one screen, after step 49).
+# Floors at step 100 (tests/golden/floor_c3_<beam>.json, oracle-only script):
+#   beam  n     FP32 floor (max of peer / per-step)   FP64 per-step floor
+#   0     1024  2.8e-5                                9.9e-15
+#   1     768   4.8e-5                                2.7e-14
+#   5     512   3.1e-5                                1.7e-14
+#   10    256   5.7e-3 (185 P_cr: unstable by step 100) 7.7e-12
+# Tolerance: FP32 5x, FP64 10x the floor.
+C3_BEAMS = {0: (1.4e-4, 1e-13), 1: (2.4e-4, 2.7e-13), 5: (1.6e-4, 1.7e-13),
+            10: (2.9e-2, 7.7e-11)}
+
+
+@pytest.fixture(scope="module")
+def c3_oracle():
+    insts = W.config3()
+    out = {}
+    for b in C3_BEAMS:
+        scr = T.instance_screens(insts[b])
+        out[b] = (M.march(W.initial_field(insts[b]), insts[b], n_steps=100, screens=scr).field,
+                  scr)
+    return insts, out
+
+
+def test_config3_screens_match_oracle(c3_oracle):
+    insts, ref = c3_oracle
+    p = _prop(insts, 32)
+    p.gen_screens()
+    for b in C3_BEAMS:
+        steps = insts[b].screen_steps()
+        for s in range(insts[b].n_screens):
+            want = ref[b][1][steps[s]]
+            got = p.screen(b, s)
+            err = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+            assert err < 2e-6, (b, s, err)
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_config3_batched_march_matches_oracle(c3_oracle, precision):
+    insts, ref = c3_oracle
+    p = _prop(insts, precision)
+    p.gen_screens()
+    for b, inst in enumerate(insts):
+        p.set_field(b, W.initial_field(inst))
+    p.propagate(100)
+    for b, tol in C3_BEAMS.items():
+        err = M.rel_l2(p.field(b), ref[b][0])
+        _report(f"c3 beam {b} n={insts[b].n} fp{precision}", field=err)
+        assert err < (tol[0] if precision == 32 else tol[1]), (b, err)
+
+
+def test_config3_batch_equals_each_beam_alone():
+    insts = W.config3()
+    p = _prop(insts, 32)
+    p.gen_screens()
+    for b, inst in enumerate(insts):
+        p.set_field(b, W.initial_field(inst))
+    p.propagate(100)
+    for b in C3_BEAMS:
+        q = _prop([insts[b]], 32)
+        q.gen_screens()
+        q.set_field(0, W.initial_field(insts[b]))
+        q.propagate(100)
+        assert np.array_equal(p.field(b), q.field(0)), b
+
+
+# ---------------------------------------------------------- config 4
+# Sparse 256^2 beam with the ansatz screen, 500 steps over 3 m, loss =
+# fluence mismatch, adjoint with a checkpoint every 50 steps.  Parity of the
+# gradient uses a target that comes from the input module (a dense-grid
+# reference computed by the library must not feed the oracle).
+def _c4():
+    inst = W.config4_sparse()
+    return inst, W.initial_field(inst), W.synthetic_target(inst, 44)
+
+
+@pytest.fixture(scope="module")
+def c4_oracle():
+    inst, u0, target = _c4()
+    return {m: M.gradient(u0, inst, n_steps=m, cotangent=lambda u: M.fluence_loss(u, target))
+            for m in (100, 500)}
+
+
+# Gradient floors (tests/golden/floor_c4.json, "gradient": loss, dL/dU0,
+# dL/dtheta against the FP64 oracle gradient):
+#             FP64 (input 2^-53)             FP32 peer (complex64, autodiff)
+#   100 steps 7.1e-15 5.0e-14 6.4e-14         1.3e-4 1.1e-3 1.4e-3
+#   500 steps 8.5e-12 1.1e-6  4.1e-10         1.6    4.6e2  3.5e1
+# The sparse beam collapses chaotically (the ansatz at theta0 only mimics
+# plasma arrest for x <= 1); FP32 gradients decorrelate after ~200 steps,
+# so FP32 parity is stated at 100 steps and only reported at 500.  FP64
+# tolerance: 10x the floor at 100 steps, 100x at 500 (the input floor omits
+# per-step rounding, which over 500 chaotic steps adds one to two decades).
+C4_TOL = {(64, 100): (7.1e-14, 5.0e-13, 6.4e-13), (64, 500): (8.5e-10, 1.1e-4, 4.1e-8),
+          (32, 100): (6.5e-4, 5.5e-3, 7.0e-3)}
+
+
+@pytest.mark.parametrize("precision,steps", [(64, 100), (64, 500), (32, 100), (32, 500)])
+def test_config4_gradient_matches_oracle(c4_oracle, precision, steps):
+    inst, u0, target = _c4()
+    loss, g_u0, g_th = c4_oracle[steps]
+    p = _prop([inst], precision, max_steps=steps, ckpt_every=50)
+    p.set_field(0, u0)
+    p.set_theta(0, inst.theta)
+    p.forward_record(steps)
+    gl = p.fluence_loss(0, target)
+    p.backward()
+    gu, gt = p.grad_field(0), p.grad_theta(0)
+    lerr = abs(gl / loss - 1)
+    ferr = M.rel_l2(gu, g_u0)
+    terr = float(np.max(np.abs(gt - g_th)) / np.max(np.abs(g_th)))
+    _report(f"c4 grad fp{precision} steps={steps}", loss=lerr, g_u0=ferr, g_theta=terr)
+    assert np.isfinite(gl) and np.all(np.isfinite(gt)) and np.all(np.isfinite(gu))
+    tol = C4_TOL.get((precision, steps))
+    if tol is not None:
+        assert lerr < tol[0] and ferr < tol[1] and terr < tol[2]
+
+
+def test_config4_gradient_matches_finite_differences():
+    """Central differences of the library's own FP64 loss in theta and in
+    random complex directions of U0 (h = 1e-6 relative)."""
+    inst, u0, target = _c4()
+    p = _prop([inst], 64, max_steps=inst.n_steps, ckpt_every=50)
+
+    def loss(u, th):
+        p.set_field(0, u)
+        p.set_theta(0, th)
+        p.forward_record(inst.n_steps)
+        return p.fluence_loss(0, target)
+
+    th0 = np.array(inst.theta)
+    loss(u0, th0)
+    p.backward()
+    g_th, g_u0 = p.grad_theta(0), p.grad_field(0)
+    for q in (0, 3, 5, 7):
+        h = 1e-6 * max(1.0, abs(th0[q]))
+        e = np.zeros(8)
+        e[q] = h
+        fd = (loss(u0, th0 + e) - loss(u0, th0 - e)) / (2 * h)
+        _report(f"c4 fd theta{q}", fd=fd, adj=float(g_th[q]))
+        assert abs(fd - g_th[q]) <= 1e-5 * max(abs(fd), 1e-3 * np.max(np.abs(g_th)))
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        d = rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape)
+        h = 1e-6 * np.abs(u0).max() / np.abs(d).max()
+        fd = (loss(u0 + h * d, th0) - loss(u0 - h * d, th0)) / (2 * h)
+        an = float(np.real(np.vdot(g_u0, d)))
+        assert abs(fd - an) <= 1e-5 * abs(fd)
+
+
+def test_config4_dense_reference_workflow():
+    """The full workflow: 2048^2 dense march (6000 steps, Kerr + MPA +
+    plasma) on the GPU, 8x8 block mean onto the sparse grid, sparse loss and
+    gradient.  Checked by properties: block mean against numpy on the same
+    fluence, finite loss and gradients, and a descent step that lowers the
+    loss."""
+    import torch
+    dense = W.config4_dense()
+    pd = _prop([dense], 32)
+    pd.set_field(0, W.initial_field(dense))
+    pd.propagate(dense.n_steps)
+    pw, pk = pd.diag(0, dense.n_steps)
+    assert np.all(np.isfinite(pw)) and np.all(np.diff(pw) <= 1e-6 * pw[0])
+    fl = pd.intensity(0, device=True)
+    tgt = pd.block_mean(fl, 8)
+    want = M.block_mean(fl.cpu().numpy(), 8)
+    assert np.max(np.abs(tgt.cpu().numpy() - want)) <= 1e-12 * np.max(want)
+    inst, u0, _ = _c4()
+    p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=50)
+    th0 = np.array(inst.theta)
+
+    def run(th):
+        p.set_field(0, u0)
+        p.set_theta(0, th)
+        p.forward_record(inst.n_steps)
+        return p.fluence_loss(0, tgt)
+
+    l0 = run(th0)
+    p.backward()
+    g = p.grad_theta(0)
+    assert np.isfinite(l0) and np.all(np.isfinite(g))
+    l1 = run(th0 - 1e-3 * g / np.max(np.abs(g)))
+    _report("c4 workflow", loss0=l0, loss1=l1, peak_dense=float(pk.max()))
+    assert l1 < l0
+
+
+# ---------------------------------------------------------- config 2
+# The bench workload at full size: 1024^2, 2000 steps, the tuned tile
+# variants.  Compared with the oracle's own samples of the same march
+# (tests/golden/floor_c2.json, written by calibrate_floor.py c2 from the
+# oracle alone): the field at 64 seeded points every 100 steps, power and
+# peak intensity after every step, and 32x32-block fluence at 500, 1000,
+# 1500 and 2000 steps.  Floors in the same file; the FP32 floor passes 1e-3
+# after step 1100, where the multifilament march turns chaotic, so FP32 field
+# parity is stated up to step 1100 and global diagnostics to the end.
+def _c2_ref():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "floor_c2.json")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_config2_full_size_against_oracle_samples(precision):
+    from paper_2306_15678_amd.tune import tune
+    d = _c2_ref()
+    ref = d["reference"]
+    pts = np.array(d["sample_points"])
+    inst = W.config2()[0]
+    p = _prop([inst], precision)
+    tune(p, reps=5, use_cache=False)
+    p.set_field(0, W.initial_field(inst))
+    power, peak = [], []
+    for k, m in enumerate(d["steps"]):
+        p.propagate(100)
+        pw, pk = p.diag(0, 100)
+        power += list(pw)
+        peak += list(pk)
+        u = p.field(0)
+        want = np.array(ref["field_re"][str(m)]) + 1j * np.array(ref["field_im"][str(m)])
+        got = u[pts[:, 0], pts[:, 1]]
+        err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+        if str(m) in ref["block_fluence"]:
+            bf = np.array(ref["block_fluence"][str(m)])
+            gb = M.block_mean(np.abs(u) ** 2, inst.n // bf.shape[0])
+            berr = float(np.linalg.norm(gb - bf) / np.linalg.norm(bf))
+            _report(f"c2 fp{precision} step {m}", samples=err, block_fluence=berr)
+        if precision == 64:
+            floor = max(d["step64"]["field"][k], d["in64"]["field"][k], 1e-13)
+            assert err < 10 * floor, (m, err, floor)
+        elif m <= 1100:
+            floor = max(d["peer32"]["field"][k], d["step32"]["field"][k])
+            assert err < 5 * floor, (m, err, floor)
+    perr = np.abs(np.array(power) / np.array(ref["power"]) - 1)
+    kerr = np.abs(np.array(peak) / np.array(ref["peak"]) - 1)
+    _report(f"c2 fp{precision} diag", power_max=float(perr.max()), power_end=float(perr[-1]),
+            peak_1100=float(kerr[:1100].max()), peak_end=float(kerr[-1]))
+    if precision == 64:
+        assert perr.max() < 1e-10 and kerr.max() < 1e-8
+    else:
+        assert perr[:1100].max() < 1e-5 and kerr[:1100].max() < 1e-3
+        assert perr.max() < 1e-2
+
+
+# ---------------------------------------------------------- config 5
+# 4096^2, 2.5 cm beam at 1000 P_cr, all screen terms and 50 Kolmogorov
+# screens over 1 km (5000 steps).  The FP64 oracle needs seconds per step at
+# this size, so parity is checked on the first 10 steps at full size (and on
+# the first screen pair); the full forward + adjoint march is checked by
+# properties that hold at any length.
+@pytest.fixture(scope="module")
+def c5_oracle():
+    inst = W.config5()[0]
+    u0 = W.initial_field(inst)
+    return inst, u0, M.march(u0, inst, n_steps=10).field
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_config5_prefix_matches_oracle(c5_oracle, precision):
+    inst, u0, ref = c5_oracle
+    p = _prop([inst], precision)
+    p.set_field(0, u0)
+    p.propagate(10)
+    err = M.rel_l2(p.field(0), ref)
+    _report(f"c5 10 steps fp{precision}", field=err)
+    assert err < C5_TOL[precision]
+
+
+def test_config5_first_screens_match_oracle():
+    inst = W.config5()[0]
+    k0 = 2 * math.pi / inst.medium.wavelength
+    amp = T.kolmogorov_amplitude(inst.n, inst.length,
+                                 T.fried_parameter(k0, inst.cn2, inst.screen_dz))
+    re, im = T.screen_pair(inst.n, inst.length, amp, inst.seed, 0)
+    p = _prop([inst], 32)
+    p.gen_screens()
+    for s, want in ((0, re), (1, im)):
+        got = p.screen(0, s)
+        err = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+        _report(f"c5 screen {s}", maxrel=err)
+        assert err < 2e-6
+
+
+def test_config5_full_forward_adjoint_properties():
+    """5000 steps, checkpoint every 71 steps (about sqrt(5000): 71 + 2 x 70
+    fields), twin-experiment loss against the fluence of a run with a seeded
+    theta_ref; finite loss and gradients, non-increasing power, and a small
+    step against the theta gradient lowers the loss."""
+    inst = W.config5()[0]
+    u0 = W.initial_field(inst)
+    p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=71)
+    p.gen_screens()
+    theta_ref = 0.05 * W.random_theta(55, 1.0)
+    p.set_field(0, u0)
+    p.set_theta(0, theta_ref)
+    p.propagate(inst.n_steps)
+    target = p.intensity(0, device=True)
+    th0 = np.zeros(8)
+
+    def run(th):
+        p.set_field(0, u0)
+        p.set_theta(0, th)
+        p.forward_record(inst.n_steps)
+        return p.fluence_loss(0, target)
+
+    l0 = run(th0)
+    pw, _ = p.diag(0, inst.n_steps)
+    p.backward()
+    g = p.grad_theta(0)
+    gu = p.grad_field(0, device=True)
+    assert np.isfinite(l0) and l0 > 0 and np.all(np.isfinite(g))
+    assert bool(gu.isfinite().all())
+    assert np.all(np.diff(pw) <= 1e-6 * pw[0])
+    l1 = run(th0 - 1e-4 * g / np.max(np.abs(g)))
+    _report("c5 fwd+adj", loss0=l0, loss1=l1, power_end=float(pw[-1] / pw[0]))
+    assert l1 < l0
