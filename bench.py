@@ -140,6 +140,27 @@ def run_batched(args):
             "bytes_pass": b_row}
 
 
+def traffic_per_launch(kind, variant):
+    """HBM bytes per launch of the forward ``kind`` pass ("row" or "col") of
+    tile ``variant`` on the 1024^2 grid, from the committed FETCH_SIZE and
+    WRITE_SIZE summary, each counter scaled by its own reading for a plain
+    copy kernel of known size.  None when the summary is absent or was taken
+    on other kernel sources."""
+    from paper_2306_15678_amd.passprof import kernel_source_hash
+    path = os.path.join(ROOT, "profiles", "traffic_c2_1024.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    c = d["copy_kernel"]
+    for e in d.get(kind, []):
+        if e["variant"] == variant:
+            return 1024.0 * (e["fetch_kib"] / c["fetch_scale"] + e["write_kib"] / c["write_scale"])
+    return None
+
+
 def parity_vs_stored(inst, power, peak, fluence, field):
     """Compare with the oracle's samples of this workload (written by
     tests/golden/calibrate_floor.py c2); None if the fixture is absent."""
@@ -212,6 +233,7 @@ def main():
     dom = "col" if ps["ms_col"] >= ps["ms_row"] else "row"
     ms = ps["ms_" + dom]
     achieved = ps["bytes_" + dom] / (ms * 1e-3) / 1e9
+    traffic = traffic_per_launch(dom, g["tune_fp32"][dom])
     line = {
         "metric": METRIC,
         "value": g[32]["value"],
@@ -239,7 +261,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_over_algorithmic": (traffic / ps["bytes_" + dom]) if traffic else None,
             "ms_per_launch": ms,
             "bytes_per_launch": ps["bytes_" + dom],
         },

@@ -54,7 +54,7 @@ typedef enum {
   SSFM_EUNSUPPORTED = -2, /* grid size or option not built into the library */
   SSFM_EHIP = -3,         /* HIP runtime error (detail in ssfm_last_error) */
   SSFM_ESTATE = -4,       /* call out of order (e.g. backward before forward) */
-  SSFM_ENONFINITE = -5,   /* non-finite power detected in the diagnostics  */
+  SSFM_ENONFINITE = -5,   /* non-finite power or theta gradient detected   */
   SSFM_EWORKSPACE = -6    /* workspace missing, misaligned or too small    */
 } ssfm_status;
 
@@ -185,7 +185,11 @@ int ssfm_backward(ssfm_ctx* ctx);
  * convention as the cotangent), to host or device. */
 int ssfm_get_grad_field(ssfm_ctx* ctx, int32_t inst, void* dst, int32_t where);
 
-/* Gradient of L w.r.t. theta of instance inst (FP64, host double[8]). */
+/* Gradient of L w.r.t. theta of instance inst (FP64, host double[8]).
+ * Returns SSFM_ENONFINITE (g still written) if a component is not finite:
+ * the linearised march can grow exponentially (e.g. an ansatz whose
+ * imaginary coefficients make a gain that rises with intensity, Eq. (6)),
+ * and a complex64 adjoint then overflows. */
 int ssfm_get_grad_theta(ssfm_ctx* ctx, int32_t inst, double* g);
 
 /* Block mean of a float64 n*n device array into (n/b)*(n/b) (device to

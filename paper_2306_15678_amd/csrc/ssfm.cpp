@@ -923,7 +923,7 @@ const char* ssfm_strerror(int s) {
     case SSFM_EUNSUPPORTED: return "unsupported grid size or option";
     case SSFM_EHIP: return "HIP runtime error";
     case SSFM_ESTATE: return "call out of order";
-    case SSFM_ENONFINITE: return "non-finite power in diagnostics";
+    case SSFM_ENONFINITE: return "non-finite power or gradient";
     case SSFM_EWORKSPACE: return "workspace missing, misaligned or too small";
     default: return "unknown status";
   }
@@ -1156,6 +1156,11 @@ int ssfm_get_grad_theta(ssfm_ctx* c, int32_t inst, double* g) {
     for (int r = 0; r < n; ++r) seed_part[p] += sp[size_t(r) * 8 + p];
     g[p] = acc[p] + seed_part[p];
   }
+  for (int p = 0; p < 8; ++p)
+    if (!std::isfinite(g[p]))
+      return fail(SSFM_ENONFINITE,
+                  "theta gradient of instance %d is not finite: the linearised march "
+                  "outgrew the precision's range", inst);
   return SSFM_OK;
 }
 

@@ -17,6 +17,8 @@ therefore stated relative to a floor measured on the oracle itself:
   intensity x = I/I_a, FP32 tables, FFTs and screen).  FP32 rounding of
   tables, twiddles and coefficients acts coherently from step to step, which
   the random models above do not capture; this peer measures it directly.
+* ``peer64``: the same independent implementation in complex128 (torch
+  CPU), for the coherent FP64 table rounding.
 
 Writes tests/golden/floor_<name>.json with the field and fluence floors at
 the listed step counts, and the oracle's own samples of the reference run at
@@ -101,10 +103,10 @@ def floors(inst, n_steps, every, screens=None):
     return out
 
 
-def peer_floors(inst, marks, screens, ref, power, peak):
+def peer_floors(inst, marks, screens, ref, power, peak, bits=32):
     """Field, fluence, block-fluence and diagnostic floors of the complex64
-    peer against the oracle reference."""
-    peer = peer32(inst, marks, screens)
+    (bits=32) or complex128 (bits=64) peer against the oracle reference."""
+    peer = peer32(inst, marks, screens, bits)
     pp = np.array(peer["diag"]["power"])
     pk = np.array(peer["diag"]["peak"])
     b = max(1, inst.n // 32)
@@ -130,20 +132,23 @@ def _quarters(marks):
     return out
 
 
-def peer32(inst, marks, screens=None):
-    """complex64 march of the same map (torch CPU), normalised units."""
+def peer32(inst, marks, screens=None, bits=32):
+    """complex64 (bits=64: complex128) march of the same map (torch CPU),
+    normalised units."""
     import torch
+    cdt, rdt = (np.complex64, np.float32) if bits == 32 else (np.complex128, np.float64)
+    tdt = torch.float32 if bits == 32 else torch.float64
     m = inst.medium
     th = [float(v) for v in (inst.theta or (0.0,) * 8)]
     n = inst.n
     k0 = 2.0 * math.pi / m.wavelength
     k = 2.0 * math.pi * np.fft.fftfreq(n, d=inst.length / n)
     prop = np.exp(-1j * (k[None, :] ** 2 + k[:, None] ** 2) * inst.dz / (2 * k0))
-    P = torch.from_numpy(prop.astype(np.complex64))
-    cK = torch.tensor(k0 * m.n2 * m.i_ref * inst.dz, dtype=torch.float32)
+    P = torch.from_numpy(prop.astype(cdt))
+    cK = torch.tensor(k0 * m.n2 * m.i_ref * inst.dz, dtype=tdt)
     K = m.mpa_order
-    cM = torch.tensor((K - 1) * m.beta_k * m.i_ref ** (K - 1) * inst.dz, dtype=torch.float32)
-    u = torch.from_numpy((W.initial_field(inst) / math.sqrt(m.i_ref)).astype(np.complex64))
+    cM = torch.tensor((K - 1) * m.beta_k * m.i_ref ** (K - 1) * inst.dz, dtype=tdt)
+    u = torch.from_numpy((W.initial_field(inst) / math.sqrt(m.i_ref)).astype(cdt))
     out = {}
     diag = {"power": [], "peak": []}
     dx2 = (inst.length / n) ** 2
@@ -163,7 +168,7 @@ def peer32(inst, marks, screens=None):
             ph = ph + cK * sum(th[q - 1] * x ** q for q in range(1, 5)) / den
             la = la - cK * sum(th[3 + q] * x ** q for q in range(1, 5)) / den
         if screens and (step - 1) in screens:
-            ph = ph + torch.from_numpy(screens[step - 1].astype(np.float32))
+            ph = ph + torch.from_numpy(screens[step - 1].astype(rdt))
         u = v * torch.exp(la) * torch.polar(torch.ones_like(ph), ph)
         inten = (u.real.double() ** 2 + u.imag.double() ** 2) * m.i_ref
         diag["power"].append(float(inten.sum()) * dx2)
@@ -249,6 +254,8 @@ def main():
     ap.add_argument("--every", type=int, default=20)
     ap.add_argument("--peer-only", action="store_true",
                     help="recompute only the complex64-peer floors into the existing file")
+    ap.add_argument("--peer-bits", type=int, default=32, choices=(32, 64),
+                    help="with --peer-only: the complex64 (32) or complex128 (64) peer")
     ap.add_argument("--floors-only", action="store_true",
                     help="omit the reference samples (the test runs the oracle itself)")
     args = ap.parse_args()
@@ -274,11 +281,12 @@ def main():
             peak += r.peak.tolist()
             done = m
             ref[m] = u
-        res["peer32"] = peer_floors(inst, marks, screens, ref, power, peak)
+        name = "peer%d" % args.peer_bits
+        res[name] = peer_floors(inst, marks, screens, ref, power, peak, args.peer_bits)
         with open(path, "w") as f:
             json.dump(res, f, indent=1)
-        for k, v in res["peer32"].items():
-            print("peer32", k, ["%.1e" % x for x in v])
+        for k, v in res[name].items():
+            print(name, k, ["%.1e" % x for x in v])
         return
     res = floors(inst, n_steps, args.every, screens)
     if args.config == "c4":

@@ -439,14 +439,19 @@ def test_config4_gradient_matches_oracle(c4_oracle, precision, steps):
 
 def test_config4_gradient_matches_finite_differences():
     """Central differences of the library's own FP64 loss in theta and in
-    random complex directions of U0 (h = 1e-6 relative)."""
+    random complex directions of U0 (h = 1e-6 relative), over the first 100
+    steps.  Past the collapse (about step 150) the loss of this march varies
+    on scales below h (the FP64 loss already differs from the oracle's by
+    2e-10 at step 500), so differences there measure curvature, not the
+    derivative; the adjoint at 500 steps is compared with the oracle's."""
     inst, u0, target = _c4()
-    p = _prop([inst], 64, max_steps=inst.n_steps, ckpt_every=50)
+    steps = 100
+    p = _prop([inst], 64, max_steps=steps, ckpt_every=50)
 
     def loss(u, th):
         p.set_field(0, u)
         p.set_theta(0, th)
-        p.forward_record(inst.n_steps)
+        p.forward_record(steps)
         return p.fluence_loss(0, target)
 
     th0 = np.array(inst.theta)
@@ -466,28 +471,47 @@ def test_config4_gradient_matches_finite_differences():
         h = 1e-6 * np.abs(u0).max() / np.abs(d).max()
         fd = (loss(u0 + h * d, th0) - loss(u0 - h * d, th0)) / (2 * h)
         an = float(np.real(np.vdot(g_u0, d)))
+        _report("c4 fd u0", fd=fd, adj=an)
         assert abs(fd - an) <= 1e-5 * abs(fd)
+
+
+def _descends(run, th0, g, l0, steps=(1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9)):
+    """Backtracking along -g: the first step size that lowers the loss, or
+    None.  Any differentiable loss with a nonzero gradient decreases for a
+    small enough step."""
+    d = g / np.max(np.abs(g))
+    for h in steps:
+        if run(th0 - h * d) < l0:
+            return h
+    return None
 
 
 def test_config4_dense_reference_workflow():
     """The full workflow: 2048^2 dense march (6000 steps, Kerr + MPA +
-    plasma) on the GPU, 8x8 block mean onto the sparse grid, sparse loss and
-    gradient.  Checked by properties: block mean against numpy on the same
-    fluence, finite loss and gradients, and a descent step that lowers the
-    loss."""
-    import torch
+    plasma, complex64) on the GPU, 8x8 block mean onto the sparse grid, then
+    the sparse model's loss and theta gradient against that target (FP64:
+    the 500-step sparse march is chaotic enough that complex64 gradients
+    are rounding noise, see the FP32 gradient floors above).  Checked by
+    properties: block mean against numpy on the same fluence, power never
+    increasing, finite loss and gradients, and -g a descent direction."""
     dense = W.config4_dense()
     pd = _prop([dense], 32)
     pd.set_field(0, W.initial_field(dense))
-    pd.propagate(dense.n_steps)
-    pw, pk = pd.diag(0, dense.n_steps)
+    pw = []
+    for _ in range(dense.n_steps // 2000):
+        pd.propagate(2000)
+        pw += list(pd.diag(0, 2000)[0])
+    pw = np.array(pw)
+    assert len(pw) == dense.n_steps
     assert np.all(np.isfinite(pw)) and np.all(np.diff(pw) <= 1e-6 * pw[0])
     fl = pd.intensity(0, device=True)
     tgt = pd.block_mean(fl, 8)
     want = M.block_mean(fl.cpu().numpy(), 8)
     assert np.max(np.abs(tgt.cpu().numpy() - want)) <= 1e-12 * np.max(want)
+    pd.close()
     inst, u0, _ = _c4()
-    p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=50)
+    p = _prop([inst], 64, max_steps=inst.n_steps, ckpt_every=50)
+    tgt = tgt.double()
     th0 = np.array(inst.theta)
 
     def run(th):
@@ -499,10 +523,10 @@ def test_config4_dense_reference_workflow():
     l0 = run(th0)
     p.backward()
     g = p.grad_theta(0)
-    assert np.isfinite(l0) and np.all(np.isfinite(g))
-    l1 = run(th0 - 1e-3 * g / np.max(np.abs(g)))
-    _report("c4 workflow", loss0=l0, loss1=l1, peak_dense=float(pk.max()))
-    assert l1 < l0
+    assert np.isfinite(l0) and np.all(np.isfinite(g)) and np.any(g != 0)
+    h = _descends(run, th0, g, l0)
+    _report("c4 workflow", loss0=l0, descent_step=h, power_end=float(pw[-1] / pw[0]))
+    assert h is not None
 
 
 # ---------------------------------------------------------- config 2
@@ -511,9 +535,14 @@ def test_config4_dense_reference_workflow():
 # (tests/golden/floor_c2.json, written by calibrate_floor.py c2 from the
 # oracle alone): the field at 64 seeded points every 100 steps, power and
 # peak intensity after every step, and 32x32-block fluence at 500, 1000,
-# 1500 and 2000 steps.  Floors in the same file; the FP32 floor passes 1e-3
-# after step 1100, where the multifilament march turns chaotic, so FP32 field
-# parity is stated up to step 1100 and global diagnostics to the end.
+# 1500 and 2000 steps.  Floors in the same file.  FP64: 10x the largest of
+# the per-step and input floors and the independent complex128 peer (whose
+# coherent table rounding dominates: 4e-13 at step 1000 against 3e-14 for
+# the random per-step model), at every sample to the end.  FP32: the floor
+# passes 1e-3 after step 1100, where the multifilament march turns chaotic,
+# so FP32 field parity is stated up to step 1100 (5x the larger of the
+# complex64 peer and the per-step floor) and the global diagnostics (block
+# fluence, power, peak) to the end at 5x the peer's.
 def _c2_ref():
     import json
     import os
@@ -546,8 +575,12 @@ def test_config2_full_size_against_oracle_samples(precision):
             gb = M.block_mean(np.abs(u) ** 2, inst.n // bf.shape[0])
             berr = float(np.linalg.norm(gb - bf) / np.linalg.norm(bf))
             _report(f"c2 fp{precision} step {m}", samples=err, block_fluence=berr)
+            if precision == 32:
+                assert berr < 5 * d["peer32"]["block_fluence"][k], (m, berr)
+            else:
+                assert berr < 10 * d["peer64"]["block_fluence"][k], (m, berr)
         if precision == 64:
-            floor = max(d["step64"]["field"][k], d["in64"]["field"][k], 1e-13)
+            floor = max(d["step64"]["field"][k], d["in64"]["field"][k], d["peer64"]["field"][k])
             assert err < 10 * floor, (m, err, floor)
         elif m <= 1100:
             floor = max(d["peer32"]["field"][k], d["step32"]["field"][k])
@@ -556,11 +589,12 @@ def test_config2_full_size_against_oracle_samples(precision):
     kerr = np.abs(np.array(peak) / np.array(ref["peak"]) - 1)
     _report(f"c2 fp{precision} diag", power_max=float(perr.max()), power_end=float(perr[-1]),
             peak_1100=float(kerr[:1100].max()), peak_end=float(kerr[-1]))
-    if precision == 64:
-        assert perr.max() < 1e-10 and kerr.max() < 1e-8
-    else:
-        assert perr[:1100].max() < 1e-5 and kerr[:1100].max() < 1e-3
-        assert perr.max() < 1e-2
+    # largest relative power / peak difference over steps 1..m, against the
+    # same for the independent peer of this precision (10x FP64, 5x FP32)
+    peer, f = ("peer64", 10) if precision == 64 else ("peer32", 5)
+    for k, m in enumerate(d["steps"]):
+        assert perr[:m].max() < f * d[peer]["power"][k], (m, perr[:m].max())
+        assert kerr[:m].max() < f * d[peer]["peak"][k], (m, kerr[:m].max())
 
 
 # ---------------------------------------------------------- config 5
@@ -569,6 +603,15 @@ def test_config2_full_size_against_oracle_samples(precision):
 # this size, so parity is checked on the first 10 steps at full size (and on
 # the first screen pair); the full forward + adjoint march is checked by
 # properties that hold at any length.
+# Floors at step 10 (tests/golden/floor_c5.json): FP32 peer 1.3e-6, per-step
+# FP32 1.4e-6 -> tolerance 5x = 7e-6.  FP64: the oracle evaluates the
+# diffraction factor exp(-i k^2 dz / 2k0) without reducing the phase, which
+# reaches 146 rad at the Nyquist mode of this grid, so its own error is up to
+# 146 x 2^-53 = 1.6e-14 per step (1.6e-13 over 10 steps; the library reduces
+# the phase modulo 2 pi in FP64 first) -> tolerance 10x that bound.
+C5_TOL = {64: 1.6e-12, 32: 7e-6}
+
+
 @pytest.fixture(scope="module")
 def c5_oracle():
     inst = W.config5()[0]
@@ -602,36 +645,117 @@ def test_config5_first_screens_match_oracle():
         assert err < 2e-6
 
 
-def test_config5_full_forward_adjoint_properties():
-    """5000 steps, checkpoint every 71 steps (about sqrt(5000): 71 + 2 x 70
-    fields), twin-experiment loss against the fluence of a run with a seeded
-    theta_ref; finite loss and gradients, non-increasing power, and a small
-    step against the theta gradient lowers the loss."""
+def test_config5_gradient_prefix_matches_oracle():
+    """The FP64 adjoint at full size (4096^2, all screen terms, seeded
+    theta) over the first 3 steps against the oracle's gradient."""
     inst = W.config5()[0]
     u0 = W.initial_field(inst)
-    p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=71)
-    p.gen_screens()
-    theta_ref = 0.05 * W.random_theta(55, 1.0)
+    target = W.synthetic_target(inst, 5)
+    theta = 0.05 * W.random_theta(56, 1.0)
+    steps = 3
+    # no screen falls in the first 3 steps (the first is after step 99)
+    l_ref, g_ref, t_ref = M.gradient(u0, inst, n_steps=steps, theta=theta,
+                                     cotangent=lambda u: M.fluence_loss(u, target))
+    p = _prop([inst], 64, max_steps=steps, ckpt_every=steps)
     p.set_field(0, u0)
-    p.set_theta(0, theta_ref)
-    p.propagate(inst.n_steps)
-    target = p.intensity(0, device=True)
-    th0 = np.zeros(8)
-
-    def run(th):
-        p.set_field(0, u0)
-        p.set_theta(0, th)
-        p.forward_record(inst.n_steps)
-        return p.fluence_loss(0, target)
-
-    l0 = run(th0)
-    pw, _ = p.diag(0, inst.n_steps)
+    p.set_theta(0, theta)
+    p.forward_record(steps)
+    gl = p.fluence_loss(0, target)
     p.backward()
-    g = p.grad_theta(0)
-    gu = p.grad_field(0, device=True)
-    assert np.isfinite(l0) and l0 > 0 and np.all(np.isfinite(g))
-    assert bool(gu.isfinite().all())
-    assert np.all(np.diff(pw) <= 1e-6 * pw[0])
-    l1 = run(th0 - 1e-4 * g / np.max(np.abs(g)))
-    _report("c5 fwd+adj", loss0=l0, loss1=l1, power_end=float(pw[-1] / pw[0]))
-    assert l1 < l0
+    gu, gt = p.grad_field(0), p.grad_theta(0)
+    lerr = abs(gl / l_ref - 1)
+    ferr = M.rel_l2(gu, g_ref)
+    terr = float(np.max(np.abs(gt - t_ref)) / np.max(np.abs(t_ref)))
+    _report("c5 grad fp64 steps=3", loss=lerr, g_u0=ferr, g_theta=terr)
+    assert lerr < C5_TOL[64] and ferr < C5_TOL[64] and terr < C5_TOL[64]
+
+
+def _absorbing_theta(seed):
+    """Seeded ansatz coefficients whose imaginary part is nonnegative, so the
+    ansatz only absorbs: (0.05 N(0,1) phase, 0.05 |N(0,1)| absorption)."""
+    th = 0.05 * W.random_theta(seed, 1.0)
+    th[4:] = np.abs(th[4:])
+    return th
+
+
+def test_nonfinite_theta_gradient_is_reported():
+    """With gain coefficients (negative imaginary theta) the linearised
+    4096^2 march grows by about e^1.45 per step (the Kerr phase per step is
+    25 rad at I = I_a), so the complex64 adjoint overflows within 200 steps;
+    ssfm_get_grad_theta reports SSFM_ENONFINITE instead of returning NaN
+    silently.  Only the arithmetic overflows: every kernel runs normally."""
+    from paper_2306_15678_amd._lib import ENONFINITE, SsfmError
+    inst = W.config5()[0]
+    theta = 0.05 * W.random_theta(55, 1.0)
+    assert np.any(theta[4:] < 0)
+    p = _prop([inst], 32, max_steps=200, ckpt_every=71)
+    p.gen_screens()
+    p.set_field(0, W.initial_field(inst))
+    p.set_theta(0, theta)
+    p.forward_record(200)
+    p.set_cotangent(0, W.random_field_like(inst.n, 7, 1.0))
+    p.backward()
+    with pytest.raises(SsfmError) as e:
+        p.grad_theta(0)
+    assert e.value.status == ENONFINITE
+
+
+def test_config5_full_forward_adjoint_properties():
+    """5000 steps, checkpoint every 71 steps (about sqrt(5000): 71 + 2 x 70
+    fields), twin experiment against the fluence of a run with a seeded,
+    absorbing theta_ref.  At theta_ref the loss and the gradients are at rounding
+    level.  At theta = 0: finite loss and gradients, power never increasing, and
+    gradients bitwise independent of the checkpoint interval (a recomputed
+    segment repeats the recorded march exactly).  After 1 km the complex64
+    march is chaotic (loss ~1 against its own twin), so no descent claim is
+    made here; descent and finite differences are checked on shorter
+    marches."""
+    import torch
+    inst = W.config5()[0]
+    u0 = W.initial_field(inst)
+    theta_ref = _absorbing_theta(55)
+    th0 = np.zeros(8)
+    grads = {}
+    for ckpt in (71, 100):
+        p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=ckpt)
+        p.gen_screens()
+        p.set_field(0, u0)
+        p.set_theta(0, theta_ref)
+        p.propagate(inst.n_steps)
+        target = p.intensity(0, device=True)
+
+        def run(th):
+            p.set_field(0, u0)
+            p.set_theta(0, th)
+            p.forward_record(inst.n_steps)
+            return p.fluence_loss(0, target)
+
+        if ckpt == 71:
+            # the target is read out by the field store and the loss by the
+            # seed kernel: the same FP64 intensity up to operation order
+            l_ref = run(theta_ref)
+            p.backward()
+            g_ref = float(np.max(np.abs(p.grad_theta(0))))
+            gu_ref = float(p.grad_field(0, device=True).abs().max())
+        l0 = run(th0)
+        pw, _ = p.diag(0, inst.n_steps)
+        p.backward()
+        g = p.grad_theta(0)
+        gu = p.grad_field(0, device=True)
+        assert np.isfinite(l0) and l0 > 0 and np.all(np.isfinite(g)) and np.any(g != 0)
+        assert bool(gu.isfinite().all())
+        assert np.all(np.diff(pw) <= 1e-6 * pw[0])
+        grads[ckpt] = (l0, g, gu.cpu())
+        _report(f"c5 fwd+adj ckpt={ckpt}", loss0=l0, power_end=float(pw[-1] / pw[0]))
+        p.close()
+        del p
+        torch.cuda.empty_cache()
+    # at theta_ref the residual is rounding of the intensity (~1e-16), and
+    # the gradients are linear in it
+    _report("c5 twin", loss=l_ref, g_theta=g_ref, g_u0=gu_ref)
+    assert l_ref < 1e-26
+    assert g_ref <= 1e-10 * np.max(np.abs(grads[71][1]))
+    assert gu_ref <= 1e-10 * float(grads[71][2].abs().max())
+    assert grads[71][0] == grads[100][0]
+    assert np.array_equal(grads[71][1], grads[100][1])
+    assert torch.equal(grads[71][2], grads[100][2])
