@@ -218,10 +218,25 @@ int ssfm_select_plan(ssfm_ctx* ctx, int32_t n, int32_t row_variant, int32_t col_
  * context's stream: reps launches of the forward row pass and of the
  * forward column pass over all instances.  Writes the mean milliseconds per
  * launch and the bytes each launch moves (algorithmic: read + write of the
- * field).  Leaves the fields unchanged only in the sense that they are
- * advanced by whole steps; call it on scratch state. */
+ * field).  The passes read the state and write the work buffer only, so the
+ * fields and the march position are unchanged. */
 int ssfm_time_passes(ssfm_ctx* ctx, int32_t reps, double* ms_row,
                      double* ms_col, double* bytes_row, double* bytes_col);
+
+/* Sampled pass timing inside the march itself.  With every > 0, each step
+ * s of ssfm_propagate and ssfm_forward_record with s % every == every / 2
+ * is launched outside the captured step graphs (which then cover the steps
+ * in between) and bracketed by HIP events on the context's stream: one
+ * before the row pass, one between the row and the column pass, one after
+ * the column pass.  Results are bitwise those of an unsampled march.  0
+ * (default) turns sampling off.  Changing it drops the captured graphs. */
+int ssfm_set_pass_timing(ssfm_ctx* ctx, int32_t every);
+
+/* Mean milliseconds of the row pass and of the column pass over the samples
+ * of the most recent propagate or forward-record call (synchronises the
+ * context's stream); *n_samples = 0 and zero times when none were taken. */
+int ssfm_pass_times(ssfm_ctx* ctx, double* ms_row, double* ms_col,
+                    int32_t* n_samples);
 
 /* Wait for all work of the context's stream. */
 int ssfm_synchronize(ssfm_ctx* ctx);

@@ -48,13 +48,15 @@ bool plan_info(bool column, int n, int v, bool fp64, PlanInfo* o) {
 
 template <typename R>
 hipError_t launch_pass(int kind, int n, int variant, int n_blocks, const PassArgs<R>& a,
-                       hipStream_t s) {
+                       hipStream_t s, const LaunchEv* ev) {
   if (n_blocks <= 0) return hipSuccess;
-  if (kind >= COL_FWD) return launch_col<R>(kind, n, variant, n_blocks, a, s);
-  return launch_row<R>(kind, n, variant, n_blocks, a, s);
+  if (kind >= COL_FWD) return launch_col<R>(kind, n, variant, n_blocks, a, s, ev);
+  return launch_row<R>(kind, n, variant, n_blocks, a, s, ev);
 }
-template hipError_t launch_pass<float>(int, int, int, int, const PassArgs<float>&, hipStream_t);
-template hipError_t launch_pass<double>(int, int, int, int, const PassArgs<double>&, hipStream_t);
+template hipError_t launch_pass<float>(int, int, int, int, const PassArgs<float>&, hipStream_t,
+                                       const LaunchEv*);
+template hipError_t launch_pass<double>(int, int, int, int, const PassArgs<double>&, hipStream_t,
+                                        const LaunchEv*);
 
 // ----------------------------------------------------- pointwise kernels
 template <typename R>

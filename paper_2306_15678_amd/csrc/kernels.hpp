@@ -20,6 +20,11 @@ struct cx;
 // epilogue).  ROW_INV / COL_INV are plain inverse DFTs for screen synthesis.
 enum PassKind { ROW_FWD = 0, ROW_ADJ = 1, ROW_INV = 2, COL_FWD = 3, COL_ADJ = 4, COL_INV = 5 };
 
+// Start/stop events carried by one pass launch (sampled timing).
+struct LaunchEv {
+  hipEvent_t start, stop;
+};
+
 template <typename R>
 struct PassArgs {
   const void* src;            // cx<R> field buffer read
@@ -51,7 +56,7 @@ bool plan_info(bool column, int n, int variant, bool fp64, PlanInfo* out);
 
 template <typename R>
 hipError_t launch_pass(int kind, int n, int variant, int n_blocks,
-                       const PassArgs<R>& a, hipStream_t s);
+                       const PassArgs<R>& a, hipStream_t s, const LaunchEv* ev = nullptr);
 
 // Pointwise helpers -------------------------------------------------------
 

@@ -21,6 +21,7 @@
 // 8 B read + 8 B written per point per pass (complex64).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "fft_core.hpp"
@@ -276,29 +277,43 @@ __global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
 }
 
 // -------------------------------------------------------------- launch
+// With ev, the launch carries start/stop events on its own dispatch (timing
+// of the kernel alone, no separate marker packets).
 template <typename R, class P, int KIND>
-hipError_t launch_one(int n_blocks, const PassArgs<R>& a, hipStream_t s) {
+hipError_t launch_one(int n_blocks, const PassArgs<R>& a, hipStream_t s, const LaunchEv* ev) {
   if constexpr (KIND >= COL_FWD) {
-    hipLaunchKernelGGL((k_col<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s, a);
+    if (ev)
+      hipExtLaunchKernelGGL((k_col<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s,
+                            ev->start, ev->stop, 0, a);
+    else
+      hipLaunchKernelGGL((k_col<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_row<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s, a);
+    if (ev)
+      hipExtLaunchKernelGGL((k_row<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s,
+                            ev->start, ev->stop, 0, a);
+    else
+      hipLaunchKernelGGL((k_row<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s, a);
   }
   return hipGetLastError();
 }
 
 template <typename R, int KIND>
-hipError_t launch_row_kind(int n, int v, int nb, const PassArgs<R>& a, hipStream_t s) {
+hipError_t launch_row_kind(int n, int v, int nb, const PassArgs<R>& a, hipStream_t s,
+                           const LaunchEv* ev) {
 #define SSFM_RCASE(NN, VV, ...) \
-  if (n == NN && v == VV) return launch_one<R, typename RowPlanSel<NN, VV>::P, KIND>(nb, a, s);
+  if (n == NN && v == VV)       \
+    return launch_one<R, typename RowPlanSel<NN, VV>::P, KIND>(nb, a, s, ev);
   SSFM_ROW_PLANS(SSFM_RCASE)
 #undef SSFM_RCASE
   return hipErrorInvalidValue;
 }
 
 template <typename R, int KIND>
-hipError_t launch_col_kind(int n, int v, int nb, const PassArgs<R>& a, hipStream_t s) {
+hipError_t launch_col_kind(int n, int v, int nb, const PassArgs<R>& a, hipStream_t s,
+                           const LaunchEv* ev) {
 #define SSFM_CCASE(NN, VV, ...) \
-  if (n == NN && v == VV) return launch_one<R, typename ColPlanSel<NN, VV>::P, KIND>(nb, a, s);
+  if (n == NN && v == VV)       \
+    return launch_one<R, typename ColPlanSel<NN, VV>::P, KIND>(nb, a, s, ev);
   SSFM_COL_PLANS(SSFM_CCASE)
 #undef SSFM_CCASE
   return hipErrorInvalidValue;
@@ -306,8 +321,10 @@ hipError_t launch_col_kind(int n, int v, int nb, const PassArgs<R>& a, hipStream
 
 // Per-unit entry points (defined in pass_{row,col}_{f32,f64}.hip).
 template <typename R>
-hipError_t launch_row(int kind, int n, int v, int nb, const PassArgs<R>& a, hipStream_t s);
+hipError_t launch_row(int kind, int n, int v, int nb, const PassArgs<R>& a, hipStream_t s,
+                      const LaunchEv* ev);
 template <typename R>
-hipError_t launch_col(int kind, int n, int v, int nb, const PassArgs<R>& a, hipStream_t s);
+hipError_t launch_col(int kind, int n, int v, int nb, const PassArgs<R>& a, hipStream_t s,
+                      const LaunchEv* ev);
 
 }  // namespace ssfm

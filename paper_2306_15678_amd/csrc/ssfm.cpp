@@ -131,7 +131,17 @@ struct ssfm_ctx {
   int64_t rec_steps = 0, rec_step0 = 0;
   bool rec_valid = false, seeded = false, grads_valid = false;
   bool use_graphs = true;
-  std::map<std::tuple<int, int64_t, int64_t>, hipGraphExec_t> graphs;
+  std::map<std::tuple<int, int64_t, int64_t, int64_t, int64_t>, hipGraphExec_t> graphs;
+  // Sampled pass timing (0: off): with timing_every = m, step s of a
+  // forward march with s % m == m / 2 runs outside the step graphs, each of
+  // its pass kernels launched with start/stop events on its own dispatch;
+  // samples holds those of the most recent forward march.  ev[2 * (p * G +
+  // g) + {0, 1}]: start/stop of pass p (0 row, 1 column) for size group g.
+  struct PassSample {
+    std::vector<hipEvent_t> ev;
+  };
+  int32_t timing_every = 0;
+  std::vector<PassSample> samples, free_samples;
   // second stream (default priority) and events for the overlapped backward
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -148,8 +158,15 @@ struct ssfm_ctx {
   void* field(size_t off, int64_t k = 0) const {
     return ws + off + size_t(k) * size_t(L.field_elems) * el;
   }
+  static void destroy(std::vector<PassSample>& v) {
+    for (auto& e : v)
+      for (auto x : e.ev) (void)hipEventDestroy(x);
+    v.clear();
+  }
   ~ssfm_ctx() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    destroy(samples);
+    destroy(free_samples);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (aux) (void)hipStreamDestroy(aux);
@@ -420,7 +437,8 @@ PassArgs<R> base_args(ssfm_ctx* c) {
 // groups the launches run concurrently (group g > 0 on its own stream,
 // forked from and joined back to st), so their ramps and tails overlap.
 template <typename R>
-int run_pass(ssfm_ctx* c, int kind, PassArgs<R> a, hipStream_t st = nullptr) {
+int run_pass(ssfm_ctx* c, int kind, PassArgs<R> a, hipStream_t st = nullptr,
+             const hipEvent_t* ev = nullptr) {
   const bool col = kind >= COL_FWD;
   if (!st) st = c->stream;
   const int chain = (st == c->aux) ? 1 : 0;
@@ -437,7 +455,8 @@ int run_pass(ssfm_ctx* c, int kind, PassArgs<R> a, hipStream_t st = nullptr) {
     const int nb = col ? g.col_blocks : g.row_blocks;
     const int v = col ? g.col_var : g.row_var;
     hipStream_t sg = (fork && gi > 0) ? c->gstream[chain][gi - 1] : st;
-    HIP_TRY(launch_pass<R>(kind, g.n, v, nb, a, sg));
+    const LaunchEv le = ev ? LaunchEv{ev[2 * gi], ev[2 * gi + 1]} : LaunchEv{nullptr, nullptr};
+    HIP_TRY(launch_pass<R>(kind, g.n, v, nb, a, sg, ev ? &le : nullptr));
   }
   if (fork) {
     for (size_t g = 1; g < ng; ++g) {
@@ -449,20 +468,50 @@ int run_pass(ssfm_ctx* c, int kind, PassArgs<R> a, hipStream_t st = nullptr) {
 }
 
 // One forward step: src (s_n) -> work -> dst (s_{n+1}), on stream st.
+// A timing sample (a start/stop pair per pass and size group) from the
+// pool; false if none could be made.
+bool take_sample(ssfm_ctx* c, ssfm_ctx::PassSample* ps) {
+  const size_t need = 4 * c->groups.size();
+  if (!c->free_samples.empty()) {
+    *ps = std::move(c->free_samples.back());
+    c->free_samples.pop_back();
+    if (ps->ev.size() == need) return true;
+    for (auto x : ps->ev) (void)hipEventDestroy(x);
+  }
+  ps->ev.assign(need, nullptr);
+  for (auto& x : ps->ev)
+    if (hipEventCreate(&x) != hipSuccess) {
+      for (auto y : ps->ev)
+        if (y) (void)hipEventDestroy(y);
+      ps->ev.clear();
+      (void)hipGetLastError();  // timing is best effort: the march proceeds unsampled
+      return false;
+    }
+  return true;
+}
+
+void clear_graphs(ssfm_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
 template <typename R>
 int fwd_step(ssfm_ctx* c, const void* src, void* dst, int64_t pending_step, double* part,
-             void* work = nullptr, hipStream_t st = nullptr) {
+             void* work = nullptr, hipStream_t st = nullptr,
+             const ssfm_ctx::PassSample* ts = nullptr) {
   if (!work) work = c->field(c->L.Wk);
+  if (!st) st = c->stream;
   PassArgs<R> a = base_args<R>(c);
   a.src = src;
   a.dst = work;
   a.step = pending_step;
-  if (int r = run_pass<R>(c, ROW_FWD, a, st)) return r;
+  const size_t ng = c->groups.size();
+  if (int r = run_pass<R>(c, ROW_FWD, a, st, ts ? ts->ev.data() : nullptr)) return r;
   PassArgs<R> b = base_args<R>(c);
   b.src = work;
   b.dst = dst;
   b.part = part;
-  return run_pass<R>(c, COL_FWD, b, st);
+  return run_pass<R>(c, COL_FWD, b, st, ts ? ts->ev.data() + 2 * ng : nullptr);
 }
 
 // One adjoint step: Lam -> Wk (columns) -> Lam (rows + adjoint screen with
@@ -491,17 +540,22 @@ int diag_flush(ssfm_ctx* c, int steps, int64_t first_step) {
   return SSFM_OK;
 }
 
-// Enqueue n plain forward steps starting at c->step.
+// Enqueue steps i0 <= i < i1 of a plain forward march from step0 (step
+// step0 + i; pending0: the state holds V with the screen of step0 - 1 still
+// to apply).  ts: timing events around the passes (single steps only).
 template <typename R>
-int enqueue_propagate(ssfm_ctx* c, int64_t n, int64_t step0, bool pending0) {
-  int64_t chunk_start = step0;
-  for (int64_t i = 0; i < n; ++i) {
+int enqueue_propagate(ssfm_ctx* c, int64_t step0, bool pending0, int64_t i0, int64_t i1,
+                      const ssfm_ctx::PassSample* ts) {
+  int64_t chunk_start = step0 + i0;
+  for (int64_t i = i0; i < i1; ++i) {
     const int64_t step = step0 + i;
-    const int slot = int(i % kDiagChunk);
+    const int slot = int((i - i0) % kDiagChunk);
     double* part = c->at<double>(c->L.diag_part) + size_t(slot) * 2 * c->L.n_widx_cols;
     const int64_t pend = (i == 0 && !pending0) ? -1 : step - 1;
-    if (int r = fwd_step<R>(c, c->field(c->L.S), c->field(c->L.S), pend, part)) return r;
-    if (slot == kDiagChunk - 1 || i == n - 1) {
+    if (int r = fwd_step<R>(c, c->field(c->L.S), c->field(c->L.S), pend, part, nullptr, nullptr,
+                            ts))
+      return r;
+    if (slot == kDiagChunk - 1 || i == i1 - 1) {
       if (int r = diag_flush<R>(c, slot + 1, chunk_start)) return r;
       chunk_start = step + 1;
     }
@@ -509,11 +563,11 @@ int enqueue_propagate(ssfm_ctx* c, int64_t n, int64_t step0, bool pending0) {
   return SSFM_OK;
 }
 
-// Runs `body` directly or through a cached graph keyed by (kind, a, b).
+// Runs `body` directly or through a cached graph keyed by (kind, a, b, i0, i1).
 template <typename F>
-int maybe_graph(ssfm_ctx* c, int kind, int64_t a, int64_t b, F body) {
+int maybe_graph(ssfm_ctx* c, int kind, int64_t a, int64_t b, int64_t i0, int64_t i1, F body) {
   if (!c->use_graphs) return body();
-  auto key = std::make_tuple(kind, a, b);
+  auto key = std::make_tuple(kind, a, b, i0, i1);
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     hipStream_t cap;
@@ -546,12 +600,44 @@ int maybe_graph(ssfm_ctx* c, int kind, int64_t a, int64_t b, F body) {
   return SSFM_OK;
 }
 
+// Steps [0, n) of a forward march from step0 through seg(i0, i1, ts): in
+// captured graphs keyed by (kind, key, n, i0, i1) between the sampled steps,
+// each sampled step launched directly between its timing events.
+template <typename Seg>
+int run_forward(ssfm_ctx* c, int kind, int64_t key, int64_t n, int64_t step0, Seg seg) {
+  for (auto& e : c->samples) c->free_samples.push_back(e);
+  c->samples.clear();
+  int64_t i = 0;
+  auto graph_to = [&](int64_t k) -> int {
+    if (k <= i) return SSFM_OK;
+    const int64_t i0 = i;
+    return maybe_graph(c, kind, key, n, i0, k, [&] { return seg(i0, k, nullptr); });
+  };
+  const int64_t m = c->timing_every;
+  if (m > 0) {
+    int64_t first = (m / 2 - step0 % m) % m;  // first i with (step0 + i) % m == m / 2
+    if (first < 0) first += m;
+    for (int64_t k = first; k < n; k += m) {
+      if (int r = graph_to(k)) return r;
+      ssfm_ctx::PassSample ps;
+      const bool have = take_sample(c, &ps);
+      int r = seg(k, k + 1, have ? &ps : nullptr);
+      if (have) c->samples.push_back(std::move(ps));
+      if (r) return r;
+      i = k + 1;
+    }
+  }
+  return graph_to(n);
+}
+
 template <typename R>
 int do_propagate(ssfm_ctx* c, int64_t n) {
   const int64_t step0 = c->step;
   const bool pend = c->pending;
-  int r = maybe_graph(c, 0, step0 * 2 + (pend ? 1 : 0), n,
-                      [&] { return enqueue_propagate<R>(c, n, step0, pend); });
+  int r = run_forward(c, 0, step0 * 2 + (pend ? 1 : 0), n, step0,
+                      [&](int64_t i0, int64_t i1, const ssfm_ctx::PassSample* ts) {
+                        return enqueue_propagate<R>(c, step0, pend, i0, i1, ts);
+                      });
   if (r) return r;
   c->step += n;
   c->pending = true;
@@ -590,16 +676,23 @@ void* rec_slot(ssfm_ctx* c, int64_t i, int64_t n) {
   return c->field(c->L.S);
 }
 
+// Steps i0 <= i < i1 of an n-step record from step0 (the first range also
+// copies s_0 into checkpoint 0).  ts: timing events (single steps only).
 template <typename R>
-int enqueue_record(ssfm_ctx* c, int64_t n, int64_t step0) {
-  HIP_TRY(launch_copy<R>(c->field(c->L.S), c->field(c->L.ckpt, 0), c->L.field_elems, c->stream));
-  int64_t chunk_start = step0;
-  for (int64_t i = 0; i < n; ++i) {
-    const int slot = int(i % kDiagChunk);
+int enqueue_record(ssfm_ctx* c, int64_t n, int64_t step0, int64_t i0, int64_t i1,
+                   const ssfm_ctx::PassSample* ts) {
+  if (i0 == 0)
+    HIP_TRY(launch_copy<R>(c->field(c->L.S), c->field(c->L.ckpt, 0), c->L.field_elems,
+                           c->stream));
+  int64_t chunk_start = step0 + i0;
+  for (int64_t i = i0; i < i1; ++i) {
+    const int slot = int((i - i0) % kDiagChunk);
     double* part = c->at<double>(c->L.diag_part) + size_t(slot) * 2 * c->L.n_widx_cols;
     const int64_t pend = (i == 0) ? -1 : step0 + i - 1;
-    if (int r = fwd_step<R>(c, rec_slot(c, i, n), rec_slot(c, i + 1, n), pend, part)) return r;
-    if (slot == kDiagChunk - 1 || i == n - 1) {
+    if (int r = fwd_step<R>(c, rec_slot(c, i, n), rec_slot(c, i + 1, n), pend, part, nullptr,
+                            nullptr, ts))
+      return r;
+    if (slot == kDiagChunk - 1 || i == i1 - 1) {
       if (int r = diag_flush<R>(c, slot + 1, chunk_start)) return r;
       chunk_start = step0 + i + 1;
     }
@@ -614,7 +707,10 @@ int do_record(ssfm_ctx* c, int64_t n) {
                 (long long)c->max_steps);
   if (int r = flush_pending<R>(c)) return r;
   const int64_t step0 = c->step;
-  int r = maybe_graph(c, 1, step0, n, [&] { return enqueue_record<R>(c, n, step0); });
+  int r = run_forward(c, 1, step0, n, step0,
+                      [&](int64_t i0, int64_t i1, const ssfm_ctx::PassSample* ts) {
+                        return enqueue_record<R>(c, n, step0, i0, i1, ts);
+                      });
   if (r) return r;
   c->step += n;
   c->pending = true;
@@ -686,7 +782,8 @@ template <typename R>
 int do_backward(ssfm_ctx* c) {
   if (!c->rec_valid) return fail(SSFM_ESTATE, "backward needs a preceding ssfm_forward_record");
   if (!c->seeded) return fail(SSFM_ESTATE, "backward needs a cotangent (set_cotangent/fluence_loss)");
-  int r = maybe_graph(c, 2, c->rec_step0, c->rec_steps, [&] { return enqueue_backward<R>(c); });
+  int r = maybe_graph(c, 2, c->rec_step0, c->rec_steps, 0, 0,
+                      [&] { return enqueue_backward<R>(c); });
   if (r) return r;
   c->grads_valid = true;
   return SSFM_OK;
@@ -904,8 +1001,7 @@ int do_select(ssfm_ctx* c, int32_t n, int32_t rv, int32_t cv) {
   HIP_TRY(hipMemcpyAsync(c->ws + c->L.wbegin_col, c->wbegin_col.data(),
                          sizeof(int32_t) * c->wbegin_col.size(), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-  c->graphs.clear();
+  clear_graphs(c);
   return SSFM_OK;
 }
 
@@ -1247,6 +1343,52 @@ int ssfm_time_passes(ssfm_ctx* c, int32_t reps, double* ms_row, double* ms_col,
   (void)hipEventDestroy(e1);
   (void)hipEventDestroy(e2);
   return r;
+}
+
+int ssfm_set_pass_timing(ssfm_ctx* c, int32_t every) {
+  if (int r = check_ctx(c)) return r;
+  if (every < 0) return fail(SSFM_EINVAL, "every must be >= 0");
+  if (every == c->timing_every) return SSFM_OK;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  clear_graphs(c);  // the step graphs are cut at the sampled steps
+  for (auto& e : c->samples) c->free_samples.push_back(e);
+  c->samples.clear();
+  c->timing_every = every;
+  return SSFM_OK;
+}
+
+int ssfm_pass_times(ssfm_ctx* c, double* ms_row, double* ms_col, int32_t* n_samples) {
+  if (int r = check_ctx(c)) return r;
+  double tr = 0.0, tc = 0.0;
+  int32_t n = 0;
+  if (!c->samples.empty()) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const size_t ng = c->groups.size();
+    for (const auto& e : c->samples) {
+      // span of each pass: earliest start to latest stop over its size
+      // groups (group 0 launches first; the others run concurrently)
+      double span[2];
+      for (int p = 0; p < 2; ++p) {
+        const hipEvent_t ref = e.ev[2 * (p * ng)];
+        double lo = 0.0, hi = 0.0;
+        for (size_t g = 0; g < ng; ++g) {
+          float t0 = 0.f, t1 = 0.f;
+          HIP_TRY(hipEventElapsedTime(&t0, ref, e.ev[2 * (p * ng + g)]));
+          HIP_TRY(hipEventElapsedTime(&t1, ref, e.ev[2 * (p * ng + g) + 1]));
+          lo = std::min(lo, double(t0));
+          hi = std::max(hi, double(t1));
+        }
+        span[p] = hi - lo;
+      }
+      tr += span[0];
+      tc += span[1];
+      ++n;
+    }
+  }
+  if (ms_row) *ms_row = n ? tr / n : 0.0;
+  if (ms_col) *ms_col = n ? tc / n : 0.0;
+  if (n_samples) *n_samples = n;
+  return SSFM_OK;
 }
 
 int ssfm_synchronize(ssfm_ctx* c) {

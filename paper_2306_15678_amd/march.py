@@ -197,6 +197,17 @@ class Propagator:
         L.call("ssfm_time_passes", self.ctx, reps, *[ctypes.byref(v) for v in vals])
         return tuple(v.value for v in vals)
 
+    def set_pass_timing(self, every: int) -> None:
+        """Sample the row/column pass durations every ``every`` steps of each
+        forward march (0: off)."""
+        L.call("ssfm_set_pass_timing", self.ctx, int(every))
+
+    def pass_times(self):
+        """(ms_row, ms_col, n_samples) of the most recent forward march."""
+        r, c, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        L.call("ssfm_pass_times", self.ctx, ctypes.byref(r), ctypes.byref(c), ctypes.byref(n))
+        return r.value, c.value, n.value
+
     def block_mean(self, src: torch.Tensor, b: int) -> torch.Tensor:
         n = src.shape[0]
         src = src.contiguous()

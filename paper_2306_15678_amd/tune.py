@@ -50,8 +50,8 @@ def save_cache(d: Dict) -> None:
 def tune(prop: Propagator, reps: int = 50, use_cache: bool = True,
          verbose: bool = False) -> Dict[int, Dict]:
     """Select the fastest row and column variants for each grid size of
-    ``prop`` and return the timings.  The timing launches advance the
-    context's fields: call before ``set_field``."""
+    ``prop`` and return the timings.  The timing launches write the work
+    buffer only; the fields are unchanged."""
     cache = load_cache() if use_cache else {}
     out = {}
     for n in sorted({d.n for d in prop.descs}):

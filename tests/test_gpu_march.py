@@ -759,3 +759,34 @@ def test_config5_full_forward_adjoint_properties():
     assert grads[71][0] == grads[100][0]
     assert np.array_equal(grads[71][1], grads[100][1])
     assert torch.equal(grads[71][2], grads[100][2])
+
+
+# ------------------------------------------------------------ pass timing
+@pytest.mark.parametrize("graphs", [True, False])
+def test_pass_timing_samples(graphs):
+    """Sampled in-march pass timing: the expected number of samples (steps
+    s with s % 10 == 5 of the last forward march), positive durations of the
+    order of the isolated pass timing, and fields bitwise identical to a run
+    without sampling."""
+    inst = W.config2()[0]
+    u0 = W.initial_field(inst)
+    out = {}
+    for every in (0, 10):
+        p = _prop([inst], 32, max_steps=60, ckpt_every=20)
+        p.use_graphs(graphs)
+        p.set_pass_timing(every)
+        p.set_field(0, u0)
+        p.propagate(37)              # steps 0..36: samples at 5, 15, 25, 35
+        r, c, n = p.pass_times()
+        assert n == (4 if every else 0)
+        if every:
+            iso_r, iso_c, _, _ = p.time_passes(reps=20)
+            _report(f"pass timing graphs={graphs}", row=r, col=c, iso_row=iso_r, iso_col=iso_c)
+            assert 0 < r < 3 * iso_r and 0 < c < 3 * iso_c
+            p.forward_record(40)      # steps 37..76: samples at 45, 55, 65, 75
+            assert p.pass_times()[2] == 4
+        else:
+            p.forward_record(40)
+        out[every] = p.field(0)
+        p.close()
+    assert np.array_equal(out[0], out[10])
