@@ -3,9 +3,11 @@
 Workload (default): the 1024 x 1024 multifilamentation beam (1 cm, 100 P_cr,
 Kerr + multiphoton absorption + saturating plasma, 10 % seeded noise),
 2000 z steps of 1 cm, complex64 with FP64 reductions.  One bench step is
-the whole differentiable march: forward with a checkpoint every 50 steps,
-the fluence-mismatch loss against a synthetic target, and the exact adjoint
-back to the input field (segment recompute included).  Grid-point . steps
+the whole differentiable march: the recorded forward march (the whole
+trajectory kept in HBM when it fits half the free memory, 16 GiB here;
+otherwise checkpoints with segment recompute in the backward), the
+fluence-mismatch loss against a synthetic target, and the exact adjoint
+back to the input field.  Grid-point . steps
 count each z step once.
 
 The JSON line also carries: the roofline of the dominant pass kernel
@@ -71,9 +73,12 @@ def run_gpu(args):
     out = {}
 
     def make(precision):
+        from paper_2306_15678_amd.march import checkpoint_interval
         from paper_2306_15678_amd.tune import tune
+        m = ckpt or checkpoint_interval(_desc_list([inst]), precision, z_steps)
+        out["ckpt_fp%d" % precision] = m
         p = Propagator(_desc_list([inst]), precision=precision, max_steps=z_steps,
-                       ckpt_every=ckpt, device=dev)
+                       ckpt_every=m, device=dev)
         # pick the fastest tile variants (setup, not timed)
         out["tune_fp%d" % precision] = tune(p, reps=30, use_cache=False)[inst.n]
         return p
@@ -226,7 +231,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--ckpt-every", type=int, default=50)
+    ap.add_argument("--ckpt-every", type=int, default=0,
+                    help="checkpoint interval of the recorded march (0: keep the whole "
+                         "trajectory when it fits half the free HBM, else about sqrt(steps))")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
@@ -259,8 +266,8 @@ def main():
         "config": {
             "workload": "multifilamentation beam, 1024x1024 complex64 (FP64 reductions), "
                         "Kerr+MPA+plasma, 2000 z steps, forward+adjoint, checkpoint every "
-                        f"{args.ckpt_every} steps",
-            "grid": inst.n, "z_steps": inst.n_steps, "ckpt_every": args.ckpt_every,
+                        f"{g['ckpt_fp32']} steps",
+            "grid": inst.n, "z_steps": inst.n_steps, "ckpt_every": g["ckpt_fp32"],
             "beam": "w0=1 cm, 100 P_cr, 10% seeded noise, window 6 cm, dz=1 cm",
         },
         "roofline": {
@@ -278,7 +285,7 @@ def main():
                       f"forward record of the last timed step ({lv['samples']} samples), "
                       "library stream",
         },
-        "fp64": {"value": g[64]["value"], "ms_per_step": t64 * 1e3,
+        "fp64": {"value": g[64]["value"], "ms_per_step": t64 * 1e3, "ckpt_every": g["ckpt_fp64"],
                  "speedup_fp32_over_fp64": t64 / t32},
         "forward_only": {"value": g["fwd"]["value"], "ms_per_step": g["fwd"]["s_per_step"] * 1e3},
         "passes_ms": {"row": lv["ms_row"], "col": lv["ms_col"]},

@@ -9,6 +9,7 @@ the library's kernels; torch is used only to hold memory and pick streams.
 from __future__ import annotations
 
 import ctypes
+import math
 from typing import Iterable, List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -215,6 +216,29 @@ class Propagator:
         L.call("ssfm_block_mean", self.ctx, ctypes.c_void_p(src.data_ptr()), n, b,
                ctypes.c_void_p(out.data_ptr()))
         return out
+
+
+def workspace_bytes(descs: Sequence[L.InstanceDesc], precision: int, max_steps: int,
+                    ckpt_every: int) -> int:
+    """Device workspace a context with these arguments needs."""
+    arr = (L.InstanceDesc * len(descs))(*descs)
+    nbytes = ctypes.c_size_t()
+    L.call("ssfm_workspace_bytes", arr, len(descs), precision, max_steps, ckpt_every,
+           ctypes.byref(nbytes))
+    return nbytes.value
+
+
+def checkpoint_interval(descs: Sequence[L.InstanceDesc], precision: int, n_steps: int,
+                        budget_bytes: Optional[int] = None) -> int:
+    """Checkpoint interval M for a recorded march of n_steps: n_steps (every
+    pre-screen field kept, no recompute in the backward) when that workspace
+    fits the budget (default: half the free device memory), else
+    ceil(sqrt(n_steps)) (checkpoints plus two banks of one segment)."""
+    if budget_bytes is None:
+        budget_bytes = torch.cuda.mem_get_info()[0] // 2
+    if workspace_bytes(descs, precision, n_steps, n_steps) <= budget_bytes:
+        return n_steps
+    return max(1, math.isqrt(n_steps - 1) + 1)
 
 
 def plan_variants(n: int, precision: int = 32) -> Tuple[int, int]:

@@ -105,3 +105,16 @@ def test_plan_variant_counts():
         assert L.lib().ssfm_plan_variants(n, 32, ctypes.byref(r), ctypes.byref(c)) == 0
         assert r.value >= 2 and c.value >= 2
     assert L.lib().ssfm_plan_variants(100, 32, ctypes.byref(r), ctypes.byref(c)) == L.EUNSUPPORTED
+
+
+def test_checkpoint_interval_keeps_trajectory_when_it_fits():
+    """The whole 2000-step complex64 trajectory of the 1024^2 beam (16 GiB)
+    is kept when the budget allows it, else ceil(sqrt(2000)) = 45."""
+    import workloads as W
+    from paper_2306_15678_amd.march import checkpoint_interval, desc_of, workspace_bytes
+    d = [desc_of(W.config2()[0])]
+    full = workspace_bytes(d, 32, 2000, 2000)
+    assert full >= 2000 * 1024 * 1024 * 8
+    assert checkpoint_interval(d, 32, 2000, budget_bytes=full) == 2000
+    assert checkpoint_interval(d, 32, 2000, budget_bytes=full - 1) == 45
+    assert workspace_bytes(d, 32, 2000, 45) < full // 10
