@@ -105,6 +105,8 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
   if constexpr (KIND == ROW_INV) {
     if (2 * a.pair >= in.n_screens || !(in.terms & T_TURB)) return;
   }
+  // screen constants fetched with the first loads, not after the FFT input
+  const ScreenConst<R> sc = screen_const<R>(in);
   const int line = threadIdx.x / T;
   const int t = threadIdx.x - line * T;
   const int row = w.line0 + line;
@@ -154,11 +156,7 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
   (void)row;
 
   if constexpr (KIND == ROW_FWD) {
-    if (a.step >= 0) {
-      const ScreenConst<R> sc = screen_const<R>(in);
-#pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = screen_apply(sc, v[e], ph[e]);
-    }
+    if (a.step >= 0) screen_apply_n<R, E>(sc, v, ph);
   }
 
   if constexpr (KIND == ROW_INV) {
@@ -172,10 +170,11 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
 
   if constexpr (KIND == ROW_ADJ) {
     if (a.step >= 0) {
-      const ScreenConst<R> sc = screen_const<R>(in);
       double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      constexpr int AC = (E % 4 == 0) ? 4 : E;  // points per adjoint batch
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = screen_adjoint(sc, sv[e], v[e], ph[e], g);
+      for (int c = 0; c < E; c += AC)
+        screen_adjoint_n<R, AC>(sc, sv + c, v + c, ph + c, plane != nullptr, g);
       if (in.terms & T_ANSATZ) {
         block_reduce<8, P::THREADS, false>(g, red);
         if (threadIdx.x == 0) {
@@ -205,6 +204,7 @@ __global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
   if constexpr (KIND == COL_INV) {
     if (2 * a.pair >= in.n_screens || !(in.terms & T_TURB)) return;
   }
+  const ScreenConst<R> sc = screen_const<R>(in);
   const int c = threadIdx.x % W;
   const int t = threadIdx.x / W;
   // uniform base (first column of the tile); per-thread 32-bit offsets
@@ -256,12 +256,14 @@ __global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
 
   if constexpr (KIND == COL_FWD) {
     if (a.part != nullptr) {
-      const ScreenConst<R> sc = screen_const<R>(in);
       double s[1] = {0.0}, m[1] = {0.0};
+      R x[E], a2[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) x[e] = v[e].re * v[e].re + v[e].im * v[e].im;
+      screen_amp2_n<R, E>(sc, x, a2);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const R x = v[e].re * v[e].re + v[e].im * v[e].im;
-        const double xa = double(x) * double(screen_amp2(sc, x));
+        const double xa = double(x[e]) * double(a2[e]);
         s[0] += xa;
         m[0] = fmax(m[0], xa);
       }

@@ -218,4 +218,244 @@ __device__ __forceinline__ cx<R> screen_adjoint(const ScreenConst<R>& s,
   return t1 + t2;
 }
 
+// ------------------------------------------------------------------------
+// Batched forms over C points of one thread.  The term tests are uniform
+// over a launch; here they sit outside the point loops, so a thread takes
+// each branch once per batch instead of once per point.  Per point the
+// arithmetic and its order are those of the single-point forms above.
+
+template <typename R, int C>
+__device__ __forceinline__ void ipow_n(const R* x, int m, R* out) {
+  if (m == 7) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const R x2 = x[e] * x[e], x4 = x2 * x2;
+      out[e] = x4 * x2 * x[e];
+    }
+  } else if (m == 6) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const R x2 = x[e] * x[e];
+      out[e] = x2 * x2 * x2;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      R r = R(1);
+      for (int i = 0; i < m; ++i) r *= x[e];
+      out[e] = r;
+    }
+  }
+}
+
+// ln A and Phi (without turbulence) at C points.
+template <typename R, int C>
+__device__ __forceinline__ void screen_eval_n(const ScreenConst<R>& s, const R* x, R* log_a,
+                                              R* phi) {
+  const unsigned tm = s.terms;
+#pragma unroll
+  for (int e = 0; e < C; ++e) {
+    log_a[e] = R(0);
+    phi[e] = R(0);
+  }
+  R xk1[C];
+  if (tm & (T_MPA | T_PLASMA)) ipow_n<R, C>(x, s.K - 1, xk1);
+  if (tm & T_KERR) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) phi[e] += s.cK * x[e];
+  }
+  if (tm & T_PLASMA) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) phi[e] -= s.cK * x[e] * (R(1) - rcp(R(1) + xk1[e]));
+  }
+  if (tm & T_MPA) {
+#pragma unroll
+    for (int e = 0; e < C; ++e)
+      log_a[e] -= fast_log2(R(1) + s.cM * xk1[e]) * (R(0.69314718055994530942) * s.inv2k1);
+  }
+  if (tm & T_ANSATZ) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const R xe = x[e], x2 = xe * xe, x3 = x2 * xe, x4 = x2 * x2;
+      const R inv = rcp(R(1) + x4);
+      const R re = (s.th[0] * xe + s.th[1] * x2 + s.th[2] * x3 + s.th[3] * x4) * inv;
+      const R im = (s.th[4] * xe + s.th[5] * x2 + s.th[6] * x3 + s.th[7] * x4) * inv;
+      phi[e] += s.cK * re;
+      log_a[e] -= s.cK * im;
+    }
+  }
+}
+
+// A^2 at C points.
+template <typename R, int C>
+__device__ __forceinline__ void screen_amp2_n(const ScreenConst<R>& s, const R* x, R* out) {
+  const unsigned tm = s.terms;
+  R l2[C];
+#pragma unroll
+  for (int e = 0; e < C; ++e) l2[e] = R(0);
+  if (tm & T_MPA) {
+    R xk1[C];
+    ipow_n<R, C>(x, s.K - 1, xk1);
+#pragma unroll
+    for (int e = 0; e < C; ++e)
+      l2[e] -= fast_log2(R(1) + s.cM * xk1[e]) * (R(2) * s.inv2k1);
+  }
+  if (tm & T_ANSATZ) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const R xe = x[e], x2 = xe * xe, x3 = x2 * xe, x4 = x2 * x2;
+      const R im = (s.th[4] * xe + s.th[5] * x2 + s.th[6] * x3 + s.th[7] * x4) *
+                   rcp(R(1) + x4);
+      l2[e] -= R(2) * s.cK * im * R(1.44269504088896340736);
+    }
+  }
+  if (tm & (T_MPA | T_ANSATZ)) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) out[e] = (l2[e] == R(0)) ? R(1) : fast_exp2(l2[e]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < C; ++e) out[e] = R(1);
+  }
+}
+
+// u <- u E(|u|^2) exp(i phi_t) at C points.
+template <typename R, int C>
+__device__ __forceinline__ void screen_apply_n(const ScreenConst<R>& s, cx<R>* u,
+                                               const R* phi_t) {
+  R x[C], log_a[C], phi[C];
+#pragma unroll
+  for (int e = 0; e < C; ++e) x[e] = u[e].re * u[e].re + u[e].im * u[e].im;
+  screen_eval_n<R, C>(s, x, log_a, phi);
+  R a[C];
+  if (s.terms & (T_MPA | T_ANSATZ)) {
+#pragma unroll
+    for (int e = 0; e < C; ++e)
+      a[e] = (log_a[e] == R(0)) ? R(1) : fast_exp2(log_a[e] * R(1.44269504088896340736));
+  } else {
+#pragma unroll
+    for (int e = 0; e < C; ++e) a[e] = R(1);
+  }
+  R sn[C], cs[C];
+  if (s.terms & T_PRECISE) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) sin_cos(phi[e] + phi_t[e], &sn[e], &cs[e], true);
+  } else {
+#pragma unroll
+    for (int e = 0; e < C; ++e) sin_cos(phi[e] + phi_t[e], &sn[e], &cs[e], false);
+  }
+#pragma unroll
+  for (int e = 0; e < C; ++e)
+    u[e] = {a[e] * (u[e].re * cs[e] - u[e].im * sn[e]),
+            a[e] * (u[e].re * sn[e] + u[e].im * cs[e])};
+}
+
+// Adjoint of the screen at C points (see screen_adjoint): lam holds the
+// cotangents of the screened values and is overwritten with those of V;
+// the ansatz gradient terms are added to gth[8] point by point in order.
+// has_plane: a turbulence plane phi_t is applied at this step.
+template <typename R, int C>
+__device__ __forceinline__ void screen_adjoint_n(const ScreenConst<R>& s, const cx<R>* v,
+                                                 cx<R>* lam, const R* phi_t, bool has_plane,
+                                                 double* gth) {
+  const unsigned tm = s.terms;
+  const bool precise = (tm & T_PRECISE) != 0;
+  if (has_plane) {  // lam <- conj(T) lam
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      R sn, cs;
+      sin_cos(phi_t[e], &sn, &cs, precise);
+      lam[e] = {lam[e].re * cs + lam[e].im * sn, lam[e].im * cs - lam[e].re * sn};
+    }
+  }
+  R x[C], log_a[C], phi[C], dla[C], dphi[C];
+#pragma unroll
+  for (int e = 0; e < C; ++e) {
+    x[e] = v[e].re * v[e].re + v[e].im * v[e].im;
+    log_a[e] = phi[e] = dla[e] = dphi[e] = R(0);
+  }
+  R xk1[C], xk2[C];
+  if (tm & (T_MPA | T_PLASMA)) {
+    ipow_n<R, C>(x, s.K - 2, xk2);
+#pragma unroll
+    for (int e = 0; e < C; ++e) xk1[e] = xk2[e] * x[e];
+  }
+  if (tm & T_KERR) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      phi[e] += s.cK * x[e];
+      dphi[e] += s.cK;
+    }
+  }
+  if (tm & T_PLASMA) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const R id = rcp(R(1) + xk1[e]);
+      const R sat = R(1) - id;
+      phi[e] -= s.cK * x[e] * sat;
+      dphi[e] -= s.cK * sat * (R(s.K) * id + sat);
+    }
+  }
+  if (tm & T_MPA) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const R q = R(1) + s.cM * xk1[e];
+      log_a[e] -= fast_log2(q) * (R(0.69314718055994530942) * s.inv2k1);
+      dla[e] -= s.cM * xk2[e] * R(0.5) * rcp(q);
+    }
+  }
+  const bool ansatz = (tm & T_ANSATZ) != 0;
+  R inv_a[C];
+  if (ansatz) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const R xe = x[e], x2 = xe * xe, x3 = x2 * xe, x4 = x2 * x2;
+      const R inv = rcp(R(1) + x4);
+      inv_a[e] = inv;
+      const R gre = s.th[0] * xe + s.th[1] * x2 + s.th[2] * x3 + s.th[3] * x4;
+      const R gim = s.th[4] * xe + s.th[5] * x2 + s.th[6] * x3 + s.th[7] * x4;
+      const R dgre = s.th[0] + R(2) * s.th[1] * xe + R(3) * s.th[2] * x2 + R(4) * s.th[3] * x3;
+      const R dgim = s.th[4] + R(2) * s.th[5] * xe + R(3) * s.th[6] * x2 + R(4) * s.th[7] * x3;
+      const R d4 = R(4) * x3 * inv;
+      const R re = gre * inv, im = gim * inv;
+      phi[e] += s.cK * re;
+      log_a[e] -= s.cK * im;
+      dphi[e] += s.cK * (dgre * inv - re * d4);
+      dla[e] -= s.cK * (dgim * inv - im * d4);
+    }
+  }
+  R sn[C], cs[C];
+  if (precise) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) sin_cos(phi[e], &sn[e], &cs[e], true);
+  } else {
+#pragma unroll
+    for (int e = 0; e < C; ++e) sin_cos(phi[e], &sn[e], &cs[e], false);
+  }
+#pragma unroll
+  for (int e = 0; e < C; ++e) {
+    const R a = (log_a[e] == R(0)) ? R(1) : fast_exp2(log_a[e] * R(1.44269504088896340736));
+    const cx<R> ee = {a * cs[e], a * sn[e]};
+    // 1 + x conj(g), g = dla + i dphi
+    const cx<R> one_xg = {R(1) + x[e] * dla[e], -x[e] * dphi[e]};
+    const cx<R> t1 = cmul(cmulc(lam[e], ee), one_xg);
+    const cx<R> v2 = {v[e].re * v[e].re - v[e].im * v[e].im, R(2) * v[e].re * v[e].im};
+    const cx<R> eg = cmul(ee, cx<R>{dla[e], dphi[e]});
+    const cx<R> t2 = cmul(cmul(conjg(lam[e]), v2), eg);
+    if (ansatz) {
+      const R xe = x[e], x2 = xe * xe, x3 = x2 * xe, x4 = x2 * x2;
+      const R inv = inv_a[e];
+      const R bx[4] = {xe * inv, x2 * inv, x3 * inv, x4 * inv};
+      const cx<R> w = cmul(v[e], ee);
+      const R q_re = lam[e].re * w.re + lam[e].im * w.im;
+      const R q_im = lam[e].re * w.im - lam[e].im * w.re;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        gth[p] += -double(s.cK) * double(q_im) * double(bx[p]);
+        gth[4 + p] += -double(s.cK) * double(q_re) * double(bx[p]);
+      }
+    }
+    lam[e] = t1 + t2;
+  }
+}
+
 }  // namespace ssfm
