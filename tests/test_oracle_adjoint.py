@@ -103,6 +103,32 @@ def test_gradient_matches_finite_differences(with_turb):
         assert abs(fd - an) <= 1e-6 * abs(fd)
 
 
+@pytest.mark.parametrize("with_turb", [False, True])
+def test_gradient_taylor_remainder_is_second_order(with_turb):
+    """Taylor test along a joint random direction d = (dU0, dtheta):
+    r(h) = |L(x + h d) - L(x) - h <grad L, d>| falls 4x per halving of h
+    (the first-order term is exact), while with a gradient 10 % off it falls
+    only 2x (an O(h) remainder survives), so the test discriminates."""
+    inst, u0, target, screens = _case(W.KPM | W.TERM_ANSATZ, with_turb)
+    loss, g_u0, g_th = M.gradient(u0, inst, screens=screens, cotangent=_loss_fn(target))
+    th0 = np.array(inst.theta)
+    rng = np.random.default_rng(21)
+    du = (rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape)) * np.abs(u0).max()
+    dth = rng.standard_normal(8) * np.maximum(1.0, np.abs(th0))
+
+    def f(h):
+        r = M.march(u0 + h * du, inst, theta=th0 + h * dth, screens=screens)
+        return M.fluence_loss(r.field, target)[0]
+
+    slope = _ip(g_u0, du) + float(g_th @ dth)
+    hs = [1e-3 / 2 ** k for k in range(4)]
+    fs = [f(h) for h in hs]
+    for scale, lo, hi in ((1.0, 3.6, 4.4), (1.1, 1.8, 2.5)):
+        r = [abs(fh - loss - h * slope * scale) for fh, h in zip(fs, hs)]
+        ratios = [r[k] / r[k + 1] for k in range(len(r) - 1)]
+        assert all(lo < q < hi for q in ratios), (scale, ratios)
+
+
 def _torch_forward(u0, inst, theta, screens, target):
     """Independent float64 torch version of the same discrete map."""
     n = inst.n
