@@ -114,6 +114,7 @@ def run_gpu(args):
             pw, pk = p.diag(0, z_steps)
             fl = p.intensity(0)
             out["parity"] = parity_vs_stored(inst, pw, pk, fl, p.field(0))
+            out["diagnostics"] = time_diagnostics(p, inst, args)
             # each pass alone, 200 back-to-back launches (the tuner's timing)
             ms_row, ms_col, b_row, b_col = p.time_passes(reps=200)
             out["passes"] = {"ms_row": ms_row, "ms_col": ms_col,
@@ -152,6 +153,36 @@ def run_batched(args):
     p.close()
     return {"s_per_step": t, "value": gp / t, "ms_row": ms_row, "ms_col": ms_col,
             "samples": n_samp, "bytes_pass": b_row}
+
+
+def time_diagnostics(p, inst, args):
+    """The paper's beam diagnostics on the end fluence of the march: hot-area
+    count (4-connected regions above 1 % of the peak, periodic window) and
+    the energy moment Q(1, 1), per call including the host read-back; the
+    oracle's count on the same FP64 array beside it."""
+    w = p.intensity(0, device=True)
+    thr = 0.01 * float(w.max())
+    reps = max(5, args.steps)
+    count = p.hot_areas(w, thr)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p.hot_areas(w, thr)
+    t_hot = (time.perf_counter() - t0) / reps
+    p.moment(w, inst.length, 1.0, 1)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p.moment(w, inst.length, 1.0, 1)
+    t_mom = (time.perf_counter() - t0) / reps
+    out = {"grid": inst.n, "threshold_of_peak": 0.01, "hot_areas": count,
+           "hot_areas_us": t_hot * 1e6, "moment_us": t_mom * 1e6}
+    if not args.no_cpu:
+        from oracle import diagnostics as D
+        wh = w.cpu().numpy()
+        t0 = time.perf_counter()
+        want = D.hot_area_count(wh, thr)
+        out["cpu_oracle_hot_areas_us"] = (time.perf_counter() - t0) * 1e6
+        out["matches_oracle"] = bool(want == count)
+    return out
 
 
 def measured_copy_peak(gib=4):
@@ -320,6 +351,7 @@ def main():
         "tile_variants": {"fp32": [g["tune_fp32"]["row"], g["tune_fp32"]["col"]],
                           "fp64": [g["tune_fp64"]["row"], g["tune_fp64"]["col"]]},
         "parity": g["parity"],
+        "diagnostics": g["diagnostics"],
     }
     if not args.no_batched:
         bt = run_batched(args)

@@ -197,6 +197,27 @@ int ssfm_get_grad_theta(ssfm_ctx* ctx, int32_t inst, double* g);
 int ssfm_block_mean(ssfm_ctx* ctx, const double* src, int32_t n, int32_t b,
                     double* dst);
 
+/* Hot areas (Results, multiple filamentation and the turbulent path: a hot
+ * area is a closed region of the fluence where w >= w_p; N_ha is their
+ * number).  Counts the 4-connected regions of w >= threshold in the n x n
+ * FP64 array w [W/m^2, row-major, device memory, e.g. from
+ * ssfm_get_intensity]; with periodic != 0 a region continues across the
+ * window edge (the march's grid is periodic).  n must not exceed the
+ * context's largest grid (the labels use its staging buffer).  Enqueued on
+ * the context's stream and synchronises; *count on the host.  SSFM_EHIP if
+ * the labelling's bounded union loop hit its cap (not expected). */
+int ssfm_hot_areas(ssfm_ctx* ctx, const double* w, int32_t n, double threshold,
+                   int32_t periodic, int64_t* count);
+
+/* Spatial moment of a fluence (Eq. (8) family, read as Q(p, m) = sum over
+ * the cell-centred grid of w^p (x^2 + y^2)^m dx^2, dx = length / n,
+ * x_j = (j + 1/2 - n/2) dx): w is n x n FP64 in device memory, p any
+ * finite exponent (p = 2m the printed form, p = 1 the energy moments),
+ * m >= 0.  FP64 block partial sums added on the host in block order
+ * (deterministic); synchronises; *q on the host. */
+int ssfm_moment(ssfm_ctx* ctx, const double* w, int32_t n, double length, double p,
+                int32_t m, double* q);
+
 /* FP32 screens evaluate sin/cos with the hardware v_sin/v_cos instructions
  * after an exact-to-rounding reduction to [-1/2, 1/2] revolutions (0,
  * default) or with the device math library's sincosf (1).  No effect on

@@ -71,6 +71,10 @@ _SIGS = {
     "ssfm_select_plan": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
     "ssfm_time_passes": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
                                    POINTER(c_double), POINTER(c_double)]),
+    "ssfm_hot_areas": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_int32,
+                                 POINTER(c_int64)]),
+    "ssfm_moment": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_double, c_int32,
+                              POINTER(c_double)]),
     "ssfm_set_pass_timing": (c_int32, [c_void_p, c_int32]),
     "ssfm_pass_times": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double),
                                   POINTER(c_int32)]),

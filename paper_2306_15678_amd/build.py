@@ -47,7 +47,8 @@ def build(verbose: bool = False, force: bool = True) -> str:
             return LIB
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
-    units = ["kernels", "pass_row_f32", "pass_row_f64", "pass_col_f32", "pass_col_f64"]
+    units = ["kernels", "diagnostics", "pass_row_f32", "pass_row_f64", "pass_col_f32",
+             "pass_col_f64"]
     jobs = [[hipcc, f"--offload-arch={ARCH}", *COMMON, *DEVICE, "-c",
              os.path.join(CSRC, u + ".hip"), "-o", os.path.join(BUILD, u + ".o")] for u in units]
     jobs.append([hipcc, f"--offload-arch={ARCH}", *COMMON, "-Wall", "-c",

@@ -118,6 +118,14 @@ hipError_t launch_screen_to_f64(const R* plane, int64_t n_elem, double* dst,
 
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 
+// Hot-area labelling of an n x n FP64 array (labels: n^2 ints, overflow:
+// one int set if a union exceeded its retry cap) and the root count as
+// n_part per-block partial sums; spatial moment partial sums.
+hipError_t launch_hot_areas(const double* w, int n, double threshold, int periodic, int* labels,
+                            int* overflow, double* part, int n_part, hipStream_t s);
+hipError_t launch_moment(const double* w, int n, double dx, double p, int m, double* part,
+                         int n_part, hipStream_t s);
+
 hipError_t launch_block_mean(const double* src, int n, int b, double* dst,
                              hipStream_t s);
 

@@ -1345,6 +1345,52 @@ int ssfm_time_passes(ssfm_ctx* c, int32_t reps, double* ms_row, double* ms_col,
   return r;
 }
 
+int ssfm_hot_areas(ssfm_ctx* c, const double* w, int32_t n, double threshold, int32_t periodic,
+                   int64_t* count) {
+  if (int r = check_ctx(c)) return r;
+  if (!w || !count) return fail(SSFM_EINVAL, "w/count is NULL");
+  if (n < 1 || n > c->L.max_n)
+    return fail(SSFM_EINVAL, "n=%d must be in [1, %d] (the context's largest grid)", n,
+                c->L.max_n);
+  if (!std::isfinite(threshold)) return fail(SSFM_EINVAL, "threshold must be finite");
+  // labels (n^2 ints) and the overflow flag live in the staging buffer
+  int* labels = c->at<int>(c->L.stage);
+  int* overflow = labels + int64_t(n) * n;
+  double* part = c->at<double>(c->L.sumsq_part);
+  constexpr int kParts = 256;
+  HIP_TRY(launch_hot_areas(w, n, threshold, periodic ? 1 : 0, labels, overflow, part, kParts,
+                           c->stream));
+  double host[kParts];
+  int ovf = 0;
+  HIP_TRY(hipMemcpyAsync(host, part, sizeof(host), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(&ovf, overflow, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (ovf) return fail(SSFM_EHIP, "hot-area labelling: a union exceeded its retry cap");
+  double total = 0.0;
+  for (int k = 0; k < kParts; ++k) total += host[k];
+  *count = int64_t(total);
+  return SSFM_OK;
+}
+
+int ssfm_moment(ssfm_ctx* c, const double* w, int32_t n, double length, double p, int32_t m,
+                double* q) {
+  if (int r = check_ctx(c)) return r;
+  if (!w || !q) return fail(SSFM_EINVAL, "w/q is NULL");
+  if (n < 1 || !(length > 0.0) || m < 0 || !std::isfinite(p))
+    return fail(SSFM_EINVAL, "need n >= 1, length > 0, m >= 0, finite p");
+  double* part = c->at<double>(c->L.sumsq_part);
+  constexpr int kParts = 256;
+  const double dx = length / n;
+  HIP_TRY(launch_moment(w, n, dx, p, m, part, kParts, c->stream));
+  double host[kParts];
+  HIP_TRY(hipMemcpyAsync(host, part, sizeof(host), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double total = 0.0;
+  for (int k = 0; k < kParts; ++k) total += host[k];
+  *q = total * dx * dx;
+  return SSFM_OK;
+}
+
 int ssfm_set_pass_timing(ssfm_ctx* c, int32_t every) {
   if (int r = check_ctx(c)) return r;
   if (every < 0) return fail(SSFM_EINVAL, "every must be >= 0");

@@ -198,6 +198,23 @@ class Propagator:
         L.call("ssfm_time_passes", self.ctx, reps, *[ctypes.byref(v) for v in vals])
         return tuple(v.value for v in vals)
 
+    def hot_areas(self, w: torch.Tensor, threshold: float, periodic: bool = True) -> int:
+        """Number of hot areas: 4-connected regions with w >= threshold
+        [W/m^2] of an n x n float64 fluence on this device."""
+        w = w.to(device=self.device, dtype=torch.float64).contiguous()
+        out = ctypes.c_int64()
+        L.call("ssfm_hot_areas", self.ctx, ctypes.c_void_p(w.data_ptr()), w.shape[0],
+               float(threshold), 1 if periodic else 0, ctypes.byref(out))
+        return out.value
+
+    def moment(self, w: torch.Tensor, length: float, p: float, m: int) -> float:
+        """Q(p, m) = sum w^p (x^2 + y^2)^m dx^2 of an n x n float64 fluence."""
+        w = w.to(device=self.device, dtype=torch.float64).contiguous()
+        out = ctypes.c_double()
+        L.call("ssfm_moment", self.ctx, ctypes.c_void_p(w.data_ptr()), w.shape[0],
+               float(length), float(p), int(m), ctypes.byref(out))
+        return out.value
+
     def set_pass_timing(self, every: int) -> None:
         """Sample the row/column pass durations every ``every`` steps of each
         forward march (0: off)."""
@@ -216,6 +233,21 @@ class Propagator:
         L.call("ssfm_block_mean", self.ctx, ctypes.c_void_p(src.data_ptr()), n, b,
                ctypes.c_void_p(out.data_ptr()))
         return out
+
+
+def hot_area_trace(prop: "Propagator", i: int, n_steps: int, every: int,
+                   threshold: float, periodic: bool = True) -> List[int]:
+    """N_ha along the optical path: march instance i's context n_steps steps
+    from its current state, counting hot areas (w >= threshold) every
+    `every` steps (all instances of the context advance together)."""
+    counts = []
+    done = 0
+    while done < n_steps:
+        k = min(every, n_steps - done)
+        prop.propagate(k)
+        done += k
+        counts.append(prop.hot_areas(prop.intensity(i, device=True), threshold, periodic))
+    return counts
 
 
 def workspace_bytes(descs: Sequence[L.InstanceDesc], precision: int, max_steps: int,

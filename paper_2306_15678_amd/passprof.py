@@ -17,22 +17,26 @@ line per phase; ``--out`` writes the layout as JSON.
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
 import sys
 
 
+# The sources the row and column pass kernels are compiled from.
+PASS_SOURCES = ("fft_core.hpp", "plans.hpp", "screen.hpp", "internal.hpp", "kernels.hpp",
+                "pass_kernels.hpp", "pass_row_f32.hip", "pass_row_f64.hip",
+                "pass_col_f32.hip", "pass_col_f64.hip")
+
+
 def kernel_source_hash() -> str:
-    """SHA-256 over the device sources (csrc/*.hpp, csrc/*.hip): a byte
-    counter taken on one hash describes the kernels of that hash only."""
+    """SHA-256 over the pass kernels' sources: a byte counter taken on one
+    hash describes the pass kernels of that hash only."""
     h = hashlib.sha256()
     here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-    for path in sorted(glob.glob(os.path.join(here, "*.hpp")) +
-                       glob.glob(os.path.join(here, "*.hip"))):
-        h.update(os.path.basename(path).encode())
-        with open(path, "rb") as f:
+    for name in PASS_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(here, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
