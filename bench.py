@@ -157,9 +157,10 @@ def run_batched(args):
 
 def time_diagnostics(p, inst, args):
     """The paper's beam diagnostics on the end fluence of the march: hot-area
-    count (4-connected regions above 1 % of the peak, periodic window) and
-    the energy moment Q(1, 1), per call including the host read-back; the
-    oracle's count on the same FP64 array beside it."""
+    count (4-connected regions above 1 % of the peak, periodic window), the
+    energy moment Q(1, 1) and one effective-lens screen, per call including
+    the host synchronisation; the oracle's count on the same FP64 array
+    beside it."""
     w = p.intensity(0, device=True)
     thr = 0.01 * float(w.max())
     reps = max(5, args.steps)
@@ -173,8 +174,21 @@ def time_diagnostics(p, inst, args):
     for _ in range(reps):
         p.moment(w, inst.length, 1.0, 1)
     t_mom = (time.perf_counter() - t0) / reps
+    # effective-lens screen (filter through the pass kernels + pointwise
+    # lens), scaled to this fluence; it changes the field, so it runs last
+    from paper_2306_15678_amd.march import make_lens
+    peak = float(w.max())
+    dx = inst.length / inst.n
+    c2 = (0.3e-3) ** 3
+    lens = make_lens(4 * dx * dx, 0.2 * peak, -2.0 * peak / c2, c2,
+                     [(0.28e-3, 0.7, 2.0e4, 0.0)], [(0.28e-3, 0.05, 1.0e4, 0.0)])
+    p.apply_lens(0, lens)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p.apply_lens(0, lens)
+    t_lens = (time.perf_counter() - t0) / reps
     out = {"grid": inst.n, "threshold_of_peak": 0.01, "hot_areas": count,
-           "hot_areas_us": t_hot * 1e6, "moment_us": t_mom * 1e6}
+           "hot_areas_us": t_hot * 1e6, "moment_us": t_mom * 1e6, "lens_us": t_lens * 1e6}
     if not args.no_cpu:
         from oracle import diagnostics as D
         wh = w.cpu().numpy()

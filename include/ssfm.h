@@ -197,6 +197,31 @@ int ssfm_get_grad_theta(ssfm_ctx* ctx, int32_t inst, double* g);
 int ssfm_block_mean(ssfm_ctx* ctx, const double* src, int32_t n, int32_t b,
                     double* dst);
 
+/* Effective-lens screen D_f (Math and Equations, Eq. (4)-(6)).  Applied to
+ * the current field U of one instance (its pending screen applied first):
+ *   w_dif = F^-1[exp(-l_dif k^2) F |U|^2]                       (Eq. (4))
+ *   where w_dif >= w_l (the trimmed lens field):
+ *     r = cbrt(w_dif / c1 + c2), clamped at 0  (inverse of the cubic lens
+ *         field w_lens = c1 (r^3 - c2), Eq. (5))
+ *     f = sum_j a_j cos(omega_j r + psi_j) on [r_{j-1}, r_j), r_0 = 0,
+ *         + i (the same with the imaginary segments)         (Eq. (6))
+ *     U <- U exp(i f) = U exp(-Im f) exp(i Re f)
+ * Segment rows are {r_j [m], amplitude, frequency [1/m], phase}, with
+ * increasing r_j; f = 0 beyond the last one.  The filter runs through the
+ * row and column pass kernels (the filter table in place of the
+ * propagator), the rest pointwise in FP64.  Ends the recorded march
+ * (backward needs a new ssfm_forward_record).  Synchronises. */
+typedef struct {
+  double l_dif;       /* [m^2] Fourier filter of Eq. (4), >= 0 */
+  double w_l;         /* [W/m^2] trimming level */
+  double c1, c2;      /* cubic lens field w = c1 (r^3 - c2): [W/m^5], [m^3]; c1 != 0 */
+  int32_t n_re, n_im; /* segments of the real / imaginary profile, 0..8 */
+  double re[8][4];    /* {r_j, a_j, omega_j, psi_j} */
+  double im[8][4];    /* {r_l, b_l, nu_l, eta_l} */
+} ssfm_lens;
+
+int ssfm_apply_lens(ssfm_ctx* ctx, int32_t inst, const ssfm_lens* lens);
+
 /* Hot areas (Results, multiple filamentation and the turbulent path: a hot
  * area is a closed region of the fluence where w >= w_p; N_ha is their
  * number).  Counts the 4-connected regions of w >= threshold in the n x n

@@ -37,6 +37,13 @@ class SsfmError(RuntimeError):
         self.status = status
 
 
+class LensParams(ctypes.Structure):
+    """Mirror of ssfm_lens (effective-lens screen parameters, SI)."""
+    _fields_ = [("l_dif", c_double), ("w_l", c_double), ("c1", c_double), ("c2", c_double),
+                ("n_re", c_int32), ("n_im", c_int32),
+                ("re", (c_double * 4) * 8), ("im", (c_double * 4) * 8)]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -71,6 +78,7 @@ _SIGS = {
     "ssfm_select_plan": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
     "ssfm_time_passes": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
                                    POINTER(c_double), POINTER(c_double)]),
+    "ssfm_apply_lens": (c_int32, [c_void_p, c_int32, POINTER(LensParams)]),
     "ssfm_hot_areas": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_int32,
                                  POINTER(c_int64)]),
     "ssfm_moment": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_double, c_int32,

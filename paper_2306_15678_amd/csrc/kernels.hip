@@ -193,6 +193,62 @@ template hipError_t launch_seed<double>(int, const void*, const InstDev*, int, i
                                         const double*, const double*, double, void*, double*,
                                         double*, int, hipStream_t);
 
+// ---------------------------------------------------- effective lens
+template <typename R>
+__global__ void k_lens_prep(const cx<R>* __restrict__ s, cx<R>* __restrict__ wk, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const cx<R> v = s[i];
+    wk[i] = cx<R>{v.re * v.re + v.im * v.im, R(0)};
+  }
+}
+
+__device__ __forceinline__ double lens_profile(double r, const double (*seg)[4], int n) {
+  double lo = 0.0;
+  for (int j = 0; j < n; ++j) {
+    if (r >= lo && r < seg[j][0]) return seg[j][1] * cos(seg[j][2] * r + seg[j][3]);
+    lo = seg[j][0];
+  }
+  return 0.0;
+}
+
+template <typename R>
+__global__ void k_lens_apply(cx<R>* __restrict__ u, const cx<R>* __restrict__ wd, int64_t n2,
+                             LensDev p) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n2;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double w_dif = double(wd[i].re) * p.i_ref;
+    if (!(w_dif >= p.w_l)) continue;
+    const double r = cbrt(fmax(w_dif / p.c1 + p.c2, 0.0));
+    const double f_re = lens_profile(r, p.re, p.n_re);
+    const double f_im = lens_profile(r, p.im, p.n_im);
+    const double a = exp(-f_im);
+    const double c = a * cos(f_re), sn = a * sin(f_re);
+    const double ur = double(u[i].re), ui = double(u[i].im);
+    u[i] = cx<R>{R(ur * c - ui * sn), R(ur * sn + ui * c)};
+  }
+}
+
+template <typename R>
+hipError_t launch_lens_prep(const void* s, void* wk, int64_t n_elem, hipStream_t st) {
+  hipLaunchKernelGGL((k_lens_prep<R>), dim3(grid_for(n_elem, 256)), dim3(256), 0, st,
+                     static_cast<const cx<R>*>(s), static_cast<cx<R>*>(wk), n_elem);
+  return hipGetLastError();
+}
+template <typename R>
+hipError_t launch_lens_apply(void* u, const void* wdif, int64_t n2, const LensDev& p,
+                             hipStream_t st) {
+  hipLaunchKernelGGL((k_lens_apply<R>), dim3(grid_for(n2, 256)), dim3(256), 0, st,
+                     static_cast<cx<R>*>(u), static_cast<const cx<R>*>(wdif), n2, p);
+  return hipGetLastError();
+}
+template hipError_t launch_lens_prep<float>(const void*, void*, int64_t, hipStream_t);
+template hipError_t launch_lens_prep<double>(const void*, void*, int64_t, hipStream_t);
+template hipError_t launch_lens_apply<float>(void*, const void*, int64_t, const LensDev&,
+                                             hipStream_t);
+template hipError_t launch_lens_apply<double>(void*, const void*, int64_t, const LensDev&,
+                                              hipStream_t);
+
 template <typename R>
 __global__ void k_copy(const cx<R>* __restrict__ src, cx<R>* __restrict__ dst, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;

@@ -118,6 +118,22 @@ hipError_t launch_screen_to_f64(const R* plane, int64_t n_elem, double* dst,
 
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 
+// Effective lens: FP64 parameters of one application (SI; segments
+// {r_end, amplitude, frequency, phase}).
+struct LensDev {
+  double i_ref, w_l, c1, c2;
+  int32_t n_re, n_im;
+  double re[8][4];
+  double im[8][4];
+};
+// wk[i] = (|s[i]|^2, 0) over all n_elem points (device units).
+template <typename R>
+hipError_t launch_lens_prep(const void* s, void* wk, int64_t n_elem, hipStream_t st);
+// u[i] *= exp(i f(w_dif[i])) over one beam's n2 points where w_dif >= w_l.
+template <typename R>
+hipError_t launch_lens_apply(void* u, const void* wdif, int64_t n2, const LensDev& p,
+                             hipStream_t st);
+
 // Hot-area labelling of an n x n FP64 array (labels: n^2 ints, overflow:
 // one int set if a union exceeded its retry cap) and the root count as
 // n_part per-block partial sums; spatial moment partial sums.

@@ -88,7 +88,7 @@ int validate_desc(const ssfm_instance_desc* d, int32_t n_inst, int32_t precision
 struct Layout {
   size_t inst, steps, work, wbegin_row, wbegin_col, tables;
   size_t S, Wk, Wk2, Lam, ckpt, stack, screens, stage, diag_part, diag, theta_acc,
-      theta_out, seed_loss, seed_theta, scal, sumsq_part;
+      theta_out, seed_loss, seed_theta, scal, sumsq_part, lens_inst;
   size_t total;
   int64_t field_elems;  // sum n^2
   int64_t table_elems;
@@ -115,6 +115,7 @@ struct ssfm_ctx {
   std::vector<ssfm_instance_desc> desc;
   std::vector<InstDev> inst;
   std::vector<int64_t> screen_steps;
+  std::vector<int64_t> lens_off;  // element offset of each beam's lens filter table
   std::vector<Group> groups;
   std::vector<WorkItem> work;  // all launch entries, group by group
   std::vector<int32_t> wbegin_row, wbegin_col;
@@ -313,7 +314,7 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
       tw_done.push_back(d[b].n);
       te += d[b].n;
     }
-    te += d[b].n;  // propagator
+    te += 2 * int64_t(d[b].n);  // propagator, effective-lens filter
     if (d[b].terms & SSFM_TURB) {
       se += int64_t(d[b].n_screens) * d[b].n * d[b].n;
       nsteps += d[b].n_screens;
@@ -367,6 +368,7 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
   l.seed_theta = take(sizeof(double) * 8 * max_n * n_inst);
   l.scal = take(sizeof(double) * 16);
   l.sumsq_part = take(sizeof(double) * 256);
+  l.lens_inst = take(sizeof(InstDev) * n_inst);
   l.total = off;
   if (groups_out) *groups_out = groups;
   if (work_out) *work_out = work;
@@ -856,6 +858,7 @@ int upload_plan(ssfm_ctx* c) {
   std::map<int, int64_t> tw_off;
   std::vector<double> tmp;
   c->inst.assign(n_inst, InstDev{});
+  c->lens_off.assign(n_inst, 0);
   c->screen_steps.clear();
   int64_t foff = 0, soff = 0;
   for (int b = 0; b < n_inst; ++b) {
@@ -878,6 +881,10 @@ int upload_plan(ssfm_ctx* c) {
     in.prop_off = int64_t(blob.size() / c->el);
     propagator(d, &tmp);
     append_table<R>(&blob, tmp);
+    c->lens_off[b] = int64_t(blob.size() / c->el);
+    tmp.assign(2 * size_t(d.n), 0.0);
+    for (int m = 0; m < d.n; ++m) tmp[2 * m] = 1.0 / d.n;  // identity filter until set
+    append_table<R>(&blob, tmp);
     in.steps_off = int64_t(c->screen_steps.size());
     for (int64_t s : screen_step_list(d)) c->screen_steps.push_back(s);
     const double k0 = 2.0 * M_PI / d.wavelength;
@@ -889,6 +896,16 @@ int upload_plan(ssfm_ctx* c) {
   HIP_TRY(hipMemcpyAsync(c->ws + c->L.tables, blob.data(), blob.size(), hipMemcpyHostToDevice,
                          c->stream));
   HIP_TRY(hipMemcpyAsync(c->ws + c->L.inst, c->inst.data(), sizeof(InstDev) * n_inst,
+                         hipMemcpyHostToDevice, c->stream));
+  // the lens filter runs the pass kernels on a copy of the beam table whose
+  // propagator is the filter and whose screen is off
+  std::vector<InstDev> lens_inst = c->inst;
+  for (int b = 0; b < n_inst; ++b) {
+    lens_inst[b].prop_off = c->lens_off[b];
+    lens_inst[b].terms = 0;
+    lens_inst[b].n_screens = 0;
+  }
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.lens_inst, lens_inst.data(), sizeof(InstDev) * n_inst,
                          hipMemcpyHostToDevice, c->stream));
   if (!c->screen_steps.empty())
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.steps, c->screen_steps.data(),
@@ -907,6 +924,54 @@ int upload_plan(ssfm_ctx* c) {
   return SSFM_OK;
 }
 
+
+// Effective lens on beam b: filter |U|^2 through the pass kernels, then the
+// pointwise lens where the filtered intensity reaches the trimming level.
+template <typename R>
+int do_apply_lens(ssfm_ctx* c, int b, const ssfm_lens& l) {
+  const ssfm_instance_desc& d = c->desc[b];
+  if (int r = flush_pending<R>(c)) return r;
+  std::vector<double> tab(2 * size_t(d.n), 0.0);
+  const double dk = 2.0 * M_PI / d.length;
+  for (int m = 0; m < d.n; ++m) {
+    const int f = (m <= (d.n - 1) / 2) ? m : m - d.n;  // fftfreq order
+    const double k = dk * f;
+    tab[2 * m] = std::exp(-l.l_dif * k * k) / d.n;
+  }
+  std::vector<unsigned char> blob;
+  append_table<R>(&blob, tab);
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.tables + c->lens_off[b] * c->el, blob.data(), blob.size(),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(launch_lens_prep<R>(c->field(c->L.S), c->field(c->L.Wk), c->L.field_elems, c->stream));
+  PassArgs<R> a = base_args<R>(c);
+  a.inst = c->at<InstDev>(c->L.lens_inst);
+  a.src = c->field(c->L.Wk);
+  a.dst = c->field(c->L.Wk);
+  if (int r = run_pass<R>(c, ROW_FWD, a)) return r;
+  a.part = nullptr;
+  if (int r = run_pass<R>(c, COL_FWD, a)) return r;
+  LensDev p{};
+  p.i_ref = d.i_ref;
+  p.w_l = l.w_l;
+  p.c1 = l.c1;
+  p.c2 = l.c2;
+  p.n_re = l.n_re;
+  p.n_im = l.n_im;
+  for (int j = 0; j < 8; ++j)
+    for (int k = 0; k < 4; ++k) {
+      p.re[j][k] = l.re[j][k];
+      p.im[j][k] = l.im[j][k];
+    }
+  const int64_t off = c->inst[b].off;
+  HIP_TRY(launch_lens_apply<R>(static_cast<char*>(c->field(c->L.S)) + off * c->el,
+                               static_cast<const char*>(c->field(c->L.Wk)) + off * c->el,
+                               int64_t(d.n) * d.n, p, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));  // the filter table above is a host temporary
+  c->rec_valid = false;
+  c->seeded = false;
+  c->grads_valid = false;
+  return SSFM_OK;
+}
 
 #define SSFM_DISPATCH(ctx, fn, ...) \
   ((ctx)->precision == SSFM_FP64 ? fn<double>(__VA_ARGS__) : fn<float>(__VA_ARGS__))
@@ -1343,6 +1408,30 @@ int ssfm_time_passes(ssfm_ctx* c, int32_t reps, double* ms_row, double* ms_col,
   (void)hipEventDestroy(e1);
   (void)hipEventDestroy(e2);
   return r;
+}
+
+int ssfm_apply_lens(ssfm_ctx* c, int32_t inst, const ssfm_lens* lens) {
+  if (int r = check_inst(c, inst)) return r;
+  if (!lens) return fail(SSFM_EINVAL, "lens is NULL");
+  const ssfm_lens& l = *lens;
+  if (!(l.l_dif >= 0.0) || !std::isfinite(l.l_dif) || !std::isfinite(l.w_l) ||
+      !std::isfinite(l.c1) || l.c1 == 0.0 || !std::isfinite(l.c2))
+    return fail(SSFM_EINVAL, "lens needs finite l_dif >= 0, w_l, c2 and c1 != 0");
+  if (l.n_re < 0 || l.n_re > 8 || l.n_im < 0 || l.n_im > 8)
+    return fail(SSFM_EINVAL, "lens segment counts must be in [0, 8]");
+  for (int part = 0; part < 2; ++part) {
+    const int n = part ? l.n_im : l.n_re;
+    const double(*seg)[4] = part ? l.im : l.re;
+    double lo = 0.0;
+    for (int j = 0; j < n; ++j) {
+      for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(seg[j][k])) return fail(SSFM_EINVAL, "lens segment not finite");
+      if (!(seg[j][0] > lo))
+        return fail(SSFM_EINVAL, "lens segment radii must increase from 0");
+      lo = seg[j][0];
+    }
+  }
+  return SSFM_DISPATCH(c, do_apply_lens, c, inst, l);
 }
 
 int ssfm_hot_areas(ssfm_ctx* c, const double* w, int32_t n, double threshold, int32_t periodic,

@@ -198,6 +198,10 @@ class Propagator:
         L.call("ssfm_time_passes", self.ctx, reps, *[ctypes.byref(v) for v in vals])
         return tuple(v.value for v in vals)
 
+    def apply_lens(self, i: int, lens: L.LensParams) -> None:
+        """Apply the effective-lens screen to instance i's current field."""
+        L.call("ssfm_apply_lens", self.ctx, i, ctypes.byref(lens))
+
     def hot_areas(self, w: torch.Tensor, threshold: float, periodic: bool = True) -> int:
         """Number of hot areas: 4-connected regions with w >= threshold
         [W/m^2] of an n x n float64 fluence on this device."""
@@ -233,6 +237,46 @@ class Propagator:
         L.call("ssfm_block_mean", self.ctx, ctypes.c_void_p(src.data_ptr()), n, b,
                ctypes.c_void_p(out.data_ptr()))
         return out
+
+
+def make_lens(l_dif: float, w_l: float, c1: float, c2: float,
+              re: Sequence[Sequence[float]] = (), im: Sequence[Sequence[float]] = ()
+              ) -> L.LensParams:
+    """Effective-lens parameters: filter l_dif [m^2], trimming level w_l
+    [W/m^2], cubic lens field w = c1 (r^3 - c2), and up to 8 segments
+    (r_end [m], amplitude, frequency [1/m], phase) of the real and the
+    imaginary profile."""
+    if len(re) > 8 or len(im) > 8:
+        raise ValueError("at most 8 segments per part")
+    p = L.LensParams()
+    p.l_dif, p.w_l, p.c1, p.c2 = float(l_dif), float(w_l), float(c1), float(c2)
+    p.n_re, p.n_im = len(re), len(im)
+    for j, row in enumerate(re):
+        for k in range(4):
+            p.re[j][k] = float(row[k])
+    for j, row in enumerate(im):
+        for k in range(4):
+            p.im[j][k] = float(row[k])
+    return p
+
+
+def march_with_lens(prop: "Propagator", i: int, n_steps: int, w_pf: float,
+                    lens: L.LensParams, chunk: int = 10) -> Optional[int]:
+    """March n_steps in chunks; after the first chunk in which the peak
+    intensity of instance i reaches the pre-filamentation level w_pf
+    [W/m^2], apply the effective lens to instance i once.  Returns the step
+    count at which it was applied, or None."""
+    done, applied = 0, None
+    while done < n_steps:
+        k = min(chunk, n_steps - done)
+        prop.propagate(k)
+        done += k
+        if applied is None:
+            _, peak = prop.diag(i, k)
+            if float(np.max(peak)) >= w_pf:
+                prop.apply_lens(i, lens)
+                applied = done
+    return applied
 
 
 def hot_area_trace(prop: "Propagator", i: int, n_steps: int, every: int,

@@ -118,3 +118,31 @@ def test_checkpoint_interval_keeps_trajectory_when_it_fits():
     assert checkpoint_interval(d, 32, 2000, budget_bytes=full) == 2000
     assert checkpoint_interval(d, 32, 2000, budget_bytes=full - 1) == 45
     assert workspace_bytes(d, 32, 2000, 45) < full // 10
+
+
+def test_parameter_structs_match_the_header(tmp_path):
+    """ctypes mirrors of ssfm_instance_desc and ssfm_lens have the C layout
+    (sizes and field offsets from a program compiled against the header)."""
+    import shutil
+    import subprocess
+    from paper_2306_15678_amd import _lib as L
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    names = {"ssfm_instance_desc": L.InstanceDesc, "ssfm_lens": L.LensParams}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ssfm.h"', 'int main(void) {']
+    for cname, py in names.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        cname, what, val = line.split()
+        py = names[cname]
+        want = ctypes.sizeof(py) if what == "size" else getattr(py, what).offset
+        assert int(val) == want, line

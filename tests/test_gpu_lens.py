@@ -1,0 +1,132 @@
+"""GPU effective-lens screen against the oracle (Eq. (4)-(6)).
+
+The GPU filters |U|^2 with its separable row/column pass kernels, the
+oracle with a 2-D FFT; both then trim, invert the cubic and apply the
+piecewise-cosine profile.  FP64: the same field to rounding.  FP32: a
+profile that vanishes smoothly where it ends (as the paper's smoothness
+requirement asks), so rounding near the trim level or a segment end moves
+f by rounding only.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import lens as LN
+from paper_2306_15678_amd._lib import EINVAL, ESTATE, SsfmError
+from paper_2306_15678_amd.march import Propagator, desc_of, make_lens, march_with_lens
+
+pytestmark = pytest.mark.gpu
+
+
+def _prop(insts, precision, **kw):
+    return Propagator([desc_of(i) for i in insts], precision=precision, **kw)
+
+
+def _lens_params(inst, u, smooth):
+    """A lens scaled to the filtered intensity w_dif of u: the cubic lens
+    field reaches 2 x max(w_dif) at its centre and 0 at r = 0.3 mm, the
+    trimming level is 0.2 x max(w_dif), so every active point has r in
+    [0.238, 0.290] mm, away from the cube root's singular point r = 0."""
+    l_dif = 4 * (inst.length / inst.n) ** 2
+    peak = float(LN.filtered_intensity(np.abs(u) ** 2, inst.length, l_dif).max())
+    c2 = (0.3e-3) ** 3
+    c1 = -2.0 * peak / c2
+    w_l = 0.2 * peak
+    if smooth:
+        # one segment per part ending at r_end with cos(...) = 0 there
+        r_end = 0.28e-3
+        om, nu = 2.0e4, 1.0e4
+        re = [(r_end, 0.7, om, math.pi / 2 - om * r_end)]
+        im = [(r_end, 0.05, nu, math.pi / 2 - nu * r_end)]
+    else:
+        re = [(0.25e-3, 0.8, 1.5e4, 0.2), (0.275e-3, -0.3, 4e3, 0.0)]
+        im = [(0.26e-3, 0.1, 5e3, 0.0)]
+    return LN.Lens(l_dif, w_l, c1, c2, re, im)
+
+
+def _to_gpu(lens):
+    return make_lens(lens.l_dif, lens.w_l, lens.c1, lens.c2, lens.re, lens.im)
+
+
+@pytest.mark.parametrize("precision,smooth,tol", [(64, False, 1e-12), (64, True, 1e-12),
+                                                  (32, True, 2e-5)])
+def test_lens_matches_oracle(precision, smooth, tol):
+    inst = W.config1()[0]
+    p = _prop([inst], precision)
+    p.set_field(0, W.initial_field(inst))
+    p.propagate(100)
+    u = p.field(0)
+    lens = _lens_params(inst, u, smooth)
+    p.apply_lens(0, _to_gpu(lens))
+    got = p.field(0)
+    want = LN.apply_lens(u, inst.length, lens)
+    _, _, active = LN.lens_exponent(u, inst.length, lens)
+    err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    moved = float(np.linalg.norm(want - u) / np.linalg.norm(u))
+    print(f"lens fp{precision} smooth={smooth} err={err:.2e} lens moved the field by {moved:.2e} "
+          f"on {int(active.sum())} points", flush=True)
+    assert 0 < active.sum() < active.size and moved > 1e-3
+    assert err < tol
+    p.close()
+
+
+def test_lens_touches_only_its_instance():
+    insts = [W.config1()[0], W.config1()[0]]
+    p = _prop(insts, 32)
+    for b in range(2):
+        p.set_field(b, W.initial_field(insts[b]))
+    p.propagate(80)
+    before = [p.field(b) for b in range(2)]
+    p.apply_lens(1, _to_gpu(_lens_params(insts[1], before[1], True)))
+    assert np.array_equal(p.field(0), before[0])
+    assert not np.array_equal(p.field(1), before[1])
+    p.close()
+
+
+def test_march_with_lens_triggers_at_the_pre_filamentation_level():
+    inst = W.config1()[0]
+    u0 = W.initial_field(inst)
+    p = _prop([inst], 32)
+    p.set_field(0, u0)
+    p.propagate(60)
+    peak0 = float(p.diag(0, 60)[1].max())
+    w_pf = 2.0 * peak0
+    lens = _to_gpu(_lens_params(inst, p.field(0), True))
+    p.set_field(0, u0)
+    at = march_with_lens(p, 0, 200, w_pf, lens, chunk=20)
+    got = p.field(0)
+    # the same by hand
+    p.set_field(0, u0)
+    manual = None
+    for k in range(10):
+        p.propagate(20)
+        if manual is None and float(p.diag(0, 20)[1].max()) >= w_pf:
+            p.apply_lens(0, lens)
+            manual = 20 * (k + 1)
+    assert at == manual and at is not None
+    assert np.array_equal(got, p.field(0))
+    p.close()
+
+
+def test_lens_ends_the_recorded_march_and_rejects_bad_parameters():
+    inst = W.config1()[0]
+    p = _prop([inst], 32, max_steps=20, ckpt_every=10)
+    p.set_field(0, W.initial_field(inst))
+    p.forward_record(20)
+    lens = _lens_params(inst, p.field(0), True)
+    p.apply_lens(0, _to_gpu(lens))
+    with pytest.raises(SsfmError) as e:
+        p.set_cotangent(0, np.zeros((inst.n, inst.n), complex))
+        p.backward()
+    assert e.value.status == ESTATE
+    bad = _to_gpu(LN.Lens(lens.l_dif, lens.w_l, lens.c1, lens.c2,
+                          [(2e-4, 1, 1, 0), (1e-4, 1, 1, 0)], []))
+    with pytest.raises(SsfmError) as e:
+        p.apply_lens(0, bad)
+    assert e.value.status == EINVAL
+    with pytest.raises(SsfmError) as e:
+        p.apply_lens(0, _to_gpu(LN.Lens(-1.0, 0, -1, 0, [], [])))
+    assert e.value.status == EINVAL
+    p.close()
