@@ -244,6 +244,35 @@ def traffic_per_launch(kind, variant):
     return None
 
 
+def run_ga(args):
+    """One generation of the genetic search: 8 individuals (theta vectors)
+    of the 256^2 single-filament beam marched 500 steps as one batch, and
+    their fitness read back."""
+    import torch
+
+    import workloads as W
+    from paper_2306_15678_amd.ga import population_evaluator
+    from paper_2306_15678_amd.march import Propagator, desc_of
+    inst = W.config4_sparse()
+    pop_n = 8
+    rng = np.random.default_rng(0)
+    pop = [np.array(inst.theta) + 0.05 * rng.standard_normal(8) for _ in range(pop_n)]
+    p = Propagator([desc_of(inst)] * pop_n, precision=32)
+    ev = population_evaluator(p, W.initial_field(inst), W.synthetic_target(inst, 44), inst.n_steps)
+    ev(pop)
+    reps = max(2, args.steps // 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ev(pop)
+    t = (time.perf_counter() - t0) / reps
+    p.close()
+    gp = float(inst.n) ** 2 * inst.n_steps * pop_n
+    return {"workload": f"{pop_n} theta vectors of the 256x256 single-filament beam, Kerr+ansatz, "
+                        f"{inst.n_steps} z steps each, one batched march + fitness read-back",
+            "ms_per_generation": t * 1e3, "value": gp / t, "unit": "grid-point·steps/s"}
+
+
 def parity_vs_stored(inst, power, peak, fluence, field):
     """Compare with the oracle's samples of this workload (written by
     tests/golden/calibrate_floor.py c2); None if the fixture is absent."""
@@ -381,6 +410,8 @@ def main():
             "dominant_pass_frac_of_measured_copy":
                 bt["bytes_pass"] / (dom_ms * 1e-3) / 1e9 / copy_peak,
         }
+    if not args.no_batched:
+        line["ga_generation"] = run_ga(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

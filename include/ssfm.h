@@ -177,6 +177,14 @@ int ssfm_set_cotangent(ssfm_ctx* ctx, int32_t inst, const void* g, int32_t where
 int ssfm_fluence_loss(ssfm_ctx* ctx, int32_t inst, const void* target,
                       int32_t where, double* loss);
 
+/* The same normalised fluence mismatch as ssfm_fluence_loss for the
+ * current field of instance inst, after any march (propagate or record),
+ * without seeding the adjoint or touching a recorded march's state: for
+ * fitness evaluations (a population of beams in one context).
+ * Synchronises. */
+int ssfm_fluence_mismatch(ssfm_ctx* ctx, int32_t inst, const void* target,
+                          int32_t where, double* loss);
+
 /* Exact discrete adjoint of the recorded march back to its first step
  * (recomputing each segment from its checkpoint when M < n_steps). */
 int ssfm_backward(ssfm_ctx* ctx);

@@ -79,6 +79,8 @@ _SIGS = {
     "ssfm_time_passes": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
                                    POINTER(c_double), POINTER(c_double)]),
     "ssfm_apply_lens": (c_int32, [c_void_p, c_int32, POINTER(LensParams)]),
+    "ssfm_fluence_mismatch": (c_int32, [c_void_p, c_int32, c_void_p, c_int32,
+                                        POINTER(c_double)]),
     "ssfm_hot_areas": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_int32,
                                  POINTER(c_int64)]),
     "ssfm_moment": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_double, c_int32,

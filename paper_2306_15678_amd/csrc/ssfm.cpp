@@ -1288,6 +1288,44 @@ int ssfm_fluence_loss(ssfm_ctx* c, int32_t inst, const void* target, int32_t whe
   return SSFM_OK;
 }
 
+int ssfm_fluence_mismatch(ssfm_ctx* c, int32_t inst, const void* target, int32_t where,
+                          double* loss) {
+  if (int r = check_inst(c, inst)) return r;
+  if (!loss) return fail(SSFM_EINVAL, "loss is NULL");
+  const int n = c->desc[inst].n;
+  const double* dt;
+  if (int r = stage_in(c, target, where, 8 * size_t(n) * n, &dt)) return r;
+  // the seed kernel in loss mode, with its cotangent and gradient partials
+  // sent to scratch: the work buffer and the staging area past the target
+  double* scratch = c->at<double>(c->L.stage) + size_t(n) * n;
+  double* th = scratch;
+  double* part = scratch + 8 * size_t(n);
+  const InstDev& in = c->inst[inst];
+  const ssfm_instance_desc& d = c->desc[inst];
+  const int64_t pend = c->pending ? c->step - 1 : -1;
+  auto run = [&]<typename R>(R*) -> int {
+    HIP_TRY(launch_sumsq(dt, int64_t(n) * n, 1.0, c->at<double>(c->L.sumsq_part),
+                         c->at<double>(c->L.scal), c->stream));
+    HIP_TRY(launch_seed<R>(0, c->field(c->L.S), c->at<InstDev>(c->L.inst), inst, in.n,
+                           c->at<R>(c->L.screens), c->at<int64_t>(c->L.steps), pend, dt,
+                           c->at<double>(c->L.scal), nullptr, d.i_ref, c->field(c->L.Wk), part,
+                           th, in.n, c->stream));
+    return SSFM_OK;
+  };
+  if (int r = (c->precision == SSFM_FP64) ? run((double*)nullptr) : run((float*)nullptr))
+    return r;
+  std::vector<double> h(n);
+  double wsum = 0.0;
+  HIP_TRY(hipMemcpyAsync(h.data(), part, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(&wsum, c->ws + c->L.scal, sizeof(double), hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += h[i];
+  *loss = s / wsum;
+  return SSFM_OK;
+}
+
 int ssfm_backward(ssfm_ctx* c) {
   if (int r = check_ctx(c)) return r;
   return SSFM_DISPATCH(c, do_backward, c);

@@ -132,6 +132,15 @@ class Propagator:
             self.stream.synchronize()
         del keep
 
+    def fluence_mismatch(self, i: int, target) -> float:
+        """The fluence loss of instance i's current field, after any march,
+        without seeding the adjoint."""
+        p, w, keep = _ptr_where(target, np.float64, torch.float64)
+        out = ctypes.c_double()
+        L.call("ssfm_fluence_mismatch", self.ctx, i, p, w, ctypes.byref(out))
+        del keep
+        return out.value
+
     def fluence_loss(self, i: int, target) -> float:
         p, w, keep = _ptr_where(target, np.float64, torch.float64)
         out = ctypes.c_double()
