@@ -135,8 +135,20 @@ int ssfm_set_field(ssfm_ctx* ctx, int32_t inst, const void* src, int32_t where);
 int ssfm_set_theta(ssfm_ctx* ctx, int32_t inst, const double* theta);
 
 /* Generate every instance's turbulence phase screens on the device
- * (Philox4x32-10 white noise, Kolmogorov spectrum, inverse FFT). */
+ * (Philox4x32-10 white noise, Kolmogorov spectrum or the instance's step
+ * spectrum, inverse FFT). */
 int ssfm_gen_screens(ssfm_ctx* ctx);
+
+/* Screen spectrum of instance inst for the next ssfm_gen_screens:
+ * SSFM_SPECTRUM_KOLMOGOROV (default; Phi(f) = 0.023 r0^(-5/3) f^(-11/3) with
+ * r0 from cn2 and screen_dz, Eq. (9)), or SSFM_SPECTRUM_STEP, Eq. (10) read
+ * as a low-pass step: every Fourier mode with 0 < kappa <= kappa_h
+ * [rad/m] gets amplitude sqrt(tau) (tau [rad^2] per mode), the others 0.
+ * kx = 2 pi (m (1 / (n (L / n)))) per axis in FP64, and the band is decided
+ * as kx^2 + ky^2 <= kappa_h^2 with correctly rounded products and sums. */
+enum { SSFM_SPECTRUM_KOLMOGOROV = 0, SSFM_SPECTRUM_STEP = 1 };
+int ssfm_set_screen_spectrum(ssfm_ctx* ctx, int32_t inst, int32_t kind, double tau,
+                             double kappa_h);
 
 /* Copy screen s of instance inst [rad], float64 n*n, to host or device. */
 int ssfm_get_screen(ssfm_ctx* ctx, int32_t inst, int32_t s, void* dst,

@@ -92,10 +92,12 @@ def kolmogorov_amplitude(n: int, length: float, r0: float) -> np.ndarray:
 
 
 def step_amplitude(n: int, length: float, tau: float, k_h: float) -> np.ndarray:
-    """Eq. (10) read as a low-pass step: sqrt(tau) for 0 < kappa <= k_h."""
+    """Eq. (10) read as a low-pass step: sqrt(tau) for 0 < kappa <= k_h,
+    decided on squares (kx^2 + ky^2 <= k_h^2) so that the inclusive edge
+    rests on correctly rounded products and sums only."""
     k = 2.0 * math.pi * np.fft.fftfreq(n, d=length / n)
-    kap = np.sqrt(k[None, :] ** 2 + k[:, None] ** 2)
-    return np.where((kap > 0) & (kap <= k_h), math.sqrt(tau), 0.0)
+    kap2 = k[None, :] * k[None, :] + k[:, None] * k[:, None]
+    return np.where((kap2 > 0) & (kap2 <= k_h * k_h), math.sqrt(tau), 0.0)
 
 
 def screen_pair(n: int, length: float, amp: np.ndarray, seed: int,
@@ -106,13 +108,17 @@ def screen_pair(n: int, length: float, amp: np.ndarray, seed: int,
     return phi.real.copy(), phi.imag.copy()
 
 
-def instance_screens(inst) -> Dict[int, np.ndarray]:
-    """Kolmogorov screens of an instance keyed by the step they follow."""
+def instance_screens(inst, step_spectrum=None) -> Dict[int, np.ndarray]:
+    """Screens of an instance keyed by the step they follow: Kolmogorov, or
+    with step_spectrum = (tau, k_h) the Eq. (10) low-pass step."""
     if inst.n_screens <= 0:
         return {}
-    k0 = 2.0 * math.pi / inst.medium.wavelength
-    r0 = fried_parameter(k0, inst.cn2, inst.screen_dz)
-    amp = kolmogorov_amplitude(inst.n, inst.length, r0)
+    if step_spectrum is not None:
+        amp = step_amplitude(inst.n, inst.length, *step_spectrum)
+    else:
+        k0 = 2.0 * math.pi / inst.medium.wavelength
+        r0 = fried_parameter(k0, inst.cn2, inst.screen_dz)
+        amp = kolmogorov_amplitude(inst.n, inst.length, r0)
     steps = []
     for s in range(1, inst.n_screens + 1):
         # the step that reaches the slab mid-plane z_s (ties round up)

@@ -37,6 +37,9 @@ class SsfmError(RuntimeError):
         self.status = status
 
 
+SPECTRUM_KOLMOGOROV, SPECTRUM_STEP = 0, 1
+
+
 class LensParams(ctypes.Structure):
     """Mirror of ssfm_lens (effective-lens screen parameters, SI)."""
     _fields_ = [("l_dif", c_double), ("w_l", c_double), ("c1", c_double), ("c2", c_double),
@@ -79,6 +82,7 @@ _SIGS = {
     "ssfm_time_passes": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
                                    POINTER(c_double), POINTER(c_double)]),
     "ssfm_apply_lens": (c_int32, [c_void_p, c_int32, POINTER(LensParams)]),
+    "ssfm_set_screen_spectrum": (c_int32, [c_void_p, c_int32, c_int32, c_double, c_double]),
     "ssfm_fluence_mismatch": (c_int32, [c_void_p, c_int32, c_void_p, c_int32,
                                         POINTER(c_double)]),
     "ssfm_hot_areas": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_int32,

@@ -364,7 +364,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 // Phi(f) df^2 = amp0^2 * m^(-11/3) with m = |(signed col, signed row)|.
 template <typename R>
 __global__ void k_noise(const InstDev* inst, int b, int pair, uint32_t k0, uint32_t k1,
-                        double amp0, cx<R>* __restrict__ dst) {
+                        double amp0, int kind, double kappa_h, double freq_unit,
+                        cx<R>* __restrict__ dst) {
   const InstDev& in = inst[b];
   const int n = in.n;
   const int64_t n2 = int64_t(n) * n;
@@ -380,24 +381,37 @@ __global__ void k_noise(const InstDev* inst, int b, int pair, uint32_t k0, uint3
     sincospi(2.0 * u2, &sn, &cs);
     const int mx = (col <= n / 2) ? col : col - n;
     const int my = (row <= n / 2) ? row : row - n;
-    const double m2 = double(mx) * mx + double(my) * my;
-    const double a = (m2 > 0.0) ? amp0 * pow(m2, -11.0 / 12.0) : 0.0;
+    double a;
+    if (kind == 1) {
+      // each product and sum rounded on its own (no contraction into an
+      // fma): the same FP64 operations as the wavenumber grid
+      // 2 pi fftfreq(n, L / n), and the band edge decided on squares
+#pragma clang fp contract(off)
+      const double kx = 6.283185307179586 * (double(mx) * freq_unit);
+      const double ky = 6.283185307179586 * (double(my) * freq_unit);
+      const double kap2 = kx * kx + ky * ky;
+      a = (kap2 > 0.0 && kap2 <= kappa_h * kappa_h) ? amp0 : 0.0;
+    } else {
+      const double m2 = double(mx) * mx + double(my) * my;
+      a = (m2 > 0.0) ? amp0 * pow(m2, -11.0 / 12.0) : 0.0;
+    }
     dst[in.off + i] = {R(a * rr * cs), R(a * rr * sn)};
   }
 }
 
 template <typename R>
 hipError_t launch_noise(const InstDev* inst, int b, int n, int pair, uint64_t seed,
-                        double amp0, void* dst, hipStream_t s) {
+                        double amp0, int kind, double kappa_h, double freq_unit, void* dst,
+                        hipStream_t s) {
   hipLaunchKernelGGL((k_noise<R>), dim3(grid_for(int64_t(n) * n, 256)), dim3(256), 0, s,
                      inst, b, pair, uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32), amp0,
-                     static_cast<cx<R>*>(dst));
+                     kind, kappa_h, freq_unit, static_cast<cx<R>*>(dst));
   return hipGetLastError();
 }
-template hipError_t launch_noise<float>(const InstDev*, int, int, int, uint64_t, double, void*,
-                                        hipStream_t);
-template hipError_t launch_noise<double>(const InstDev*, int, int, int, uint64_t, double, void*,
-                                         hipStream_t);
+template hipError_t launch_noise<float>(const InstDev*, int, int, int, uint64_t, double, int,
+                                        double, double, void*, hipStream_t);
+template hipError_t launch_noise<double>(const InstDev*, int, int, int, uint64_t, double, int,
+                                         double, double, void*, hipStream_t);
 
 template <typename R>
 __global__ void k_plane_f64(const R* __restrict__ p, int64_t n, double* __restrict__ d) {

@@ -108,9 +108,12 @@ hipError_t launch_reduce_rows(const double* part, int width,
 hipError_t launch_sumsq(const double* x, int64_t n, double inv_scale,
                         double* partial, double* out, hipStream_t s);
 
+// White noise shaped by the screen spectrum: kind 0 Kolmogorov (amp0 (m^2)^(-11/12)),
+// kind 1 step (amp0 where 0 < kappa <= kappa_h, kappa = 2 pi m freq_unit per axis).
 template <typename R>
 hipError_t launch_noise(const InstDev* inst, int b, int n, int pair,
-                        uint64_t seed, double amp0, void* dst, hipStream_t s);
+                        uint64_t seed, double amp0, int kind, double kappa_h,
+                        double freq_unit, void* dst, hipStream_t s);
 
 template <typename R>
 hipError_t launch_screen_to_f64(const R* plane, int64_t n_elem, double* dst,

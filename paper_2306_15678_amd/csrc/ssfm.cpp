@@ -116,6 +116,11 @@ struct ssfm_ctx {
   std::vector<InstDev> inst;
   std::vector<int64_t> screen_steps;
   std::vector<int64_t> lens_off;  // element offset of each beam's lens filter table
+  struct Spectrum {
+    int kind = SSFM_SPECTRUM_KOLMOGOROV;
+    double tau = 0.0, kappa_h = 0.0;
+  };
+  std::vector<Spectrum> spectrum;  // per beam, for gen_screens
   std::vector<Group> groups;
   std::vector<WorkItem> work;  // all launch entries, group by group
   std::vector<int32_t> wbegin_row, wbegin_col;
@@ -825,15 +830,19 @@ int do_gen_screens(ssfm_ctx* c) {
       const ssfm_instance_desc& d = c->desc[b];
       if (!(d.terms & SSFM_TURB) || 2 * p >= d.n_screens) continue;
       const double k0 = 2.0 * M_PI / d.wavelength;
+      const ssfm_ctx::Spectrum& sp = c->spectrum[b];
       double amp0 = 0.0;
-      if (d.cn2 > 0) {
+      if (sp.kind == SSFM_SPECTRUM_STEP) {
+        amp0 = std::sqrt(sp.tau);
+      } else if (d.cn2 > 0) {
         // sqrt(Phi(f)) df with Phi(f) = 0.023 r0^(-5/3) f^(-11/3), f = m / L,
         // df = 1 / L:  amplitude = sqrt(0.023) (L / r0)^(5/6) m^(-11/6)
         const double r0 = std::pow(0.423 * k0 * k0 * d.cn2 * d.screen_dz, -0.6);
         amp0 = std::sqrt(0.023) * std::pow(d.length / r0, 5.0 / 6.0);
       }
-      HIP_TRY(launch_noise<R>(c->at<InstDev>(c->L.inst), int(b), d.n, p, d.seed, amp0,
-                              c->field(c->L.Wk), c->stream));
+      const double freq_unit = 1.0 / (d.n * (d.length / d.n));
+      HIP_TRY(launch_noise<R>(c->at<InstDev>(c->L.inst), int(b), d.n, p, d.seed, amp0, sp.kind,
+                              sp.kappa_h, freq_unit, c->field(c->L.Wk), c->stream));
     }
     PassArgs<R> a = base_args<R>(c);
     a.src = c->field(c->L.Wk);
@@ -859,6 +868,7 @@ int upload_plan(ssfm_ctx* c) {
   std::vector<double> tmp;
   c->inst.assign(n_inst, InstDev{});
   c->lens_off.assign(n_inst, 0);
+  if (c->spectrum.size() != size_t(n_inst)) c->spectrum.assign(n_inst, ssfm_ctx::Spectrum{});
   c->screen_steps.clear();
   int64_t foff = 0, soff = 0;
   for (int b = 0; b < n_inst; ++b) {
@@ -1446,6 +1456,18 @@ int ssfm_time_passes(ssfm_ctx* c, int32_t reps, double* ms_row, double* ms_col,
   (void)hipEventDestroy(e1);
   (void)hipEventDestroy(e2);
   return r;
+}
+
+int ssfm_set_screen_spectrum(ssfm_ctx* c, int32_t inst, int32_t kind, double tau,
+                             double kappa_h) {
+  if (int r = check_inst(c, inst)) return r;
+  if (kind != SSFM_SPECTRUM_KOLMOGOROV && kind != SSFM_SPECTRUM_STEP)
+    return fail(SSFM_EINVAL, "unknown spectrum kind %d", kind);
+  if (kind == SSFM_SPECTRUM_STEP &&
+      (!(tau >= 0.0) || !std::isfinite(tau) || !(kappa_h > 0.0) || !std::isfinite(kappa_h)))
+    return fail(SSFM_EINVAL, "step spectrum needs finite tau >= 0 and kappa_h > 0");
+  c->spectrum[inst] = ssfm_ctx::Spectrum{kind, tau, kappa_h};
+  return SSFM_OK;
 }
 
 int ssfm_apply_lens(ssfm_ctx* c, int32_t inst, const ssfm_lens* lens) {

@@ -207,6 +207,16 @@ class Propagator:
         L.call("ssfm_time_passes", self.ctx, reps, *[ctypes.byref(v) for v in vals])
         return tuple(v.value for v in vals)
 
+    def set_screen_spectrum(self, i: int, step: Optional[Tuple[float, float]] = None) -> None:
+        """Screen spectrum of instance i for the next gen_screens: Kolmogorov
+        (None) or the Eq. (10) low-pass step (tau [rad^2 per mode],
+        kappa_h [rad/m])."""
+        if step is None:
+            L.call("ssfm_set_screen_spectrum", self.ctx, i, L.SPECTRUM_KOLMOGOROV, 0.0, 0.0)
+        else:
+            L.call("ssfm_set_screen_spectrum", self.ctx, i, L.SPECTRUM_STEP,
+                   float(step[0]), float(step[1]))
+
     def apply_lens(self, i: int, lens: L.LensParams) -> None:
         """Apply the effective-lens screen to instance i's current field."""
         L.call("ssfm_apply_lens", self.ctx, i, ctypes.byref(lens))

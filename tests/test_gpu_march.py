@@ -790,3 +790,49 @@ def test_pass_timing_samples(graphs):
         out[every] = p.field(0)
         p.close()
     assert np.array_equal(out[0], out[10])
+
+
+# ------------------------------------------------ step-spectrum screens
+def _step_instance():
+    # 60 steps: the first screen (after step 49) acts, and the 185 P_cr beam
+    # is still far from its collapse (per-step FP64 floor 2.4e-14 here; at
+    # 120 steps its peak has grown 42x and the floor is 4e-10)
+    inst = dataclasses.replace([b for b in W.config3() if b.n == 256][0], n_steps=60)
+    val = 1.0 / (inst.n * (inst.length / inst.n))
+    k_h = 2.0 * math.pi * (5 * val)      # exactly on the |m| = 5 ring of modes
+    return inst, (4e-3, k_h)
+
+
+def test_step_spectrum_screens_match_oracle():
+    inst, step = _step_instance()
+    want = T.instance_screens(inst, step_spectrum=step)
+    p = _prop([inst], 32)
+    p.set_screen_spectrum(0, step)
+    p.gen_screens()
+    steps = sorted(want)
+    amp = T.step_amplitude(inst.n, inst.length, *step)
+    for s_idx, st in enumerate(steps[:4]):
+        got = p.screen(0, s_idx)
+        err = float(np.max(np.abs(got - want[st])) / np.max(np.abs(want[st])))
+        _report(f"step spectrum screen {s_idx}", maxrel=err)
+        assert err < 2e-6, (s_idx, err)
+    re, im = p.screen(0, 0), p.screen(0, 1)
+    spec = np.fft.fft2(re + 1j * im)
+    assert np.max(np.abs(spec[amp == 0])) < 1e-5 * np.max(np.abs(spec))
+    p.close()
+
+
+def test_step_spectrum_march_matches_oracle():
+    inst, step = _step_instance()
+    screens = T.instance_screens(inst, step_spectrum=step)
+    u0 = W.initial_field(inst)
+    ref = M.march(u0, inst, screens=screens).field
+    p = _prop([inst], 64)
+    p.set_screen_spectrum(0, step)
+    p.gen_screens()
+    p.set_field(0, u0)
+    p.propagate(inst.n_steps)
+    err = M.rel_l2(p.field(0), ref)
+    _report("step spectrum march fp64", field=err)
+    assert err < 10 * 2.4e-14  # 10x the per-step FP64 floor of this march
+    p.close()

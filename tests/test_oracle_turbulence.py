@@ -127,3 +127,23 @@ def test_screen_schedule_follows_slab_midplanes():
     tie.medium.terms = W.TERM_TURB
     assert tie.screen_steps() == [1, 4, 7]
     assert sorted(T.instance_screens(tie)) == [1, 4, 7]
+
+
+def test_step_spectrum_screens_are_band_limited():
+    """Eq. (10) low-pass step: the screens' own spectrum c amp vanishes
+    outside 0 < kappa <= k_h (to rounding), and <phi^2> = tau x (number of
+    modes in the band) for both screens of a pair."""
+    n, length, tau = 64, 0.05, 2.5e-3
+    k_h = 2 * math.pi / length * 6.5
+    amp = T.step_amplitude(n, length, tau, k_h)
+    band = amp > 0
+    assert band.sum() == sum(1 for mx in range(-32, 32) for my in range(-32, 32)
+                             if 0 < mx * mx + my * my <= 6.5 ** 2)
+    acc = []
+    for pair in range(40):
+        re, im = T.screen_pair(n, length, amp, 99, pair)
+        spec = np.fft.fft2(re + 1j * im) / (n * n)
+        assert np.max(np.abs(spec[~band])) < 1e-13 * np.max(np.abs(spec))
+        acc += [np.mean(re ** 2), np.mean(im ** 2)]
+    want = tau * band.sum()
+    assert abs(np.mean(acc) / want - 1) < 0.05
