@@ -577,6 +577,14 @@ int maybe_graph(ssfm_ctx* c, int kind, int64_t a, int64_t b, int64_t i0, int64_t
   auto key = std::make_tuple(kind, a, b, i0, i1);
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
+    // graphs are specific to their first step; a caller marching in many
+    // small chunks would grow the cache without bound, so past a limit it
+    // is emptied (after the stream drains, so no cached graph still runs)
+    constexpr size_t kMaxGraphs = 128;
+    if (c->graphs.size() >= kMaxGraphs) {
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      clear_graphs(c);
+    }
     hipStream_t cap;
     HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipStream_t saved = c->stream;
@@ -1417,10 +1425,16 @@ int ssfm_time_passes(ssfm_ctx* c, int32_t reps, double* ms_row, double* ms_col,
                      double* bytes_row, double* bytes_col) {
   if (int r = check_ctx(c)) return r;
   if (reps < 1) return fail(SSFM_EINVAL, "reps must be >= 1");
-  hipEvent_t e0, e1, e2;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  HIP_TRY(hipEventCreate(&e2));
+  // events released on every return path
+  struct Events {
+    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+    ~Events() {
+      for (auto x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  for (auto& x : ev.e) HIP_TRY(hipEventCreate(&x));
+  hipEvent_t e0 = ev.e[0], e1 = ev.e[1], e2 = ev.e[2];
   int r = SSFM_OK;
   auto body = [&]<typename R>(R*) -> int {
     PassArgs<R> a = base_args<R>(c);
@@ -1452,9 +1466,6 @@ int ssfm_time_passes(ssfm_ctx* c, int32_t reps, double* ms_row, double* ms_col,
     if (bytes_row) *bytes_row = b;
     if (bytes_col) *bytes_col = b;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipEventDestroy(e2);
   return r;
 }
 

@@ -836,3 +836,20 @@ def test_step_spectrum_march_matches_oracle():
     _report("step spectrum march fp64", field=err)
     assert err < 10 * 2.4e-14  # 10x the per-step FP64 floor of this march
     p.close()
+
+
+def test_many_small_chunks_equal_one_march():
+    """300 one-step propagates (graph mode: one captured graph per start
+    step, so the bounded graph cache is emptied on the way) give the field
+    of one 300-step propagate bitwise."""
+    inst = W.config1()[0]
+    u0 = W.initial_field(inst)
+    p = _prop([inst], 32)
+    p.set_field(0, u0)
+    p.propagate(150)
+    one = p.field(0)
+    p.set_field(0, u0)
+    for _ in range(150):
+        p.propagate(1)
+    assert np.array_equal(p.field(0), one)
+    p.close()
