@@ -839,9 +839,9 @@ def test_step_spectrum_march_matches_oracle():
 
 
 def test_many_small_chunks_equal_one_march():
-    """300 one-step propagates (graph mode: one captured graph per start
+    """150 one-step propagates (graph mode: one captured graph per start
     step, so the bounded graph cache is emptied on the way) give the field
-    of one 300-step propagate bitwise."""
+    of one 150-step propagate bitwise."""
     inst = W.config1()[0]
     u0 = W.initial_field(inst)
     p = _prop([inst], 32)
