@@ -176,11 +176,17 @@ class MarchResult:
 def march(u0: np.ndarray, inst, n_steps: Optional[int] = None,
           theta: Optional[Sequence[float]] = None,
           screens: Optional[Dict[int, np.ndarray]] = None,
-          keep_pre_screen: bool = False) -> MarchResult:
-    """Split-step march: for each step V = F^-1 P F U, U = V E(|V|^2) T."""
+          keep_pre_screen: bool = False, strang: bool = False) -> MarchResult:
+    """Split-step march: for each step V = F^-1 P F U, U = V E(|V|^2) T
+    (Lie, diffraction first).  With strang=True each step is symmetric:
+    V = F^-1 P_h F U, W = V E(|V|^2) T, U = F^-1 P_h F W with P_h the
+    half-step propagator (Strang splitting, second order in dz)."""
     n_steps = inst.n_steps if n_steps is None else n_steps
-    prop = propagator(inst.n, inst.length, inst.dz,
-                      2.0 * math.pi / inst.medium.wavelength)
+    k0 = 2.0 * math.pi / inst.medium.wavelength
+    if strang:
+        half = propagator(inst.n, inst.length, inst.dz / 2, k0)
+        return _march_strang(u0, inst, n_steps, theta, screens, half)
+    prop = propagator(inst.n, inst.length, inst.dz, k0)
     scr = Screen.of(inst, theta)
     turb = screens if (inst.medium.terms & TURB) else None
     dx2 = inst.dx ** 2
@@ -198,6 +204,23 @@ def march(u0: np.ndarray, inst, n_steps: Optional[int] = None,
         pw[n] = inten.sum() * dx2
         pk[n] = inten.max()
     return MarchResult(u, pw, pk, hist)
+
+
+def _march_strang(u0, inst, n_steps, theta, screens, half) -> MarchResult:
+    scr = Screen.of(inst, theta)
+    turb = screens if (inst.medium.terms & TURB) else None
+    dx2 = inst.dx ** 2
+    u = np.array(u0, dtype=np.complex128)
+    pw = np.empty(n_steps)
+    pk = np.empty(n_steps)
+    for n in range(n_steps):
+        v = diffract(u, half)
+        phi = turb.get(n) if turb else None
+        u = diffract(apply_screen(v, scr, phi), half)
+        inten = np.abs(u) ** 2
+        pw[n] = inten.sum() * dx2
+        pk[n] = inten.max()
+    return MarchResult(u, pw, pk, None)
 
 
 # ------------------------------------------------------------ loss, adjoint

@@ -200,6 +200,44 @@ def test_lie_splitting_is_first_order():
     assert 1.9 < r1 < 2.1 and 1.9 < r2 < 2.1
 
 
+def test_strang_splitting_is_second_order():
+    base = W.config1()[0]
+    inst = dataclasses.replace(base, n=64, sigma=0.0)
+    u0 = W.initial_field(inst)
+    lz = 200 * base.dz
+
+    def run(steps):
+        return M.march(u0, dataclasses.replace(inst, dz=lz / steps), n_steps=steps,
+                       strang=True).field
+
+    ref = run(64 * 64)
+    errs = [np.linalg.norm(run(s) - ref) for s in (64, 128, 256)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.8 < r1 < 4.2 and 3.8 < r2 < 4.2, (r1, r2)
+
+
+def test_strang_step_is_time_reversible():
+    """With a phase-only screen the Strang step is symmetric: n steps of dz
+    followed by n steps of -dz return U0 (the Lie step is not)."""
+    inst = dataclasses.replace(W.config1()[0], n=64,
+                               medium=W.Medium(terms=W.TERM_KERR | W.TERM_PLASMA))
+    u0 = W.initial_field(inst)
+    back = dataclasses.replace(inst, dz=-inst.dz)
+    fwd = M.march(u0, inst, n_steps=40, strang=True).field
+    ret = M.march(fwd, back, n_steps=40, strang=True).field
+    assert M.rel_l2(ret, u0) < 1e-12
+    lie = M.march(M.march(u0, inst, n_steps=40).field, back, n_steps=40).field
+    assert M.rel_l2(lie, u0) > 1e-6
+
+
+def test_strang_without_nonlinearity_is_the_linear_propagator():
+    inst = dataclasses.replace(W.config1()[0], n=64, medium=W.Medium(terms=0))
+    u0 = W.initial_field(inst)
+    s = M.march(u0, inst, n_steps=7, strang=True).field
+    lie = M.march(u0, inst, n_steps=7).field
+    assert M.rel_l2(s, lie) < 1e-14
+
+
 def test_virial_identity_fixes_kerr_strength():
     """Kerr-only NLS: V(z) = int r^2 |U|^2 is exactly quadratic in z,
     V(z) = (P w0^2/2) (1 + (z/z_R)^2 (1 - P/P_G)), P_G = lambda^2/(2 pi n2)
