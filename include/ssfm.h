@@ -139,6 +139,19 @@ int ssfm_set_theta(ssfm_ctx* ctx, int32_t inst, const double* theta);
  * spectrum, inverse FFT). */
 int ssfm_gen_screens(ssfm_ctx* ctx);
 
+/* Splitting of each z step.  SSFM_LIE (default): diffraction L(dz), then
+ * the screen.  SSFM_STRANG: L(dz/2), screen, L(dz/2), second order in dz
+ * (a scheme variant; the paper does not state its splitting).  A Strang
+ * context keeps V = L(dz/2) U between steps (one extra half step when a
+ * field is set, one backward half step when it is read); it marches and
+ * reads out fields, intensities, per-step diagnostics and screens, while
+ * the recorded march, its adjoint, the fluence loss and mismatch and the
+ * effective lens return SSFM_EUNSUPPORTED.  Its per-step power is exact;
+ * its per-step peak is that of L(dz/2) U.  Changing the scheme zeroes
+ * every field: call it before ssfm_set_field. */
+enum { SSFM_LIE = 0, SSFM_STRANG = 1 };
+int ssfm_set_splitting(ssfm_ctx* ctx, int32_t scheme);
+
 /* Screen spectrum of instance inst for the next ssfm_gen_screens:
  * SSFM_SPECTRUM_KOLMOGOROV (default; Phi(f) = 0.023 r0^(-5/3) f^(-11/3) with
  * r0 from cn2 and screen_dz, Eq. (9)), or SSFM_SPECTRUM_STEP, Eq. (10) read

@@ -40,7 +40,7 @@ struct PassArgs {
                               // ROW_ADJ: [n_work][8] theta accumulators
   int64_t step;               // step whose screen is pending (-1: none)
   int32_t pair;               // COL_INV: screen pair index
-  int32_t pad;
+  int32_t flags;              // COL_FWD: bit 0 = power partials without the screen's A^2
 };
 
 struct PlanInfo {

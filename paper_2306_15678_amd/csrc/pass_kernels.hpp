@@ -260,7 +260,12 @@ __global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
       R x[E], a2[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) x[e] = v[e].re * v[e].re + v[e].im * v[e].im;
-      screen_amp2_n<R, E>(sc, x, a2);
+      if (a.flags & 1) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) a2[e] = R(1);
+      } else {
+        screen_amp2_n<R, E>(sc, x, a2);
+      }
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const double xa = double(x[e]) * double(a2[e]);

@@ -88,7 +88,7 @@ int validate_desc(const ssfm_instance_desc* d, int32_t n_inst, int32_t precision
 struct Layout {
   size_t inst, steps, work, wbegin_row, wbegin_col, tables;
   size_t S, Wk, Wk2, Lam, ckpt, stack, screens, stage, diag_part, diag, theta_acc,
-      theta_out, seed_loss, seed_theta, scal, sumsq_part, lens_inst;
+      theta_out, seed_loss, seed_theta, scal, sumsq_part, lens_inst, half_inst, back_inst;
   size_t total;
   int64_t field_elems;  // sum n^2
   int64_t table_elems;
@@ -116,6 +116,10 @@ struct ssfm_ctx {
   std::vector<InstDev> inst;
   std::vector<int64_t> screen_steps;
   std::vector<int64_t> lens_off;  // element offset of each beam's lens filter table
+  // Strang splitting: the state holds V = L(dz/2) U and every step applies
+  // its own screen on load; half_off / back_off: tables of L(+-dz/2)
+  bool strang = false;
+  std::vector<int64_t> half_off, back_off;
   struct Spectrum {
     int kind = SSFM_SPECTRUM_KOLMOGOROV;
     double tau = 0.0, kappa_h = 0.0;
@@ -319,7 +323,7 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
       tw_done.push_back(d[b].n);
       te += d[b].n;
     }
-    te += 2 * int64_t(d[b].n);  // propagator, effective-lens filter
+    te += 4 * int64_t(d[b].n);  // propagator, lens filter, +/- half-step propagators
     if (d[b].terms & SSFM_TURB) {
       se += int64_t(d[b].n_screens) * d[b].n * d[b].n;
       nsteps += d[b].n_screens;
@@ -374,6 +378,8 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
   l.scal = take(sizeof(double) * 16);
   l.sumsq_part = take(sizeof(double) * 256);
   l.lens_inst = take(sizeof(InstDev) * n_inst);
+  l.half_inst = take(sizeof(InstDev) * n_inst);
+  l.back_inst = take(sizeof(InstDev) * n_inst);
   l.total = off;
   if (groups_out) *groups_out = groups;
   if (work_out) *work_out = work;
@@ -518,6 +524,7 @@ int fwd_step(ssfm_ctx* c, const void* src, void* dst, int64_t pending_step, doub
   b.src = work;
   b.dst = dst;
   b.part = part;
+  b.flags = c->strang ? 1 : 0;  // Strang: |U|^2 = |V|^2 summed as it is
   return run_pass<R>(c, COL_FWD, b, st, ts ? ts->ev.data() + 2 * ng : nullptr);
 }
 
@@ -558,7 +565,9 @@ int enqueue_propagate(ssfm_ctx* c, int64_t step0, bool pending0, int64_t i0, int
     const int64_t step = step0 + i;
     const int slot = int((i - i0) % kDiagChunk);
     double* part = c->at<double>(c->L.diag_part) + size_t(slot) * 2 * c->L.n_widx_cols;
-    const int64_t pend = (i == 0 && !pending0) ? -1 : step - 1;
+    // Lie: the screen of the previous step, pending in the state; Strang:
+    // the state is V = L(dz/2) U and this step's own screen acts first
+    const int64_t pend = c->strang ? step : ((i == 0 && !pending0) ? -1 : step - 1);
     if (int r = fwd_step<R>(c, c->field(c->L.S), c->field(c->L.S), pend, part, nullptr, nullptr,
                             ts))
       return r;
@@ -655,11 +664,24 @@ int do_propagate(ssfm_ctx* c, int64_t n) {
                       });
   if (r) return r;
   c->step += n;
-  c->pending = true;
+  c->pending = !c->strang;
   c->diag_valid = std::min<int64_t>(n, c->L.diag_cap);
   c->rec_valid = false;
   c->seeded = false;
   return SSFM_OK;
+}
+
+// Half-step diffraction L(+-dz/2) of every beam: S -> Wk through the pass
+// kernels with the half-step tables (no screen).
+template <typename R>
+int half_steps(ssfm_ctx* c, bool forward) {
+  HIP_TRY(launch_copy<R>(c->field(c->L.S), c->field(c->L.Wk), c->L.field_elems, c->stream));
+  PassArgs<R> a = base_args<R>(c);
+  a.inst = c->at<InstDev>(forward ? c->L.half_inst : c->L.back_inst);
+  a.src = c->field(c->L.Wk);
+  a.dst = c->field(c->L.Wk);
+  if (int r = run_pass<R>(c, ROW_FWD, a)) return r;
+  return run_pass<R>(c, COL_FWD, a);
 }
 
 // Apply the pending screen in place (state becomes U_n).
@@ -876,6 +898,8 @@ int upload_plan(ssfm_ctx* c) {
   std::vector<double> tmp;
   c->inst.assign(n_inst, InstDev{});
   c->lens_off.assign(n_inst, 0);
+  c->half_off.assign(n_inst, 0);
+  c->back_off.assign(n_inst, 0);
   if (c->spectrum.size() != size_t(n_inst)) c->spectrum.assign(n_inst, ssfm_ctx::Spectrum{});
   c->screen_steps.clear();
   int64_t foff = 0, soff = 0;
@@ -903,6 +927,13 @@ int upload_plan(ssfm_ctx* c) {
     tmp.assign(2 * size_t(d.n), 0.0);
     for (int m = 0; m < d.n; ++m) tmp[2 * m] = 1.0 / d.n;  // identity filter until set
     append_table<R>(&blob, tmp);
+    for (int sgn = 1; sgn >= -1; sgn -= 2) {
+      ssfm_instance_desc h = d;
+      h.dz = sgn * 0.5 * d.dz;
+      (sgn > 0 ? c->half_off : c->back_off)[b] = int64_t(blob.size() / c->el);
+      propagator(h, &tmp);
+      append_table<R>(&blob, tmp);
+    }
     in.steps_off = int64_t(c->screen_steps.size());
     for (int64_t s : screen_step_list(d)) c->screen_steps.push_back(s);
     const double k0 = 2.0 * M_PI / d.wavelength;
@@ -924,6 +955,15 @@ int upload_plan(ssfm_ctx* c) {
     lens_inst[b].n_screens = 0;
   }
   HIP_TRY(hipMemcpyAsync(c->ws + c->L.lens_inst, lens_inst.data(), sizeof(InstDev) * n_inst,
+                         hipMemcpyHostToDevice, c->stream));
+  std::vector<InstDev> half_inst = lens_inst, back_inst = lens_inst;
+  for (int b = 0; b < n_inst; ++b) {
+    half_inst[b].prop_off = c->half_off[b];
+    back_inst[b].prop_off = c->back_off[b];
+  }
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.half_inst, half_inst.data(), sizeof(InstDev) * n_inst,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.back_inst, back_inst.data(), sizeof(InstDev) * n_inst,
                          hipMemcpyHostToDevice, c->stream));
   if (!c->screen_steps.empty())
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.steps, c->screen_steps.data(),
@@ -1039,6 +1079,14 @@ int do_set_field(ssfm_ctx* c, int b, const void* src, int32_t where) {
   if (int r = stage_in(c, src, where, 16 * size_t(n) * n, &dsrc)) return r;
   HIP_TRY(launch_load_field<R>(dsrc, static_cast<char*>(c->field(c->L.S)) + c->inst[b].off * c->el,
                                int64_t(n) * n, 1.0 / std::sqrt(c->desc[b].i_ref), c->stream));
+  if (c->strang) {
+    // the state of a Strang march is V = L(dz/2) U: half a step for beam b
+    if (int r = half_steps<R>(c, true)) return r;
+    const size_t off = size_t(c->inst[b].off) * c->el;
+    HIP_TRY(launch_copy<R>(static_cast<char*>(c->field(c->L.Wk)) + off,
+                           static_cast<char*>(c->field(c->L.S)) + off, int64_t(n) * n,
+                           c->stream));
+  }
   c->step = 0;
   c->pending = false;
   c->diag_valid = 0;
@@ -1225,19 +1273,56 @@ int ssfm_propagate(ssfm_ctx* c, int64_t n_steps) {
   return SSFM_DISPATCH(c, do_propagate, c, n_steps);
 }
 
+extern "C++" {
+// Read-out of beam b: Lie applies the pending screen; Strang diffracts the
+// state V back by half a step (U = L(-dz/2) V) in the work buffer first.
+template <typename R>
+int read_out(ssfm_ctx* c, int b, void* dst, int32_t where, bool intensity) {
+  const double sc = std::sqrt(c->desc[b].i_ref);
+  if (c->strang) {
+    if (int r = half_steps<R>(c, false)) return r;
+    return store_out<R>(c, b, c->field(c->L.Wk), -1, sc, dst, where, intensity);
+  }
+  const int64_t pend = c->pending ? c->step - 1 : -1;
+  return store_out<R>(c, b, c->field(c->L.S), pend, sc, dst, where, intensity);
+}
+}  // extern "C++"
+
 int ssfm_get_field(ssfm_ctx* c, int32_t inst, void* dst, int32_t where) {
   if (int r = check_inst(c, inst)) return r;
-  const double sc = std::sqrt(c->desc[inst].i_ref);
-  const int64_t pend = c->pending ? c->step - 1 : -1;
-  return SSFM_DISPATCH(c, store_out, c, inst, c->field(c->L.S), pend, sc, dst, where, false);
+  return SSFM_DISPATCH(c, read_out, c, inst, dst, where, false);
 }
 
 int ssfm_get_intensity(ssfm_ctx* c, int32_t inst, void* dst, int32_t where) {
   if (int r = check_inst(c, inst)) return r;
-  const double sc = std::sqrt(c->desc[inst].i_ref);
-  const int64_t pend = c->pending ? c->step - 1 : -1;
-  return SSFM_DISPATCH(c, store_out, c, inst, c->field(c->L.S), pend, sc, dst, where, true);
+  return SSFM_DISPATCH(c, read_out, c, inst, dst, where, true);
 }
+
+int ssfm_set_splitting(ssfm_ctx* c, int32_t scheme) {
+  if (int r = check_ctx(c)) return r;
+  if (scheme != SSFM_LIE && scheme != SSFM_STRANG)
+    return fail(SSFM_EINVAL, "unknown splitting %d", scheme);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  clear_graphs(c);
+  c->strang = (scheme == SSFM_STRANG);
+  HIP_TRY(hipMemsetAsync(c->field(c->L.S), 0, c->el * c->L.field_elems, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->step = 0;
+  c->pending = false;
+  c->diag_valid = 0;
+  c->rec_valid = false;
+  c->seeded = false;
+  c->grads_valid = false;
+  return SSFM_OK;
+}
+
+namespace {
+int lie_only(ssfm_ctx* c, const char* what) {
+  if (c->strang)
+    return fail(SSFM_EUNSUPPORTED, "%s needs Lie splitting (Strang marches forward only)", what);
+  return SSFM_OK;
+}
+}  // namespace
 
 int ssfm_get_diag(ssfm_ctx* c, int32_t inst, double* power, double* peak, int64_t n) {
   if (int r = check_inst(c, inst)) return r;
@@ -1267,12 +1352,14 @@ int ssfm_get_diag(ssfm_ctx* c, int32_t inst, double* power, double* peak, int64_
 
 int ssfm_forward_record(ssfm_ctx* c, int64_t n_steps) {
   if (int r = check_ctx(c)) return r;
+  if (int r = lie_only(c, "forward_record")) return r;
   if (n_steps < 1) return fail(SSFM_EINVAL, "n_steps must be >= 1");
   return SSFM_DISPATCH(c, do_record, c, n_steps);
 }
 
 int ssfm_set_cotangent(ssfm_ctx* c, int32_t inst, const void* g, int32_t where) {
   if (int r = check_inst(c, inst)) return r;
+  if (int r = lie_only(c, "set_cotangent")) return r;
   if (!c->rec_valid) return fail(SSFM_ESTATE, "set_cotangent needs a preceding forward_record");
   const int n = c->desc[inst].n;
   const double* dg;
@@ -1286,6 +1373,7 @@ int ssfm_set_cotangent(ssfm_ctx* c, int32_t inst, const void* g, int32_t where) 
 
 int ssfm_fluence_loss(ssfm_ctx* c, int32_t inst, const void* target, int32_t where, double* loss) {
   if (int r = check_inst(c, inst)) return r;
+  if (int r = lie_only(c, "fluence_loss")) return r;
   if (!c->rec_valid) return fail(SSFM_ESTATE, "fluence_loss needs a preceding forward_record");
   const int n = c->desc[inst].n;
   const double* dt;
@@ -1310,6 +1398,7 @@ int ssfm_fluence_mismatch(ssfm_ctx* c, int32_t inst, const void* target, int32_t
                           double* loss) {
   if (int r = check_inst(c, inst)) return r;
   if (!loss) return fail(SSFM_EINVAL, "loss is NULL");
+  if (int r = lie_only(c, "fluence_mismatch")) return r;
   const int n = c->desc[inst].n;
   const double* dt;
   if (int r = stage_in(c, target, where, 8 * size_t(n) * n, &dt)) return r;
@@ -1346,6 +1435,7 @@ int ssfm_fluence_mismatch(ssfm_ctx* c, int32_t inst, const void* target, int32_t
 
 int ssfm_backward(ssfm_ctx* c) {
   if (int r = check_ctx(c)) return r;
+  if (int r = lie_only(c, "backward")) return r;
   return SSFM_DISPATCH(c, do_backward, c);
 }
 
@@ -1483,6 +1573,7 @@ int ssfm_set_screen_spectrum(ssfm_ctx* c, int32_t inst, int32_t kind, double tau
 
 int ssfm_apply_lens(ssfm_ctx* c, int32_t inst, const ssfm_lens* lens) {
   if (int r = check_inst(c, inst)) return r;
+  if (int r = lie_only(c, "the effective lens")) return r;
   if (!lens) return fail(SSFM_EINVAL, "lens is NULL");
   const ssfm_lens& l = *lens;
   if (!(l.l_dif >= 0.0) || !std::isfinite(l.l_dif) || !std::isfinite(l.w_l) ||

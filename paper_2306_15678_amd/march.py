@@ -207,6 +207,10 @@ class Propagator:
         L.call("ssfm_time_passes", self.ctx, reps, *[ctypes.byref(v) for v in vals])
         return tuple(v.value for v in vals)
 
+    def set_splitting(self, strang: bool) -> None:
+        """Lie (default) or Strang splitting of each step; zeroes the fields."""
+        L.call("ssfm_set_splitting", self.ctx, L.STRANG if strang else L.LIE)
+
     def set_screen_spectrum(self, i: int, step: Optional[Tuple[float, float]] = None) -> None:
         """Screen spectrum of instance i for the next gen_screens: Kolmogorov
         (None) or the Eq. (10) low-pass step (tau [rad^2 per mode],
