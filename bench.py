@@ -79,8 +79,15 @@ def run_gpu(args):
         out["ckpt_fp%d" % precision] = m
         p = Propagator(_desc_list([inst]), precision=precision, max_steps=z_steps,
                        ckpt_every=m, device=dev)
-        # pick the fastest tile variants (setup, not timed)
-        out["tune_fp%d" % precision] = tune(p, reps=30, use_cache=False)[inst.n]
+        if precision == 32 and args.variants:
+            # tile variants given on the command line (a profiled run pins the
+            # ones an unprofiled run chose: the profiler perturbs the tuner)
+            r, c = (int(v) for v in args.variants.split(","))
+            p.select_plan(inst.n, r, c)
+            out["tune_fp32"] = {"row": r, "col": c, "pinned": True}
+        else:
+            # pick the fastest tile variants (setup, not timed)
+            out["tune_fp%d" % precision] = tune(p, reps=30, use_cache=False)[inst.n]
         return p
 
     def fwd_adj(p):
@@ -334,6 +341,9 @@ def main():
                          "trajectory when it fits half the free HBM, else about sqrt(steps))")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--variants", default="",
+                    help="ROW,COL: tile variants of the 1024^2 complex64 passes instead of "
+                         "tuning them (FP32 march only)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the march of one beam or a "
