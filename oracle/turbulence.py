@@ -24,6 +24,12 @@ Two uniforms (u + 1/2) 2^-32 from output words 0 and 1 feed one Box-Muller
 transform, giving c = z0 + i z1 for that spectral sample.  One complex draw
 gives two screens: the real part (even screen index) and the imaginary part
 (odd screen index) of sum_k c_k sqrt(Phi(f_k)) df e^{2 pi i f_k.x}.
+
+An FFT screen has no power below the window's fundamental 1/L.  Optionally
+the subharmonic method (Lane, Glindemann and Dainty 1992) adds it back:
+levels p = 1..P of 8 modes on a 3 x 3 grid of spacing 1/(3^p L) around
+f = 0, each with its own Philox draw (counter word 3 = 1), summed on the
+cell-centred grid and made mean-free.
 """
 from __future__ import annotations
 
@@ -108,17 +114,74 @@ def screen_pair(n: int, length: float, amp: np.ndarray, seed: int,
     return phi.real.copy(), phi.imag.copy()
 
 
-def instance_screens(inst, step_spectrum=None) -> Dict[int, np.ndarray]:
+def kolmogorov_density(r0: float):
+    """Phase spectral density Phi(fx, fy) = 0.023 r0^(-5/3) f^(-11/3) [rad^2 m^2]."""
+    return lambda fx, fy: 0.023 * r0 ** (-5.0 / 3.0) * math.hypot(fx, fy) ** (-11.0 / 3.0)
+
+
+def step_density(length: float, tau: float, k_h: float):
+    """The Eq. (10) step as a density: tau per FFT cell of area 1/L^2, i.e.
+    tau L^2, for kappa^2 = (2 pi fx)^2 + (2 pi fy)^2 <= k_h^2."""
+    def dens(fx, fy):
+        kx, ky = 2.0 * math.pi * fx, 2.0 * math.pi * fy
+        return tau * length * length if kx * kx + ky * ky <= k_h * k_h else 0.0
+    return dens
+
+
+def subharmonic_modes(length: float, levels: int, density):
+    """Modes of the subharmonic method (Lane, Glindemann and Dainty, Waves in
+    Random Media 2 (1992) 209): at level p = 1..levels the frequency cell
+    df_p = 1/(3^p L) is split around f = 0 into a 3 x 3 grid, and each of the
+    8 outer cells is one mode f = (mx, my) df_p with amplitude
+    sqrt(density(f)) df_p.  Returns (p, q, fx, fy, a) with q = 3 (my + 1) +
+    (mx + 1) the cell's index (the centre, q = 4, is skipped)."""
+    out = []
+    for p in range(1, levels + 1):
+        df = 1.0 / (3 ** p * length)
+        for q in range(9):
+            if q == 4:
+                continue
+            mx, my = q % 3 - 1, q // 3 - 1
+            fx, fy = mx * df, my * df
+            out.append((p, q, fx, fy, math.sqrt(density(fx, fy)) * df))
+    return out
+
+
+def subharmonic_pair(n: int, length: float, modes, seed: int,
+                     pair: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Low-frequency part of screen pair `pair`: lo(x, y) = sum c a
+    exp(2 pi i (fx x + fy y)) over the modes, on the cell-centred grid, minus
+    its mean over the grid; real part for the even screen, imaginary part for
+    the odd one.  The coefficient c of mode (p, q) is one Box-Muller draw from
+    Philox counter (q, p, pair, 1) (the FFT noise uses counter word 3 = 0)."""
+    x = (np.arange(n) + 0.5 - n / 2) * (length / n)
+    lo = np.zeros((n, n), dtype=np.complex128)
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    for p, q, fx, fy, a in modes:
+        o = philox4x32_10(([q], [p], [pair], [1]), key)
+        z0, z1 = box_muller(uniform_open(o[0]), uniform_open(o[1]))
+        c = complex(z0[0], z1[0])
+        lo += c * a * np.exp(2j * math.pi * (fx * x[None, :] + fy * x[:, None]))
+    lo -= lo.mean()
+    return lo.real.copy(), lo.imag.copy()
+
+
+def instance_screens(inst, step_spectrum=None, subharmonics: int = 0) -> Dict[int, np.ndarray]:
     """Screens of an instance keyed by the step they follow: Kolmogorov, or
-    with step_spectrum = (tau, k_h) the Eq. (10) low-pass step."""
+    with step_spectrum = (tau, k_h) the Eq. (10) low-pass step; with
+    subharmonics = P the low-frequency part of P subharmonic levels of the
+    same spectrum is added to every screen."""
     if inst.n_screens <= 0:
         return {}
     if step_spectrum is not None:
         amp = step_amplitude(inst.n, inst.length, *step_spectrum)
+        dens = step_density(inst.length, *step_spectrum)
     else:
         k0 = 2.0 * math.pi / inst.medium.wavelength
         r0 = fried_parameter(k0, inst.cn2, inst.screen_dz)
         amp = kolmogorov_amplitude(inst.n, inst.length, r0)
+        dens = kolmogorov_density(r0)
+    modes = subharmonic_modes(inst.length, subharmonics, dens)
     steps = []
     for s in range(1, inst.n_screens + 1):
         # the step that reaches the slab mid-plane z_s (ties round up)
@@ -126,6 +189,9 @@ def instance_screens(inst, step_spectrum=None) -> Dict[int, np.ndarray]:
     out = {}
     for p in range((inst.n_screens + 1) // 2):
         re, im = screen_pair(inst.n, inst.length, amp, inst.seed, p)
+        if modes:
+            lre, lim = subharmonic_pair(inst.n, inst.length, modes, inst.seed, p)
+            re, im = re + lre, im + lim
         out[steps[2 * p]] = re
         if 2 * p + 1 < inst.n_screens:
             out[steps[2 * p + 1]] = im
