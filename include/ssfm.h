@@ -163,6 +163,21 @@ enum { SSFM_SPECTRUM_KOLMOGOROV = 0, SSFM_SPECTRUM_STEP = 1 };
 int ssfm_set_screen_spectrum(ssfm_ctx* ctx, int32_t inst, int32_t kind, double tau,
                              double kappa_h);
 
+/* Subharmonic levels of instance inst for the next ssfm_gen_screens (0, the
+ * default, to 8).  An FFT screen carries no power below the window's
+ * fundamental 1/L; with P levels the subharmonic method (Lane, Glindemann
+ * and Dainty 1992; the paper's spectral screen method, Eq. (9)-(10), leaves
+ * the low end to the implementation) adds, to every screen pair, the modes
+ * f = (mx, my) / (3^p L) for p = 1..P and (mx, my) in {-1, 0, 1}^2 without
+ * (0, 0), with amplitude sqrt(density(f)) / (3^p L) (density: the
+ * Kolmogorov Phi, or tau L^2 inside kappa^2 <= kappa_h^2 for the step
+ * spectrum) and coefficient c = z0 + i z1 from Philox4x32-10 counter
+ * (q, p, pair, 1), q = 3 (my + 1) + (mx + 1), key = seed; the sum over the
+ * cell-centred grid, minus its grid mean, adds its real part to screen
+ * 2 pair and its imaginary part to screen 2 pair + 1.  Kolmogorov beams with
+ * cn2 = 0 get none.  SSFM_EINVAL outside [0, 8]. */
+int ssfm_set_subharmonics(ssfm_ctx* ctx, int32_t inst, int32_t levels);
+
 /* Copy screen s of instance inst [rad], float64 n*n, to host or device. */
 int ssfm_get_screen(ssfm_ctx* ctx, int32_t inst, int32_t s, void* dst,
                     int32_t where);

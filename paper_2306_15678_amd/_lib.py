@@ -84,6 +84,7 @@ _SIGS = {
                                    POINTER(c_double), POINTER(c_double)]),
     "ssfm_apply_lens": (c_int32, [c_void_p, c_int32, POINTER(LensParams)]),
     "ssfm_set_screen_spectrum": (c_int32, [c_void_p, c_int32, c_int32, c_double, c_double]),
+    "ssfm_set_subharmonics": (c_int32, [c_void_p, c_int32, c_int32]),
     "ssfm_set_splitting": (c_int32, [c_void_p, c_int32]),
     "ssfm_fluence_mismatch": (c_int32, [c_void_p, c_int32, c_void_p, c_int32,
                                         POINTER(c_double)]),

@@ -7,6 +7,7 @@
 
 #include "kernels.hpp"
 #include "pass_kernels.hpp"
+#include "subharmonics.hpp"
 
 namespace ssfm {
 
@@ -412,6 +413,114 @@ template hipError_t launch_noise<float>(const InstDev*, int, int, int, uint64_t,
                                         double, double, void*, hipStream_t);
 template hipError_t launch_noise<double>(const InstDev*, int, int, int, uint64_t, double, int,
                                          double, double, void*, hipStream_t);
+
+// Subharmonic modes: thread t < 8 levels draws mode t (level p = t / 8 + 1,
+// cell q = the t % 8-th of the 3 x 3 cells around f = 0 without the centre,
+// (mx, my) = (q % 3 - 1, q / 3 - 1), frequency spacing df = 1 / (3^p L)) from
+// Philox counter (q, p, pair, 1) and stores w = c sqrt(density) df in LDS.
+// The grid mean of exp(2 pi i m df x) over the cell-centred grid
+// x_j = (j + 1/2 - n/2) L/n is sin(pi/3^p) / (n sin(pi/(3^p n))) for
+// |m| = 1 (1 for m = 0), so the mean of the sum is formed from the w alone.
+// Every point then adds Re / Im of sum w e^{2 pi i f.x} - mean in FP64.
+template <typename R>
+__global__ void __launch_bounds__(256) k_subharmonics(const InstDev* inst, int b, int pair,
+                                                     uint32_t k0, uint32_t k1, SubharmonicSpec sp,
+                                                     R* __restrict__ planes) {
+  constexpr int kModes = 8 * kMaxSubharmonicLevels;
+  __shared__ double wre[kModes], wim[kModes], mean[2];
+  const InstDev& in = inst[b];
+  const int n = in.n;
+  const int nm = 8 * sp.levels;
+  const int t = threadIdx.x;
+  if (t < nm) {
+    const int p = t / 8 + 1, j = t % 8, q = (j < 4) ? j : j + 1;
+    const int mx = q % 3 - 1, my = q / 3 - 1;
+    uint32_t c[4] = {uint32_t(q), uint32_t(p), uint32_t(pair), 1u};
+    philox4x32_10(c, k0, k1);
+    const double u1 = (double(c[0]) + 0.5) * 2.3283064365386962890625e-10;
+    const double u2 = (double(c[1]) + 0.5) * 2.3283064365386962890625e-10;
+    const double rr = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    double pow3 = 1.0;
+    for (int i = 0; i < p; ++i) pow3 *= 3.0;
+    const double df = 1.0 / (pow3 * sp.length);
+    double a;
+    {
+#pragma clang fp contract(off)
+      const double fx = double(mx) * df, fy = double(my) * df;
+      if (sp.kind == 1) {
+        const double kx = 6.283185307179586 * fx, ky = 6.283185307179586 * fy;
+        const double kap2 = kx * kx + ky * ky;
+        a = (kap2 <= sp.kappa_h * sp.kappa_h) ? sqrt(sp.tau * sp.length * sp.length) * df : 0.0;
+      } else {
+        a = sqrt(0.023 * pow(sp.r0, -5.0 / 3.0) * pow(hypot(fx, fy), -11.0 / 3.0)) * df;
+      }
+    }
+    wre[t] = rr * cs * a;
+    wim[t] = rr * sn * a;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double mre = 0.0, mim = 0.0;
+    for (int m = 0; m < nm; ++m) {
+      const int p = m / 8 + 1, j = m % 8, q = (j < 4) ? j : j + 1;
+      double pow3 = 1.0;
+      for (int i = 0; i < p; ++i) pow3 *= 3.0;
+      const double g = sinpi(1.0 / pow3) / (double(n) * sinpi(1.0 / (pow3 * n)));
+      const double f = ((q % 3 == 1) ? 1.0 : g) * ((q / 3 == 1) ? 1.0 : g);
+      mre += wre[m] * f;
+      mim += wim[m] * f;
+    }
+    mean[0] = mre;
+    mean[1] = mim;
+  }
+  __syncthreads();
+  const int64_t n2 = int64_t(n) * n;
+  R* pre = planes + in.screen_off + int64_t(2 * pair) * n2;
+  R* pim = pre + n2;
+  const bool has_im = 2 * pair + 1 < in.n_screens;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n2;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int row = int(i / n), col = int(i - int64_t(row) * n);
+    const double xc = double(col) + 0.5 - 0.5 * n, yc = double(row) + 0.5 - 0.5 * n;
+    double sre = 0.0, sim = 0.0, pow3 = 1.0;
+    for (int p = 0; p < sp.levels; ++p) {
+      pow3 *= 3.0;
+      double exs, exc, eys, eyc;
+      sincospi(2.0 * xc / (pow3 * n), &exs, &exc);
+      sincospi(2.0 * yc / (pow3 * n), &eys, &eyc);
+      for (int j = 0; j < 8; ++j) {
+        const int q = (j < 4) ? j : j + 1, mx = q % 3 - 1, my = q / 3 - 1;
+        // e^{i (mx ax + my ay)} from the per-axis factors
+        const double xr = exc, xi = double(mx) * exs;  // mx in {-1, 0, 1}
+        const double yr = eyc, yi = double(my) * eys;
+        const double er0 = (mx == 0) ? 1.0 : xr, ei0 = (mx == 0) ? 0.0 : xi;
+        const double er1 = (my == 0) ? 1.0 : yr, ei1 = (my == 0) ? 0.0 : yi;
+        const double er = er0 * er1 - ei0 * ei1, ei = er0 * ei1 + ei0 * er1;
+        const double wr = wre[8 * p + j], wi = wim[8 * p + j];
+        sre += wr * er - wi * ei;
+        sim += wr * ei + wi * er;
+      }
+    }
+    pre[i] = R(double(pre[i]) + (sre - mean[0]));
+    if (has_im) pim[i] = R(double(pim[i]) + (sim - mean[1]));
+  }
+}
+
+template <typename R>
+hipError_t launch_subharmonics(const InstDev* inst, int b, int n, int pair, uint64_t seed,
+                               const SubharmonicSpec& spec, void* planes, hipStream_t s) {
+  if (spec.levels < 1 || spec.levels > kMaxSubharmonicLevels) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_subharmonics<R>), dim3(grid_for(int64_t(n) * n, 256)), dim3(256), 0, s,
+                     inst, b, pair, uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32), spec,
+                     static_cast<R*>(planes));
+  return hipGetLastError();
+}
+template hipError_t launch_subharmonics<float>(const InstDev*, int, int, int, uint64_t,
+                                               const SubharmonicSpec&, void*, hipStream_t);
+template hipError_t launch_subharmonics<double>(const InstDev*, int, int, int, uint64_t,
+                                                const SubharmonicSpec&, void*, hipStream_t);
 
 template <typename R>
 __global__ void k_plane_f64(const R* __restrict__ p, int64_t n, double* __restrict__ d) {

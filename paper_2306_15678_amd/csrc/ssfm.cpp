@@ -27,6 +27,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "subharmonics.hpp"
 
 using namespace ssfm;
 
@@ -123,6 +124,7 @@ struct ssfm_ctx {
   struct Spectrum {
     int kind = SSFM_SPECTRUM_KOLMOGOROV;
     double tau = 0.0, kappa_h = 0.0;
+    int subharmonics = 0;  // subharmonic levels added to each screen
   };
   std::vector<Spectrum> spectrum;  // per beam, for gen_screens
   std::vector<Group> groups;
@@ -884,6 +886,24 @@ int do_gen_screens(ssfm_ctx* c) {
     b.planes_out = c->at<R>(c->L.screens);
     b.pair = p;
     if (int r = run_pass<R>(c, COL_INV, b)) return r;
+    // the low-frequency part below 1/L, added to the pair's planes
+    for (size_t bi = 0; bi < c->desc.size(); ++bi) {
+      const ssfm_instance_desc& d = c->desc[bi];
+      const ssfm_ctx::Spectrum& sp = c->spectrum[bi];
+      if (!(d.terms & SSFM_TURB) || 2 * p >= d.n_screens || sp.subharmonics == 0) continue;
+      if (sp.kind != SSFM_SPECTRUM_STEP && !(d.cn2 > 0)) continue;
+      SubharmonicSpec ss{};
+      ss.levels = sp.subharmonics;
+      ss.kind = sp.kind;
+      const double k0 = 2.0 * M_PI / d.wavelength;
+      ss.r0 = (sp.kind == SSFM_SPECTRUM_STEP) ? 0.0
+                                               : std::pow(0.423 * k0 * k0 * d.cn2 * d.screen_dz, -0.6);
+      ss.tau = sp.tau;
+      ss.kappa_h = sp.kappa_h;
+      ss.length = d.length;
+      HIP_TRY(launch_subharmonics<R>(c->at<InstDev>(c->L.inst), int(bi), d.n, p, d.seed, ss,
+                                     c->at<R>(c->L.screens), c->stream));
+    }
   }
   return SSFM_OK;
 }
@@ -1567,7 +1587,19 @@ int ssfm_set_screen_spectrum(ssfm_ctx* c, int32_t inst, int32_t kind, double tau
   if (kind == SSFM_SPECTRUM_STEP &&
       (!(tau >= 0.0) || !std::isfinite(tau) || !(kappa_h > 0.0) || !std::isfinite(kappa_h)))
     return fail(SSFM_EINVAL, "step spectrum needs finite tau >= 0 and kappa_h > 0");
-  c->spectrum[inst] = ssfm_ctx::Spectrum{kind, tau, kappa_h};
+  ssfm_ctx::Spectrum& sp = c->spectrum[inst];
+  sp.kind = kind;
+  sp.tau = tau;
+  sp.kappa_h = kappa_h;
+  return SSFM_OK;
+}
+
+int ssfm_set_subharmonics(ssfm_ctx* c, int32_t inst, int32_t levels) {
+  if (int r = check_inst(c, inst)) return r;
+  if (levels < 0 || levels > kMaxSubharmonicLevels)
+    return fail(SSFM_EINVAL, "subharmonic levels must be in [0, %d], got %d",
+                kMaxSubharmonicLevels, levels);
+  c->spectrum[inst].subharmonics = levels;
   return SSFM_OK;
 }
 

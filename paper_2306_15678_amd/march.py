@@ -221,6 +221,11 @@ class Propagator:
             L.call("ssfm_set_screen_spectrum", self.ctx, i, L.SPECTRUM_STEP,
                    float(step[0]), float(step[1]))
 
+    def set_subharmonics(self, i: int, levels: int) -> None:
+        """Subharmonic levels (0-8) added to instance i's screens by the next
+        gen_screens: the power below the window's fundamental 1/L."""
+        L.call("ssfm_set_subharmonics", self.ctx, i, int(levels))
+
     def apply_lens(self, i: int, lens: L.LensParams) -> None:
         """Apply the effective-lens screen to instance i's current field."""
         L.call("ssfm_apply_lens", self.ctx, i, ctypes.byref(lens))
