@@ -149,8 +149,27 @@ int ssfm_gen_screens(ssfm_ctx* ctx);
  * effective lens return SSFM_EUNSUPPORTED.  Its per-step power is exact;
  * its per-step peak is that of L(dz/2) U.  Changing the scheme zeroes
  * every field: call it before ssfm_set_field. */
-enum { SSFM_LIE = 0, SSFM_STRANG = 1 };
+enum { SSFM_LIE = 0, SSFM_STRANG = 1, SSFM_FD = 2 };
 int ssfm_set_splitting(ssfm_ctx* ctx, int32_t scheme);
+
+/* SSFM_FD selects the finite-difference reference scheme instead of the
+ * split-step march (the paper's dense reference solver for Eq. (3), a
+ * semi-implicit conservative finite-difference scheme; the scheme is not
+ * printed, the reading here is Crank-Nicolson with the nonlinearity at the
+ * step's mean intensity):
+ *   (U+ - U)/dz = (i/2k0) Lap_h Ubar + G(J) Ubar,  Ubar = (U+ + U)/2,
+ *   J = (|U+|^2 + |U|^2)/2,
+ *   G(I) = i k0 n2 [I - I_a x^K/(1 + x^(K-1))] - beta_K I^(K-1)/2, x = I/I_a,
+ * G holding the beam's Kerr, plasma and multiphoton terms, Lap_h the
+ * periodic 5-point Laplacian.  Each step solves
+ * Ubar = (1 - (i dz/4k0) Lap_h)^-1 [U + (dz/2) G(J) Ubar] by a fixed number of
+ * fixed-point iterations from Ubar = U (ssfm_set_fd_iterations, default 4;
+ * the linear solve is exact, Lap_h being diagonal in the 2-D DFT basis),
+ * then U+ = 2 Ubar - U.  Converged, a step conserves power exactly without
+ * absorption.  The per-step power and peak are those of U+.  Returns
+ * SSFM_EUNSUPPORTED when a beam has the ansatz term or turbulence screens;
+ * forward only, like Strang.  Zeroes every field. */
+int ssfm_set_fd_iterations(ssfm_ctx* ctx, int32_t iterations);  /* 1..64 */
 
 /* Screen spectrum of instance inst for the next ssfm_gen_screens:
  * SSFM_SPECTRUM_KOLMOGOROV (default; Phi(f) = 0.023 r0^(-5/3) f^(-11/3) with

@@ -38,7 +38,7 @@ class SsfmError(RuntimeError):
 
 
 SPECTRUM_KOLMOGOROV, SPECTRUM_STEP = 0, 1
-LIE, STRANG = 0, 1
+LIE, STRANG, FD = 0, 1, 2
 
 
 class LensParams(ctypes.Structure):
@@ -85,6 +85,7 @@ _SIGS = {
     "ssfm_apply_lens": (c_int32, [c_void_p, c_int32, POINTER(LensParams)]),
     "ssfm_set_screen_spectrum": (c_int32, [c_void_p, c_int32, c_int32, c_double, c_double]),
     "ssfm_set_subharmonics": (c_int32, [c_void_p, c_int32, c_int32]),
+    "ssfm_set_fd_iterations": (c_int32, [c_void_p, c_int32]),
     "ssfm_set_splitting": (c_int32, [c_void_p, c_int32]),
     "ssfm_fluence_mismatch": (c_int32, [c_void_p, c_int32, c_void_p, c_int32,
                                         POINTER(c_double)]),

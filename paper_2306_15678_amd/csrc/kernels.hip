@@ -51,7 +51,7 @@ template <typename R>
 hipError_t launch_pass(int kind, int n, int variant, int n_blocks, const PassArgs<R>& a,
                        hipStream_t s, const LaunchEv* ev) {
   if (n_blocks <= 0) return hipSuccess;
-  if (kind >= COL_FWD) return launch_col<R>(kind, n, variant, n_blocks, a, s, ev);
+  if (is_col_kind(kind)) return launch_col<R>(kind, n, variant, n_blocks, a, s, ev);
   return launch_row<R>(kind, n, variant, n_blocks, a, s, ev);
 }
 template hipError_t launch_pass<float>(int, int, int, int, const PassArgs<float>&, hipStream_t,

@@ -18,7 +18,23 @@ struct cx;
 // partials, store of the pre-screen field).  An adjoint step is COL_ADJ
 // followed by ROW_ADJ (adjoint screen of the previous step fused into the
 // epilogue).  ROW_INV / COL_INV are plain inverse DFTs for screen synthesis.
-enum PassKind { ROW_FWD = 0, ROW_ADJ = 1, ROW_INV = 2, COL_FWD = 3, COL_ADJ = 4, COL_INV = 5 };
+// ROW_FD / COL_FD are the finite-difference reference scheme's passes: COL_FD
+// applies the inverse of 1 - (i dz/4k0) Lap_h between a forward and an
+// inverse column DFT (Lap_h diagonal in the 2-D DFT basis), ROW_FD inverts
+// the row DFT, forms the next right-hand side pointwise (or finishes the
+// step) and transforms the rows again.
+enum PassKind {
+  ROW_FWD = 0, ROW_ADJ = 1, ROW_INV = 2, COL_FWD = 3, COL_ADJ = 4, COL_INV = 5,
+  ROW_FD = 6, COL_FD = 7
+};
+constexpr bool is_col_kind(int k) {
+  return k == COL_FWD || k == COL_ADJ || k == COL_INV || k == COL_FD;
+}
+
+// ROW_FD flags: the input is row-transformed (else it is U itself), the pass
+// finishes the step (U+ = 2 Ubar - U into the state, power partials), the
+// finished step is the last one of the launch sequence (no next RHS).
+enum : int32_t { FD_SPECTRAL = 2, FD_FINISH = 4, FD_LAST = 8 };
 
 // Start/stop events carried by one pass launch (sampled timing).
 struct LaunchEv {
@@ -30,6 +46,7 @@ struct PassArgs {
   const void* src;            // cx<R> field buffer read
   void* dst;                  // cx<R> field buffer written
   const void* aux;            // ROW_ADJ: pre-screen field s_n (cx<R>)
+  void* state;                // ROW_FD: U of the step (read; U+ written when finishing)
   const WorkItem* work;       // one entry per workgroup
   const InstDev* inst;        // beam table
   const void* tables;         // cx<R> twiddle and propagator tables
@@ -40,7 +57,8 @@ struct PassArgs {
                               // ROW_ADJ: [n_work][8] theta accumulators
   int64_t step;               // step whose screen is pending (-1: none)
   int32_t pair;               // COL_INV: screen pair index
-  int32_t flags;              // COL_FWD: bit 0 = power partials without the screen's A^2
+  int32_t flags;              // COL_FWD: bit 0 = power partials without the screen's A^2;
+                              // ROW_FD: FD_* bits
 };
 
 struct PlanInfo {

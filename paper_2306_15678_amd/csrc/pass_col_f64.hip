@@ -10,6 +10,7 @@ hipError_t launch_col<double>(int kind, int n, int v, int nb, const PassArgs<dou
     case COL_FWD: return launch_col_kind<double, COL_FWD>(n, v, nb, a, s, ev);
     case COL_ADJ: return launch_col_kind<double, COL_ADJ>(n, v, nb, a, s, ev);
     case COL_INV: return launch_col_kind<double, COL_INV>(n, v, nb, a, s, ev);
+    case COL_FD: return launch_col_kind<double, COL_FD>(n, v, nb, a, s, ev);
     default: return hipErrorInvalidValue;
   }
 }

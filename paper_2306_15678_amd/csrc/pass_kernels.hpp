@@ -86,6 +86,21 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double* red) {
   }
 }
 
+// dz G(x) of the finite-difference scheme, x = |u|^2 / I_a: the generators
+// of the Kerr, plasma and multiphoton terms (each split-step screen term is
+// the exact solution of du/dz = G u over one step).
+template <typename R>
+__device__ __forceinline__ void fd_generator(const ScreenConst<R>& s, R x, R& gr, R& gi) {
+  const unsigned tm = s.terms;
+  R xk1 = R(0);
+  if (tm & (T_MPA | T_PLASMA)) xk1 = ipow(x, s.K - 1);
+  gr = R(0);
+  gi = R(0);
+  if (tm & T_KERR) gi += s.cK * x;
+  if (tm & T_PLASMA) gi -= s.cK * x * (R(1) - rcp(R(1) + xk1));
+  if (tm & T_MPA) gr -= s.cM * s.inv2k1 * xk1;
+}
+
 template <class P>
 constexpr int tw_regs() {
   return TwCount<P>::value > 0 ? TwCount<P>::value : 1;
@@ -127,7 +142,7 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
   cx<R> wt[tw_regs<P>()];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = src[toff + uint32_t(T * e)];
-  if constexpr (KIND != ROW_INV) {
+  if constexpr (KIND != ROW_INV && KIND != ROW_FD) {
 #pragma unroll
     for (int e = 0; e < E; ++e) pr[e] = prop[t + T * e];
   }
@@ -154,6 +169,55 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
     }
   }
   (void)row;
+
+  if constexpr (KIND == ROW_FD) {
+    // finite-difference iteration: v is Ubar row-transformed (the column pass
+    // applied the solve and both 1/N), or U itself when the step starts
+    cx<R>* __restrict__ st = static_cast<cx<R>*>(a.state) + wbase;
+    cx<R> un[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) un[e] = st[toff + uint32_t(T * e)];
+    if (a.flags & FD_SPECTRAL) fft_line<R, P, +1>(v, t, lds, wt);
+    if (a.flags & FD_FINISH) {
+      // U+ = 2 Ubar - U, its power partials; it is the next step's U and
+      // its first Ubar
+      double s[1] = {0.0}, m[1] = {0.0};
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        v[e] = {R(2) * v[e].re - un[e].re, R(2) * v[e].im - un[e].im};
+        st[toff + uint32_t(T * e)] = v[e];
+        const double x = double(v[e].re) * double(v[e].re) + double(v[e].im) * double(v[e].im);
+        s[0] += x;
+        m[0] = fmax(m[0], x);
+        un[e] = v[e];
+      }
+      if (a.part != nullptr) {
+        block_reduce<1, P::THREADS, false>(s, red);
+        __syncthreads();
+        block_reduce<1, P::THREADS, true>(m, red + ((P::THREADS + 63) / 64));
+        if (threadIdx.x == 0) {
+          a.part[int64_t(w.widx) * 2 + 0] = s[0];
+          a.part[int64_t(w.widx) * 2 + 1] = m[0];
+        }
+      }
+      if (a.flags & FD_LAST) return;
+    }
+    // right-hand side U + (dz/2) G(J) Ubar, J = (|2 Ubar - U|^2 + |U|^2) / 2
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const R dr = R(2) * v[e].re - un[e].re, di = R(2) * v[e].im - un[e].im;
+      const R j = R(0.5) * (dr * dr + di * di + un[e].re * un[e].re + un[e].im * un[e].im);
+      R gr, gi;
+      fd_generator<R>(sc, j, gr, gi);
+      gr *= R(0.5);
+      gi *= R(0.5);
+      v[e] = {un[e].re + (gr * v[e].re - gi * v[e].im), un[e].im + (gr * v[e].im + gi * v[e].re)};
+    }
+    fft_line<R, P, -1>(v, t, lds, wt);
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[toff + uint32_t(T * e)] = v[e];
+    return;
+  }
 
   if constexpr (KIND == ROW_FWD) {
     if (a.step >= 0) screen_apply_n<R, E>(sc, v, ph);
@@ -232,8 +296,23 @@ __global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
     fft_line<R, P, +1>(v, t, lds, wt);
   } else {
     fft_line<R, P, -1>(v, t, lds, wt);
+    if constexpr (KIND == COL_FD) {
+      // (1 - (i dz/4k0) Lap_h)^-1 = 1 / (1 + i (d[kx] + d[ky])) with the 1/N^2
+      // of both inverse DFTs; the table holds d[m] = (dz/4k0)(4/dx^2)
+      // sin^2(pi m / N) in its real parts
+      const R dkx = prop[w.line0 + c].re;
+      const R inv_n2 = R(1) / (R(N) * R(N));
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = (KIND == COL_ADJ) ? cmulc(v[e], pr[e]) : cmul(v[e], pr[e]);
+      for (int e = 0; e < E; ++e) {
+        const R sm = dkx + pr[e].re;
+        const R den = inv_n2 / (R(1) + sm * sm);
+        v[e] = cmul(v[e], cx<R>{den, -sm * den});
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        v[e] = (KIND == COL_ADJ) ? cmulc(v[e], pr[e]) : cmul(v[e], pr[e]);
+    }
     fft_line<R, P, +1>(v, t, lds, wt);
   }
 
@@ -288,7 +367,7 @@ __global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
 // of the kernel alone, no separate marker packets).
 template <typename R, class P, int KIND>
 hipError_t launch_one(int n_blocks, const PassArgs<R>& a, hipStream_t s, const LaunchEv* ev) {
-  if constexpr (KIND >= COL_FWD) {
+  if constexpr (is_col_kind(KIND)) {
     if (ev)
       hipExtLaunchKernelGGL((k_col<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s,
                             ev->start, ev->stop, 0, a);

@@ -89,7 +89,8 @@ int validate_desc(const ssfm_instance_desc* d, int32_t n_inst, int32_t precision
 struct Layout {
   size_t inst, steps, work, wbegin_row, wbegin_col, tables;
   size_t S, Wk, Wk2, Lam, ckpt, stack, screens, stage, diag_part, diag, theta_acc,
-      theta_out, seed_loss, seed_theta, scal, sumsq_part, lens_inst, half_inst, back_inst;
+      theta_out, seed_loss, seed_theta, scal, sumsq_part, lens_inst, half_inst, back_inst,
+      fd_inst;
   size_t total;
   int64_t field_elems;  // sum n^2
   int64_t table_elems;
@@ -121,6 +122,12 @@ struct ssfm_ctx {
   // its own screen on load; half_off / back_off: tables of L(+-dz/2)
   bool strang = false;
   std::vector<int64_t> half_off, back_off;
+  // finite-difference reference scheme (Crank-Nicolson, fixed-point
+  // iterations per step); fd_off: each beam's table of
+  // d[m] = (dz / (k0 dx^2)) sin^2(pi m / n)
+  bool fd = false;
+  int fd_iters = 4;
+  std::vector<int64_t> fd_off;
   struct Spectrum {
     int kind = SSFM_SPECTRUM_KOLMOGOROV;
     double tau = 0.0, kappa_h = 0.0;
@@ -325,7 +332,8 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
       tw_done.push_back(d[b].n);
       te += d[b].n;
     }
-    te += 4 * int64_t(d[b].n);  // propagator, lens filter, +/- half-step propagators
+    // propagator, lens filter, +/- half-step propagators, finite-difference table
+    te += 5 * int64_t(d[b].n);
     if (d[b].terms & SSFM_TURB) {
       se += int64_t(d[b].n_screens) * d[b].n * d[b].n;
       nsteps += d[b].n_screens;
@@ -371,7 +379,9 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
   l.stack = take(el * fe * l.n_stack * (l.n_ckpt > 1 ? 2 : 1));
   l.screens = take(rel * se);
   l.stage = take(16 * size_t(max_n) * max_n);
-  l.diag_part = take(sizeof(double) * 2 * kDiagChunk * nc_max);
+  // power partials of column work items (split-step) or row work items
+  // (finite differences)
+  l.diag_part = take(sizeof(double) * 2 * kDiagChunk * std::max(nr_max, nc_max));
   l.diag = take(sizeof(double) * 2 * l.diag_cap * n_inst);
   l.theta_acc = take(sizeof(double) * 8 * nr_max);
   l.theta_out = take(sizeof(double) * 8 * n_inst);
@@ -382,6 +392,7 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
   l.lens_inst = take(sizeof(InstDev) * n_inst);
   l.half_inst = take(sizeof(InstDev) * n_inst);
   l.back_inst = take(sizeof(InstDev) * n_inst);
+  l.fd_inst = take(sizeof(InstDev) * n_inst);
   l.total = off;
   if (groups_out) *groups_out = groups;
   if (work_out) *work_out = work;
@@ -454,7 +465,7 @@ PassArgs<R> base_args(ssfm_ctx* c) {
 template <typename R>
 int run_pass(ssfm_ctx* c, int kind, PassArgs<R> a, hipStream_t st = nullptr,
              const hipEvent_t* ev = nullptr) {
-  const bool col = kind >= COL_FWD;
+  const bool col = is_col_kind(kind);
   if (!st) st = c->stream;
   const int chain = (st == c->aux) ? 1 : 0;
   const size_t ng = c->groups.size();
@@ -581,6 +592,48 @@ int enqueue_propagate(ssfm_ctx* c, int64_t step0, bool pending0, int64_t i0, int
   return SSFM_OK;
 }
 
+// Steps i0 <= i < i1 of a finite-difference march from step step0 + i0, on
+// S (U) and Wk (the row-transformed right-hand side).  The first row pass
+// forms U + (dz/2) G(|U|^2) U from S; each of the fd_iters iterations is a
+// column pass (the solve) and a row pass (Ubar, then the next right-hand
+// side); the last row pass of a step writes U+ = 2 Ubar - U and its power
+// partials and, unless the range ends, starts the next step.
+template <typename R>
+int enqueue_fd(ssfm_ctx* c, int64_t step0, int64_t i0, int64_t i1) {
+  PassArgs<R> a = base_args<R>(c);
+  a.inst = c->at<InstDev>(c->L.fd_inst);
+  a.state = c->field(c->L.S);
+  a.src = c->field(c->L.S);
+  a.dst = c->field(c->L.Wk);
+  a.flags = 0;
+  if (int r = run_pass<R>(c, ROW_FD, a)) return r;
+  PassArgs<R> col = base_args<R>(c);
+  col.inst = a.inst;
+  col.src = c->field(c->L.Wk);
+  col.dst = c->field(c->L.Wk);
+  a.src = c->field(c->L.Wk);
+  int64_t chunk_start = step0 + i0;
+  for (int64_t i = i0; i < i1; ++i) {
+    const int slot = int((i - i0) % kDiagChunk);
+    for (int k = 1; k <= c->fd_iters; ++k) {
+      if (int r = run_pass<R>(c, COL_FD, col)) return r;
+      const bool fin = (k == c->fd_iters);
+      a.flags = FD_SPECTRAL | (fin ? FD_FINISH : 0) | ((fin && i == i1 - 1) ? FD_LAST : 0);
+      a.part = fin ? c->at<double>(c->L.diag_part) + size_t(slot) * 2 * c->L.n_widx_rows
+                   : nullptr;
+      if (int r = run_pass<R>(c, ROW_FD, a)) return r;
+    }
+    if (slot == kDiagChunk - 1 || i == i1 - 1) {
+      HIP_TRY(launch_diag_finalize(c->at<double>(c->L.diag_part), int(c->L.n_widx_rows),
+                                   c->at<int32_t>(c->L.wbegin_row), int(c->desc.size()),
+                                   slot + 1, c->at<double>(c->L.diag), chunk_start,
+                                   c->L.diag_cap, 0.0, c->stream));
+      chunk_start = step0 + i + 1;
+    }
+  }
+  return SSFM_OK;
+}
+
 // Runs `body` directly or through a cached graph keyed by (kind, a, b, i0, i1).
 template <typename F>
 int maybe_graph(ssfm_ctx* c, int kind, int64_t a, int64_t b, int64_t i0, int64_t i1, F body) {
@@ -660,6 +713,18 @@ template <typename R>
 int do_propagate(ssfm_ctx* c, int64_t n) {
   const int64_t step0 = c->step;
   const bool pend = c->pending;
+  if (c->fd) {
+    // one graph per (start step, length): the diagnostics ring slots depend
+    // on the absolute step
+    int r = maybe_graph(c, 3, step0, n, 0, n, [&] { return enqueue_fd<R>(c, step0, 0, n); });
+    if (r) return r;
+    c->step += n;
+    c->pending = false;
+    c->diag_valid = std::min<int64_t>(n, c->L.diag_cap);
+    c->rec_valid = false;
+    c->seeded = false;
+    return SSFM_OK;
+  }
   int r = run_forward(c, 0, step0 * 2 + (pend ? 1 : 0), n, step0,
                       [&](int64_t i0, int64_t i1, const ssfm_ctx::PassSample* ts) {
                         return enqueue_propagate<R>(c, step0, pend, i0, i1, ts);
@@ -920,6 +985,7 @@ int upload_plan(ssfm_ctx* c) {
   c->lens_off.assign(n_inst, 0);
   c->half_off.assign(n_inst, 0);
   c->back_off.assign(n_inst, 0);
+  c->fd_off.assign(n_inst, 0);
   if (c->spectrum.size() != size_t(n_inst)) c->spectrum.assign(n_inst, ssfm_ctx::Spectrum{});
   c->screen_steps.clear();
   int64_t foff = 0, soff = 0;
@@ -954,6 +1020,20 @@ int upload_plan(ssfm_ctx* c) {
       propagator(h, &tmp);
       append_table<R>(&blob, tmp);
     }
+    {
+      // 1 - (i dz/4k0) Lap_h has eigenvalue 1 + i (d[mx] + d[my]) on the DFT
+      // mode (mx, my) of the periodic 5-point Laplacian
+      const double k0 = 2.0 * M_PI / d.wavelength;
+      const double dx = d.length / d.n;
+      const double coef = d.dz / (k0 * dx * dx);
+      c->fd_off[b] = int64_t(blob.size() / c->el);
+      tmp.assign(2 * size_t(d.n), 0.0);
+      for (int m = 0; m < d.n; ++m) {
+        const double sn = std::sin(M_PI * m / d.n);
+        tmp[2 * m] = coef * sn * sn;
+      }
+      append_table<R>(&blob, tmp);
+    }
     in.steps_off = int64_t(c->screen_steps.size());
     for (int64_t s : screen_step_list(d)) c->screen_steps.push_back(s);
     const double k0 = 2.0 * M_PI / d.wavelength;
@@ -984,6 +1064,14 @@ int upload_plan(ssfm_ctx* c) {
   HIP_TRY(hipMemcpyAsync(c->ws + c->L.half_inst, half_inst.data(), sizeof(InstDev) * n_inst,
                          hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipMemcpyAsync(c->ws + c->L.back_inst, back_inst.data(), sizeof(InstDev) * n_inst,
+                         hipMemcpyHostToDevice, c->stream));
+  // finite differences: the beam's own screen constants, the solve table
+  std::vector<InstDev> fd_inst = c->inst;
+  for (int b = 0; b < n_inst; ++b) {
+    fd_inst[b].prop_off = c->fd_off[b];
+    fd_inst[b].n_screens = 0;
+  }
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.fd_inst, fd_inst.data(), sizeof(InstDev) * n_inst,
                          hipMemcpyHostToDevice, c->stream));
   if (!c->screen_steps.empty())
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.steps, c->screen_steps.data(),
@@ -1320,11 +1408,21 @@ int ssfm_get_intensity(ssfm_ctx* c, int32_t inst, void* dst, int32_t where) {
 
 int ssfm_set_splitting(ssfm_ctx* c, int32_t scheme) {
   if (int r = check_ctx(c)) return r;
-  if (scheme != SSFM_LIE && scheme != SSFM_STRANG)
-    return fail(SSFM_EINVAL, "unknown splitting %d", scheme);
+  if (scheme != SSFM_LIE && scheme != SSFM_STRANG && scheme != SSFM_FD)
+    return fail(SSFM_EINVAL, "unknown scheme %d", scheme);
+  if (scheme == SSFM_FD) {
+    for (size_t b = 0; b < c->desc.size(); ++b) {
+      const ssfm_instance_desc& d = c->desc[b];
+      if ((d.terms & SSFM_ANSATZ) || ((d.terms & SSFM_TURB) && d.n_screens > 0))
+        return fail(SSFM_EUNSUPPORTED,
+                    "the finite-difference scheme covers the Kerr, plasma and multiphoton "
+                    "terms only (instance %zu has the ansatz or turbulence screens)", b);
+    }
+  }
   HIP_TRY(hipStreamSynchronize(c->stream));
   clear_graphs(c);
   c->strang = (scheme == SSFM_STRANG);
+  c->fd = (scheme == SSFM_FD);
   HIP_TRY(hipMemsetAsync(c->field(c->L.S), 0, c->el * c->L.field_elems, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->step = 0;
@@ -1338,10 +1436,26 @@ int ssfm_set_splitting(ssfm_ctx* c, int32_t scheme) {
 
 namespace {
 int lie_only(ssfm_ctx* c, const char* what) {
-  if (c->strang)
-    return fail(SSFM_EUNSUPPORTED, "%s needs Lie splitting (Strang marches forward only)", what);
+  if (c->strang || c->fd)
+    return fail(SSFM_EUNSUPPORTED, "%s needs the Lie split-step scheme (%s marches forward only)",
+                what, c->strang ? "Strang" : "the finite-difference scheme");
   return SSFM_OK;
 }
+
+}  // namespace
+
+int ssfm_set_fd_iterations(ssfm_ctx* c, int32_t iterations) {
+  if (int r = check_ctx(c)) return r;
+  if (iterations < 1 || iterations > 64)
+    return fail(SSFM_EINVAL, "finite-difference iterations must be in [1, 64], got %d",
+                iterations);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  clear_graphs(c);
+  c->fd_iters = iterations;
+  return SSFM_OK;
+}
+
+namespace {
 }  // namespace
 
 int ssfm_get_diag(ssfm_ctx* c, int32_t inst, double* power, double* peak, int64_t n) {

@@ -211,6 +211,13 @@ class Propagator:
         """Lie (default) or Strang splitting of each step; zeroes the fields."""
         L.call("ssfm_set_splitting", self.ctx, L.STRANG if strang else L.LIE)
 
+    def set_finite_difference(self, iterations: Optional[int] = None) -> None:
+        """March with the finite-difference reference scheme (Crank-Nicolson,
+        `iterations` fixed-point iterations per step); zeroes the fields."""
+        L.call("ssfm_set_splitting", self.ctx, L.FD)
+        if iterations is not None:
+            L.call("ssfm_set_fd_iterations", self.ctx, int(iterations))
+
     def set_screen_spectrum(self, i: int, step: Optional[Tuple[float, float]] = None) -> None:
         """Screen spectrum of instance i for the next gen_screens: Kolmogorov
         (None) or the Eq. (10) low-pass step (tau [rad^2 per mode],
