@@ -162,6 +162,78 @@ def run_batched(args):
             "samples": n_samp, "bytes_pass": b_row}
 
 
+FD_ITERS = 4
+
+
+def run_schemes(args):
+    """The scheme variants on the 1024^2 workload, complex64, forward march:
+    Strang splitting (2000 steps) beside Lie; the finite-difference reference
+    scheme (500 steps, FD_ITERS iterations per step) with its whole-step HBM
+    rate; and the cost of 3 subharmonic levels in the screen synthesis of
+    the 64-beam batch."""
+    import torch
+
+    import workloads as W
+    from paper_2306_15678_amd.march import Propagator
+    from paper_2306_15678_amd.tune import tune
+
+    dev = torch.device("cuda", 0)
+    inst = W.config2()[0]
+    n = inst.n
+    u0_d = torch.from_numpy(W.initial_field(inst)).to(dev)
+    out = {}
+    p = Propagator(_desc_list([inst]), precision=32, device=dev)
+    tune(p, reps=10, use_cache=False)
+
+    def fwd(steps):
+        def go():
+            p.set_field(0, u0_d)
+            p.propagate(steps)
+        return go
+
+    reps = max(1, args.steps // 2)
+    t_lie = _timed(fwd(inst.n_steps), reps, 1, p.synchronize)
+    p.set_splitting(True)
+    t_strang = _timed(fwd(inst.n_steps), reps, 1, p.synchronize)
+    gp = float(n) * n * inst.n_steps
+    out["strang_forward"] = {"z_steps": inst.n_steps, "value": gp / t_strang,
+                             "unit": "grid-point\u00b7steps/s", "ms_per_march": t_strang * 1e3,
+                             "lie_ms_per_march": t_lie * 1e3}
+    fd_steps = 500
+    p.set_finite_difference(FD_ITERS)
+    t_fd = _timed(fwd(fd_steps), reps, 1, p.synchronize)
+    pw, _ = p.diag(0, fd_steps)
+    field_bytes = 8.0 * n * n
+    # per step: FD_ITERS column passes (Wk read + written), FD_ITERS - 1 row
+    # passes (Wk and S read, Wk written), the finishing row pass (Wk and S
+    # read, S and Wk written)
+    step_bytes = field_bytes * (2 * FD_ITERS + 3 * (FD_ITERS - 1) + 4)
+    us_step = t_fd / fd_steps * 1e6
+    out["fd_reference"] = {
+        "workload": f"{n}x{n} complex64, Kerr+MPA+plasma, {fd_steps} z steps, "
+                    f"{FD_ITERS} fixed-point iterations per step",
+        "value": float(n) * n * fd_steps / t_fd, "unit": "grid-point\u00b7steps/s",
+        "us_per_step": us_step, "launches_per_step": 2 * FD_ITERS,
+        "bytes_per_step": step_bytes, "achieved_GBps": step_bytes / (us_step * 1e-6) / 1e9,
+        "frac_of_8TBps": step_bytes / (us_step * 1e-6) / 8e12,
+        "power_drift": float(abs(pw[-1] / pw[0] - 1))}
+    p.close()
+    del p
+    torch.cuda.empty_cache()
+    insts = W.config3()
+    q = Propagator(_desc_list(insts), precision=32, device=dev)
+    t0 = _timed(q.gen_screens, 5, 1, q.synchronize)
+    for b in range(len(insts)):
+        q.set_subharmonics(b, 3)
+    t3 = _timed(q.gen_screens, 5, 1, q.synchronize)
+    q.close()
+    pts = float(sum(i.n * i.n * i.n_screens for i in insts))
+    out["subharmonics"] = {"workload": "64 beams x 20 screens, n in 256..1024, 3 levels",
+                           "gen_screens_ms": t0 * 1e3, "with_3_levels_ms": t3 * 1e3,
+                           "ns_per_screen_point": (t3 - t0) / pts * 1e9}
+    return out
+
+
 def time_diagnostics(p, inst, args):
     """The paper's beam diagnostics on the end fluence of the march: hot-area
     count (4-connected regions above 1 % of the peak, periodic window), the
@@ -422,6 +494,7 @@ def main():
         }
     if not args.no_batched:
         line["ga_generation"] = run_ga(args)
+        line.update(run_schemes(args))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

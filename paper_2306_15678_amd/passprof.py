@@ -11,8 +11,9 @@ checkpoint slot: a plain copy kernel of known size (n^2 complex elements
 read and written) against which byte counters can be scaled.
 
 Variants appear in index order: the k-th distinct forward row-pass kernel
-name in dispatch order is row variant k, likewise for columns.  Prints one
-line per phase; ``--out`` writes the layout as JSON.
+name in dispatch order is row variant k, likewise for columns.  Last comes
+an eager march of the finite-difference scheme (variant 0 plans).  Prints
+one line per phase; ``--out`` writes the layout as JSON.
 """
 from __future__ import annotations
 
@@ -27,6 +28,9 @@ import sys
 PASS_SOURCES = ("fft_core.hpp", "plans.hpp", "screen.hpp", "internal.hpp", "kernels.hpp",
                 "pass_kernels.hpp", "pass_row_f32.hip", "pass_row_f64.hip",
                 "pass_col_f32.hip", "pass_col_f64.hip")
+
+
+FD_ITERS = 4  # fixed-point iterations per finite-difference step
 
 
 def kernel_source_hash() -> str:
@@ -67,9 +71,18 @@ def main(argv=None) -> int:
             p.synchronize()
             order.append([kind, v])
             print(f"{kind} variant {v}: {args.steps} steps", flush=True)
+    # the finite-difference scheme's passes (variant 0 plans): one starting
+    # row pass, then per step FD_ITERS column passes and as many row passes
+    p.select_plan(n, 0, 0)
+    p.set_finite_difference(FD_ITERS)
+    p.set_field(0, u0)
+    p.propagate(args.steps)
+    p.synchronize()
+    order.append(["fd", 0])
+    print(f"finite differences: {args.steps} steps, {FD_ITERS} iterations", flush=True)
     p.close()
     info = {"grid": n, "precision": args.precision, "steps": args.steps,
-            "n_row": n_row, "n_col": n_col, "order": order,
+            "n_row": n_row, "n_col": n_col, "order": order, "fd_iters": FD_ITERS,
             "copy_bytes": n * n * (8 if args.precision == 32 else 16),
             "source_hash": kernel_source_hash()}
     if args.out:
