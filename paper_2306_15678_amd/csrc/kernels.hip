@@ -414,22 +414,27 @@ template hipError_t launch_noise<float>(const InstDev*, int, int, int, uint64_t,
 template hipError_t launch_noise<double>(const InstDev*, int, int, int, uint64_t, double, int,
                                          double, double, void*, hipStream_t);
 
-// Subharmonic modes: thread t < 8 levels draws mode t (level p = t / 8 + 1,
-// cell q = the t % 8-th of the 3 x 3 cells around f = 0 without the centre,
-// (mx, my) = (q % 3 - 1, q / 3 - 1), frequency spacing df = 1 / (3^p L)) from
-// Philox counter (q, p, pair, 1) and stores w = c sqrt(density) df in LDS.
-// The grid mean of exp(2 pi i m df x) over the cell-centred grid
-// x_j = (j + 1/2 - n/2) L/n is sin(pi/3^p) / (n sin(pi/(3^p n))) for
-// |m| = 1 (1 for m = 0), so the mean of the sum is formed from the w alone.
-// Every point then adds Re / Im of sum w e^{2 pi i f.x} - mean in FP64.
+// Subharmonic part of one screen pair in two kernels.  Setup (one
+// workgroup): thread t < 8 levels draws mode t (level p = t / 8 + 1, cell q =
+// the t % 8-th of the 3 x 3 cells around f = 0 without the centre, (mx, my) =
+// (q % 3 - 1, q / 3 - 1), spacing df = 1 / (3^p L)) from Philox counter
+// (q, p, pair, 1) and stores w = c sqrt(density) df; thread 0 forms the grid
+// mean of sum w e^{2 pi i f.x} (the mean of exp(2 pi i m df x) over the
+// cell-centred grid x_j = (j + 1/2 - n/2) L/n is sin(pi/3^p) /
+// (n sin(pi/(3^p n))) for |m| = 1, 1 for m = 0); all threads fill the axis
+// table e_p[j] = exp(2 pi i (j + 1/2 - n/2) / (3^p n)), the same for rows and
+// columns of the square grid.  Apply: every point adds Re / Im of
+// sum w e_p[col]^mx e_p[row]^my - mean to its two planes, in FP64.
+// Scratch layout (doubles): w (re, im) at [0, 128), mean at [128, 130), the
+// axis tables (re, im) from kSubTab on, level-major.
+
 template <typename R>
-__global__ void __launch_bounds__(256) k_subharmonics(const InstDev* inst, int b, int pair,
-                                                     uint32_t k0, uint32_t k1, SubharmonicSpec sp,
-                                                     R* __restrict__ planes) {
-  constexpr int kModes = 8 * kMaxSubharmonicLevels;
-  __shared__ double wre[kModes], wim[kModes], mean[2];
-  const InstDev& in = inst[b];
-  const int n = in.n;
+__global__ void __launch_bounds__(256) k_subharm_setup(const InstDev* inst, int b, int pair,
+                                                      uint32_t k0, uint32_t k1,
+                                                      SubharmonicSpec sp,
+                                                      double* __restrict__ scr) {
+  __shared__ double wre[8 * kMaxSubharmonicLevels], wim[8 * kMaxSubharmonicLevels];
+  const int n = inst[b].n;
   const int nm = 8 * sp.levels;
   const int t = threadIdx.x;
   if (t < nm) {
@@ -459,6 +464,8 @@ __global__ void __launch_bounds__(256) k_subharmonics(const InstDev* inst, int b
     }
     wre[t] = rr * cs * a;
     wim[t] = rr * sn * a;
+    scr[2 * t] = wre[t];
+    scr[2 * t + 1] = wim[t];
   }
   __syncthreads();
   if (t == 0) {
@@ -472,10 +479,33 @@ __global__ void __launch_bounds__(256) k_subharmonics(const InstDev* inst, int b
       mre += wre[m] * f;
       mim += wim[m] * f;
     }
-    mean[0] = mre;
-    mean[1] = mim;
+    scr[128] = mre;
+    scr[129] = mim;
   }
+  for (int k = t; k < sp.levels * n; k += blockDim.x) {
+    const int p = k / n, j = k - p * n;
+    double pow3 = 3.0;
+    for (int i = 0; i < p; ++i) pow3 *= 3.0;
+    double sn, cs;
+    sincospi(2.0 * (double(j) + 0.5 - 0.5 * n) / (pow3 * n), &sn, &cs);
+    scr[kSubTab + 2 * k] = cs;
+    scr[kSubTab + 2 * k + 1] = sn;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_subharm_apply(const InstDev* inst, int b, int pair,
+                                                      int levels, const double* __restrict__ scr,
+                                                      R* __restrict__ planes) {
+  __shared__ double w[2 * 8 * kMaxSubharmonicLevels + 2];
+  const InstDev& in = inst[b];
+  const int n = in.n;
+  const int nw = 2 * 8 * levels;
+  for (int k = threadIdx.x; k < nw; k += blockDim.x) w[k] = scr[k];
+  if (threadIdx.x < 2) w[2 * 8 * kMaxSubharmonicLevels + threadIdx.x] = scr[128 + threadIdx.x];
   __syncthreads();
+  const double mre = w[2 * 8 * kMaxSubharmonicLevels], mim = w[2 * 8 * kMaxSubharmonicLevels + 1];
+  const double* __restrict__ tab = scr + kSubTab;
   const int64_t n2 = int64_t(n) * n;
   R* pre = planes + in.screen_off + int64_t(2 * pair) * n2;
   R* pim = pre + n2;
@@ -483,44 +513,47 @@ __global__ void __launch_bounds__(256) k_subharmonics(const InstDev* inst, int b
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n2;
        i += int64_t(gridDim.x) * blockDim.x) {
     const int row = int(i / n), col = int(i - int64_t(row) * n);
-    const double xc = double(col) + 0.5 - 0.5 * n, yc = double(row) + 0.5 - 0.5 * n;
-    double sre = 0.0, sim = 0.0, pow3 = 1.0;
-    for (int p = 0; p < sp.levels; ++p) {
-      pow3 *= 3.0;
-      double exs, exc, eys, eyc;
-      sincospi(2.0 * xc / (pow3 * n), &exs, &exc);
-      sincospi(2.0 * yc / (pow3 * n), &eys, &eyc);
+    double sre = 0.0, sim = 0.0;
+    for (int p = 0; p < levels; ++p) {
+      const double xr = tab[2 * (p * n + col)], xi = tab[2 * (p * n + col) + 1];
+      const double yr = tab[2 * (p * n + row)], yi = tab[2 * (p * n + row) + 1];
+      // e^{i a} for the 3 x-exponents (-1, 0, 1) and y-exponents, combined
+      // per cell; cells in the order q = 0..8 without q = 4
+      const double exr[3] = {xr, 1.0, xr}, exi[3] = {-xi, 0.0, xi};
+      const double eyr[3] = {yr, 1.0, yr}, eyi[3] = {-yi, 0.0, yi};
+      const double* wp = w + 16 * p;
+#pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int q = (j < 4) ? j : j + 1, mx = q % 3 - 1, my = q / 3 - 1;
-        // e^{i (mx ax + my ay)} from the per-axis factors
-        const double xr = exc, xi = double(mx) * exs;  // mx in {-1, 0, 1}
-        const double yr = eyc, yi = double(my) * eys;
-        const double er0 = (mx == 0) ? 1.0 : xr, ei0 = (mx == 0) ? 0.0 : xi;
-        const double er1 = (my == 0) ? 1.0 : yr, ei1 = (my == 0) ? 0.0 : yi;
-        const double er = er0 * er1 - ei0 * ei1, ei = er0 * ei1 + ei0 * er1;
-        const double wr = wre[8 * p + j], wi = wim[8 * p + j];
+        const int q = (j < 4) ? j : j + 1, ix = q % 3, iy = q / 3;
+        const double er = exr[ix] * eyr[iy] - exi[ix] * eyi[iy];
+        const double ei = exr[ix] * eyi[iy] + exi[ix] * eyr[iy];
+        const double wr = wp[2 * j], wi = wp[2 * j + 1];
         sre += wr * er - wi * ei;
         sim += wr * ei + wi * er;
       }
     }
-    pre[i] = R(double(pre[i]) + (sre - mean[0]));
-    if (has_im) pim[i] = R(double(pim[i]) + (sim - mean[1]));
+    pre[i] = R(double(pre[i]) + (sre - mre));
+    if (has_im) pim[i] = R(double(pim[i]) + (sim - mim));
   }
 }
 
 template <typename R>
 hipError_t launch_subharmonics(const InstDev* inst, int b, int n, int pair, uint64_t seed,
-                               const SubharmonicSpec& spec, void* planes, hipStream_t s) {
+                               const SubharmonicSpec& spec, void* planes, void* scratch,
+                               hipStream_t s) {
   if (spec.levels < 1 || spec.levels > kMaxSubharmonicLevels) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_subharmonics<R>), dim3(grid_for(int64_t(n) * n, 256)), dim3(256), 0, s,
-                     inst, b, pair, uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32), spec,
+  double* scr = static_cast<double*>(scratch);
+  hipLaunchKernelGGL((k_subharm_setup<R>), dim3(1), dim3(256), 0, s, inst, b, pair,
+                     uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32), spec, scr);
+  hipLaunchKernelGGL((k_subharm_apply<R>), dim3(grid_for(int64_t(n) * n, 256)), dim3(256), 0, s,
+                     inst, b, pair, int(spec.levels), static_cast<const double*>(scr),
                      static_cast<R*>(planes));
   return hipGetLastError();
 }
 template hipError_t launch_subharmonics<float>(const InstDev*, int, int, int, uint64_t,
-                                               const SubharmonicSpec&, void*, hipStream_t);
+                                               const SubharmonicSpec&, void*, void*, hipStream_t);
 template hipError_t launch_subharmonics<double>(const InstDev*, int, int, int, uint64_t,
-                                                const SubharmonicSpec&, void*, hipStream_t);
+                                                const SubharmonicSpec&, void*, void*, hipStream_t);
 
 template <typename R>
 __global__ void k_plane_f64(const R* __restrict__ p, int64_t n, double* __restrict__ d) {

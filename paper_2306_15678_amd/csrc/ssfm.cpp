@@ -966,8 +966,13 @@ int do_gen_screens(ssfm_ctx* c) {
       ss.tau = sp.tau;
       ss.kappa_h = sp.kappa_h;
       ss.length = d.length;
+      // scratch: this beam's slice of the work buffer, idle until the next pair
+      const InstDev& in = c->inst[bi];
+      if (subharmonic_scratch_bytes(d.n, ss.levels) > size_t(d.n) * d.n * c->el)
+        return fail(SSFM_EINVAL, "grid %d too small for %d subharmonic levels", d.n, ss.levels);
+      void* scr = static_cast<char*>(c->field(c->L.Wk)) + in.off * int64_t(c->el);
       HIP_TRY(launch_subharmonics<R>(c->at<InstDev>(c->L.inst), int(bi), d.n, p, d.seed, ss,
-                                     c->at<R>(c->L.screens), c->stream));
+                                     c->at<R>(c->L.screens), scr, c->stream));
     }
   }
   return SSFM_OK;
