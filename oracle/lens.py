@@ -75,3 +75,64 @@ def apply_lens(u: np.ndarray, length: float, lens: Lens) -> np.ndarray:
     """U exp(i f_lens) where the lens is present, U elsewhere."""
     f_re, f_im, active = lens_exponent(u, length, lens)
     return np.where(active, u * np.exp(-f_im) * np.exp(1j * f_re), u)
+
+
+def _profile_terms(r: np.ndarray, segments):
+    """Per segment j: the mask of r on [r_{j-1}, r_j), cos and sin of
+    (freq r + phase) there."""
+    out = []
+    r_lo = 0.0
+    for r_hi, amp, freq, phase in segments:
+        sel = (r >= r_lo) & (r < r_hi)
+        arg = freq * r + phase
+        out.append((sel, amp, freq, np.cos(arg), np.sin(arg)))
+        r_lo = r_hi
+    return out
+
+
+def lens_vjp(u: np.ndarray, g_out: np.ndarray, length: float, lens: Lens):
+    """Vector-Jacobian product of apply_lens at u.
+
+    Cotangents follow G = dL/dRe U + i dL/dIm U, so dL = Re sum conj(G) dU.
+    With E = exp(i f(w_dif)), f = f_re + i f_im on the active points:
+      dU_out = E dU + U E i f'(w_dif) dw_dif,  dw_dif = Gauss(2 Re(conj(U) dU)),
+    and with z = conj(G_out) U E, q_re = -Im z, q_im = -Re z (the factors of
+    the real and imaginary parts of f in dL),
+      h     = q_re df_re/dw + q_im df_im/dw          (active points)
+      G_in  = conj(E) G_out + 2 Gauss(h) U            (Gauss is symmetric)
+      dL/dp = sum q_re df_re/dp + q_im df_im/dp       (profile parameters, c1, c2).
+    Returns (G_in, grad) with grad = [dL/dc1, dL/dc2, then (a, omega, psi) of
+    each real segment, then (b, nu, eta) of each imaginary one].  The
+    trimming level, the joining points and l_dif are not differentiated
+    (the first two are discontinuities of f)."""
+    w = np.abs(u) ** 2
+    w_dif = filtered_intensity(w, length, lens.l_dif)
+    active = w_dif >= lens.w_l
+    arg = np.where(active, w_dif / lens.c1 + lens.c2, 0.0)
+    r = np.cbrt(np.maximum(arg, 0.0))
+    inside = active & (arg > 0.0)
+    f_re, f_im, _ = lens_exponent(u, length, lens)
+    e = np.where(active, np.exp(-f_im) * np.exp(1j * f_re), 1.0)
+    z = np.conj(g_out) * u * e
+    q_re = np.where(active, -z.imag, 0.0)
+    q_im = np.where(active, -z.real, 0.0)
+    # d(profile)/dr of each part and the per-parameter sums
+    dp_dr = np.zeros_like(w)
+    grad_seg = []
+    for part, q in ((lens.re, q_re), (lens.im, q_im)):
+        dpart = np.zeros_like(w)
+        for sel, amp, freq, cs, sn in _profile_terms(r, part):
+            m = sel & active
+            dpart[m] = -amp * freq * sn[m]
+            grad_seg += [float(np.sum(q[m] * cs[m])),
+                         float(np.sum(q[m] * (-amp * r[m] * sn[m]))),
+                         float(np.sum(q[m] * (-amp * sn[m])))]
+        dp_dr += q * dpart
+    # r = cbrt(w / c1 + c2): dr/dw = 1 / (3 c1 r^2), dr/dc1 = -w / (3 c1^2 r^2),
+    # dr/dc2 = 1 / (3 r^2), where the cube root's argument is positive
+    inv3r2 = np.where(inside, 1.0 / (3.0 * np.where(inside, r, 1.0) ** 2), 0.0)
+    h = dp_dr * inv3r2 / lens.c1
+    g_c1 = float(np.sum(dp_dr * inv3r2 * (-w_dif / lens.c1 ** 2)))
+    g_c2 = float(np.sum(dp_dr * inv3r2))
+    g_in = np.conj(e) * g_out + 2.0 * filtered_intensity(h, length, lens.l_dif) * u
+    return g_in, np.array([g_c1, g_c2] + grad_seg)

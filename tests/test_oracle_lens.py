@@ -72,3 +72,70 @@ def test_absorbing_lens_lowers_the_power():
     inst, u = _field()
     v = LN.apply_lens(u, inst.length, _lens(inst, u, absorb=True))
     assert np.sum(np.abs(v) ** 2) < np.sum(np.abs(u) ** 2)
+
+
+def _smooth_lens(inst, u):
+    """A lens whose f is continuous: one segment per part ending at r_end with
+    cos(...) = 0 there, trimming beyond r_end (r in [0.238, 0.29] mm on the
+    active points), so finite differences see no jump."""
+    peak = float(LN.filtered_intensity(np.abs(u) ** 2, inst.length,
+                                       4 * (inst.length / inst.n) ** 2).max())
+    c2 = (0.3e-3) ** 3
+    r_end, om, nu = 0.28e-3, 2.0e4, 1.0e4
+    return LN.Lens(4 * (inst.length / inst.n) ** 2, 0.2 * peak, -2.0 * peak / c2, c2,
+                   [(r_end, 0.7, om, math.pi / 2 - om * r_end)],
+                   [(r_end, 0.05, nu, math.pi / 2 - nu * r_end)])
+
+
+def _functional(u, g, length, lens):
+    return float(np.real(np.sum(np.conj(g) * LN.apply_lens(u, length, lens))))
+
+
+def test_lens_vjp_field_cotangent_matches_finite_differences():
+    inst, u = _field()
+    lens = _smooth_lens(inst, u)
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(u.shape) + 1j * rng.standard_normal(u.shape)
+    d = (rng.standard_normal(u.shape) + 1j * rng.standard_normal(u.shape)) * np.abs(u).max()
+    g_in, _ = LN.lens_vjp(u, g, inst.length, lens)
+    want = float(np.real(np.sum(np.conj(g_in) * d)))
+    for h in (1e-5, 5e-6):
+        fd = (_functional(u + h * d, g, inst.length, lens)
+              - _functional(u - h * d, g, inst.length, lens)) / (2 * h)
+        assert abs(fd / want - 1) < 1e-6, (h, fd, want)
+    # the nonlocal part (through the filtered intensity) carries a share of
+    # the derivative far above the tolerance, so an error in it shows
+    f_re, f_im, act = LN.lens_exponent(u, inst.length, lens)
+    local = np.where(act, np.exp(-f_im) * np.exp(-1j * f_re), 1.0) * g
+    share = float(np.real(np.sum(np.conj(g_in - local) * d))) / want
+    assert abs(share) > 1e-3, share
+
+
+def test_lens_vjp_parameter_gradients_match_finite_differences():
+    inst, u = _field()
+    lens = _smooth_lens(inst, u)
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal(u.shape) + 1j * rng.standard_normal(u.shape)
+    _, grad = LN.lens_vjp(u, g, inst.length, lens)
+    names = ["c1", "c2", "re.a", "re.omega", "re.psi", "im.b", "im.nu", "im.eta"]
+
+    def with_param(k, v):
+        c1, c2 = lens.c1, lens.c2
+        re, im = [list(s) for s in lens.re], [list(s) for s in lens.im]
+        if k == 0:
+            c1 = v
+        elif k == 1:
+            c2 = v
+        elif k < 5:
+            re[0][k - 1] = v
+        else:
+            im[0][k - 4] = v
+        return LN.Lens(lens.l_dif, lens.w_l, c1, c2, [tuple(s) for s in re], [tuple(s) for s in im])
+
+    base = [lens.c1, lens.c2, *lens.re[0][1:], *lens.im[0][1:]]
+    for k, name in enumerate(names):
+        h = 1e-6 * abs(base[k])
+        fd = (_functional(u, g, inst.length, with_param(k, base[k] + h))
+              - _functional(u, g, inst.length, with_param(k, base[k] - h))) / (2 * h)
+        assert abs(fd - grad[k]) < 1e-5 * abs(grad[k]) + 1e-12, (name, fd, grad[k])
+        assert abs(grad[k]) > 0, name
