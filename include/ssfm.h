@@ -289,6 +289,25 @@ typedef struct {
 
 int ssfm_apply_lens(ssfm_ctx* ctx, int32_t inst, const ssfm_lens* lens);
 
+/* Vector-Jacobian product of the effective lens, for fitting the lens
+ * parameters by gradients (the differentiable variant of the lens that can
+ * take the place of the ansatz f_theta; Eq. (4)-(6)).  For the lens applied
+ * to the field u_in of instance inst's grid (the context's own fields and
+ * recorded march are not used or changed), given the cotangent g_out of
+ * its output, writes the cotangent g_in of its input and grad[] = dL/d
+ * (c1, c2, then amplitude, frequency, phase of each real segment, then of
+ * each imaginary segment): 2 + 3 (n_re + n_im) values, n_grad at least that.
+ * Cotangents follow G = dL/dRe U + i dL/dIm U (as ssfm_set_cotangent);
+ * u_in, g_out, g_in: device complex128 n x n row-major [sqrt(W/m^2)],
+ * g_in may not alias the others.  With z = conj(g_out) U E, E = exp(i f):
+ *   g_in = conj(E) g_out + 2 F^-1[exp(-l_dif k^2) F h] U,
+ *   h = -Im(z) df_re/dw_dif - Re(z) df_im/dw_dif on the active points;
+ * l_dif, w_l and the joining points are not differentiated (the last two
+ * are jumps of f).  Uses the work buffer and the staging area; synchronises.
+ * SSFM_EINVAL for an invalid lens, NULL pointers or a short grad. */
+int ssfm_lens_vjp(ssfm_ctx* ctx, int32_t inst, const ssfm_lens* lens, const void* u_in,
+                  const void* g_out, void* g_in, double* grad, int32_t n_grad);
+
 /* Hot areas (Results, multiple filamentation and the turbulent path: a hot
  * area is a closed region of the fluence where w >= w_p; N_ha is their
  * number).  Counts the 4-connected regions of w >= threshold in the n x n

@@ -83,6 +83,8 @@ _SIGS = {
     "ssfm_time_passes": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
                                    POINTER(c_double), POINTER(c_double)]),
     "ssfm_apply_lens": (c_int32, [c_void_p, c_int32, POINTER(LensParams)]),
+    "ssfm_lens_vjp": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_void_p, c_int32]),
     "ssfm_set_screen_spectrum": (c_int32, [c_void_p, c_int32, c_int32, c_double, c_double]),
     "ssfm_set_subharmonics": (c_int32, [c_void_p, c_int32, c_int32]),
     "ssfm_set_fd_iterations": (c_int32, [c_void_p, c_int32]),

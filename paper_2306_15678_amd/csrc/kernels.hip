@@ -5,8 +5,11 @@
 // precision in pass_{row,col}_{f32,f64}.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "pass_kernels.hpp"
+#include "lens_vjp.hpp"
 #include "subharmonics.hpp"
 
 namespace ssfm {
@@ -249,6 +252,172 @@ template hipError_t launch_lens_apply<float>(void*, const void*, int64_t, const 
                                              hipStream_t);
 template hipError_t launch_lens_apply<double>(void*, const void*, int64_t, const LensDev&,
                                               hipStream_t);
+
+// Vector-Jacobian product of the lens (G = dL/dRe U + i dL/dIm U).  With
+// E = exp(i f(w_dif)) on the active points, z = conj(G_out) U E, q_re =
+// -Im z, q_im = -Re z:
+//   h    = q_re df_re/dw + q_im df_im/dw,   G_in = conj(E) G_out + 2 Gauss(h) U,
+//   dL/dp = sum q_re df_re/dp + q_im df_im/dp  (c1, c2, each segment's
+//           amplitude, frequency and phase).
+// Fields u, g_out, g_in: complex128 SI of one beam; wk: that beam's slice of
+// the work buffer (w_dif in, h I_a out, both real parts, device units).
+template <typename R>
+__global__ void k_lens_vjp_prep(const double* __restrict__ u, double inv_iref,
+                                cx<R>* __restrict__ wk, int64_t n2) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n2;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double ur = u[2 * i], ui = u[2 * i + 1];
+    wk[i] = cx<R>{R((ur * ur + ui * ui) * inv_iref), R(0)};
+  }
+}
+
+// segment of r in one part (-1: beyond the last joining point)
+__device__ __forceinline__ int lens_segment(double r, const double (*seg)[4], int n) {
+  double lo = 0.0;
+  for (int j = 0; j < n; ++j) {
+    if (r >= lo && r < seg[j][0]) return j;
+    lo = seg[j][0];
+  }
+  return -1;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_lens_vjp_point(const double* __restrict__ u, const double* __restrict__ g_out,
+                 cx<R>* __restrict__ wk, double* __restrict__ g_in, int64_t n2, LensDev p,
+                 double* __restrict__ part) {
+  __shared__ double red[4 * kLensGrads];
+  double acc[kLensGrads];
+#pragma unroll
+  for (int k = 0; k < kLensGrads; ++k) acc[k] = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n2;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double gr = g_out[2 * i], gi = g_out[2 * i + 1];
+    const double w_dif = double(wk[i].re) * p.i_ref;
+    if (!(w_dif >= p.w_l)) {
+      g_in[2 * i] = gr;
+      g_in[2 * i + 1] = gi;
+      wk[i] = cx<R>{R(0), R(0)};
+      continue;
+    }
+    const double arg = w_dif / p.c1 + p.c2;
+    const double r = cbrt(fmax(arg, 0.0));
+    const int jr = lens_segment(r, p.re, p.n_re), ji = lens_segment(r, p.im, p.n_im);
+    double cr = 0.0, sr = 0.0, ci = 0.0, si = 0.0;
+    if (jr >= 0) sincos(p.re[jr][2] * r + p.re[jr][3], &sr, &cr);
+    if (ji >= 0) sincos(p.im[ji][2] * r + p.im[ji][3], &si, &ci);
+    const double f_re = (jr >= 0) ? p.re[jr][1] * cr : 0.0;
+    const double f_im = (ji >= 0) ? p.im[ji][1] * ci : 0.0;
+    const double a = exp(-f_im);
+    const double er = a * cos(f_re), ei = a * sin(f_re);
+    const double ur = u[2 * i], ui = u[2 * i + 1];
+    // z = conj(G) U E
+    const double xr = gr * ur + gi * ui, xi = gr * ui - gi * ur;
+    const double zr = xr * er - xi * ei, zi = xr * ei + xi * er;
+    const double q_re = -zi, q_im = -zr;
+    double dp_dr = 0.0;
+    if (jr >= 0) {
+      const double amp = p.re[jr][1];
+      dp_dr += q_re * (-amp * p.re[jr][2] * sr);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j == jr) {
+          acc[2 + 3 * j] += q_re * cr;
+          acc[3 + 3 * j] += q_re * (-amp * r * sr);
+          acc[4 + 3 * j] += q_re * (-amp * sr);
+        }
+      }
+    }
+    if (ji >= 0) {
+      const double amp = p.im[ji][1];
+      dp_dr += q_im * (-amp * p.im[ji][2] * si);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j == ji) {
+          acc[26 + 3 * j] += q_im * ci;
+          acc[27 + 3 * j] += q_im * (-amp * r * si);
+          acc[28 + 3 * j] += q_im * (-amp * si);
+        }
+      }
+    }
+    // r = cbrt(w / c1 + c2): dr/dw = 1 / (3 c1 r^2), dr/dc1 = -w / (3 c1^2 r^2),
+    // dr/dc2 = 1 / (3 r^2) where the root's argument is positive
+    const double inv3r2 = (arg > 0.0) ? 1.0 / (3.0 * r * r) : 0.0;
+    acc[0] += dp_dr * inv3r2 * (-w_dif / (p.c1 * p.c1));
+    acc[1] += dp_dr * inv3r2;
+    const double h = dp_dr * inv3r2 / p.c1;
+    g_in[2 * i] = er * gr + ei * gi;
+    g_in[2 * i + 1] = er * gi - ei * gr;
+    wk[i] = cx<R>{R(h * p.i_ref), R(0)};
+  }
+  block_reduce<kLensGrads, 256, false>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kLensGrads; ++k) part[int64_t(blockIdx.x) * kLensGrads + k] = acc[k];
+  }
+}
+
+// G_in += 2 Gauss(h) U (wk: Gauss(h I_a) in its real parts)
+template <typename R>
+__global__ void k_lens_vjp_final(const double* __restrict__ u, const cx<R>* __restrict__ wk,
+                                 double inv_iref, double* __restrict__ g_in, int64_t n2) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n2;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double t = 2.0 * double(wk[i].re) * inv_iref;
+    g_in[2 * i] += t * u[2 * i];
+    g_in[2 * i + 1] += t * u[2 * i + 1];
+  }
+}
+
+// fixed-order sum of the per-block partials
+__global__ void k_lens_vjp_reduce(const double* __restrict__ part, int blocks,
+                                  double* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k >= kLensGrads) return;
+  double s = 0.0;
+  for (int b = 0; b < blocks; ++b) s += part[int64_t(b) * kLensGrads + k];
+  out[k] = s;
+}
+
+template <typename R>
+hipError_t launch_lens_vjp_prep(const double* u, double i_ref, void* wk, int64_t n2,
+                                hipStream_t st) {
+  hipLaunchKernelGGL((k_lens_vjp_prep<R>), dim3(grid_for(n2, 256)), dim3(256), 0, st, u,
+                     1.0 / i_ref, static_cast<cx<R>*>(wk), n2);
+  return hipGetLastError();
+}
+
+int lens_vjp_blocks(int64_t n2) { return std::min(grid_for(n2, 256), 512); }
+
+template <typename R>
+hipError_t launch_lens_vjp_point(const double* u, const double* g_out, void* wk, double* g_in,
+                                 int64_t n2, const LensDev& p, double* part, hipStream_t st) {
+  hipLaunchKernelGGL((k_lens_vjp_point<R>), dim3(lens_vjp_blocks(n2)), dim3(256), 0, st, u,
+                     g_out, static_cast<cx<R>*>(wk), g_in, n2, p, part);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_lens_vjp_final(const double* u, const void* wk, double i_ref, double* g_in,
+                                 int64_t n2, double* part, double* grads, hipStream_t st) {
+  hipLaunchKernelGGL((k_lens_vjp_final<R>), dim3(grid_for(n2, 256)), dim3(256), 0, st, u,
+                     static_cast<const cx<R>*>(wk), 1.0 / i_ref, g_in, n2);
+  hipLaunchKernelGGL(k_lens_vjp_reduce, dim3(1), dim3(64), 0, st, part, lens_vjp_blocks(n2),
+                     grads);
+  return hipGetLastError();
+}
+template hipError_t launch_lens_vjp_prep<float>(const double*, double, void*, int64_t,
+                                                hipStream_t);
+template hipError_t launch_lens_vjp_prep<double>(const double*, double, void*, int64_t,
+                                                 hipStream_t);
+template hipError_t launch_lens_vjp_point<float>(const double*, const double*, void*, double*,
+                                                 int64_t, const LensDev&, double*, hipStream_t);
+template hipError_t launch_lens_vjp_point<double>(const double*, const double*, void*, double*,
+                                                  int64_t, const LensDev&, double*, hipStream_t);
+template hipError_t launch_lens_vjp_final<float>(const double*, const void*, double, double*,
+                                                 int64_t, double*, double*, hipStream_t);
+template hipError_t launch_lens_vjp_final<double>(const double*, const void*, double, double*,
+                                                  int64_t, double*, double*, hipStream_t);
 
 template <typename R>
 __global__ void k_copy(const cx<R>* __restrict__ src, cx<R>* __restrict__ dst, int64_t n) {

@@ -27,6 +27,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "lens_vjp.hpp"
 #include "subharmonics.hpp"
 
 using namespace ssfm;
@@ -1096,31 +1097,38 @@ int upload_plan(ssfm_ctx* c) {
 }
 
 
-// Effective lens on beam b: filter |U|^2 through the pass kernels, then the
-// pointwise lens where the filtered intensity reaches the trimming level.
+// The lens filter exp(-l_dif k^2) of beam b (1/n per pass) into its filter
+// table; *blob holds the host copy until the caller synchronises.
 template <typename R>
-int do_apply_lens(ssfm_ctx* c, int b, const ssfm_lens& l) {
+int upload_lens_filter(ssfm_ctx* c, int b, double l_dif, std::vector<unsigned char>* blob) {
   const ssfm_instance_desc& d = c->desc[b];
-  if (int r = flush_pending<R>(c)) return r;
   std::vector<double> tab(2 * size_t(d.n), 0.0);
   const double dk = 2.0 * M_PI / d.length;
   for (int m = 0; m < d.n; ++m) {
     const int f = (m <= (d.n - 1) / 2) ? m : m - d.n;  // fftfreq order
     const double k = dk * f;
-    tab[2 * m] = std::exp(-l.l_dif * k * k) / d.n;
+    tab[2 * m] = std::exp(-l_dif * k * k) / d.n;
   }
-  std::vector<unsigned char> blob;
-  append_table<R>(&blob, tab);
-  HIP_TRY(hipMemcpyAsync(c->ws + c->L.tables + c->lens_off[b] * c->el, blob.data(), blob.size(),
-                         hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(launch_lens_prep<R>(c->field(c->L.S), c->field(c->L.Wk), c->L.field_elems, c->stream));
+  append_table<R>(blob, tab);
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.tables + c->lens_off[b] * c->el, blob->data(),
+                         blob->size(), hipMemcpyHostToDevice, c->stream));
+  return SSFM_OK;
+}
+
+// Wk <- the lens filter applied to Wk (row and column passes with the filter
+// tables in place of the propagators, no screen).
+template <typename R>
+int lens_filter_passes(ssfm_ctx* c) {
   PassArgs<R> a = base_args<R>(c);
   a.inst = c->at<InstDev>(c->L.lens_inst);
   a.src = c->field(c->L.Wk);
   a.dst = c->field(c->L.Wk);
   if (int r = run_pass<R>(c, ROW_FWD, a)) return r;
   a.part = nullptr;
-  if (int r = run_pass<R>(c, COL_FWD, a)) return r;
+  return run_pass<R>(c, COL_FWD, a);
+}
+
+LensDev lens_dev(const ssfm_instance_desc& d, const ssfm_lens& l) {
   LensDev p{};
   p.i_ref = d.i_ref;
   p.w_l = l.w_l;
@@ -1133,6 +1141,53 @@ int do_apply_lens(ssfm_ctx* c, int b, const ssfm_lens& l) {
       p.re[j][k] = l.re[j][k];
       p.im[j][k] = l.im[j][k];
     }
+  return p;
+}
+
+// Vector-Jacobian product of the lens at u_in (device complex128 of beam b):
+// filter |u|^2, pointwise cotangent and partials, filter h, final cotangent
+// and the fixed-order parameter sums (partials and sums in the staging area).
+template <typename R>
+int do_lens_vjp(ssfm_ctx* c, int b, const ssfm_lens& l, const double* u, const double* g_out,
+                double* g_in, double* grad, int n_grad) {
+  const ssfm_instance_desc& d = c->desc[b];
+  const int64_t n2 = int64_t(d.n) * d.n;
+  void* wk = static_cast<char*>(c->field(c->L.Wk)) + c->inst[b].off * int64_t(c->el);
+  double* part = c->at<double>(c->L.stage);
+  double* sums = part + int64_t(lens_vjp_blocks(n2)) * kLensGrads;
+  std::vector<unsigned char> blob;
+  if (int r = upload_lens_filter<R>(c, b, l.l_dif, &blob)) return r;
+  HIP_TRY(launch_lens_vjp_prep<R>(u, d.i_ref, wk, n2, c->stream));
+  if (int r = lens_filter_passes<R>(c)) return r;
+  HIP_TRY(launch_lens_vjp_point<R>(u, g_out, wk, g_in, n2, lens_dev(d, l), part, c->stream));
+  if (int r = lens_filter_passes<R>(c)) return r;
+  HIP_TRY(launch_lens_vjp_final<R>(u, wk, d.i_ref, g_in, n2, part, sums, c->stream));
+  double all[kLensGrads];
+  HIP_TRY(hipMemcpyAsync(all, sums, sizeof(all), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  // slots: c1, c2, real segments 0..7, imaginary segments 0..7 -> packed
+  int k = 0;
+  grad[k++] = all[0];
+  grad[k++] = all[1];
+  for (int j = 0; j < l.n_re; ++j)
+    for (int q = 0; q < 3; ++q) grad[k++] = all[2 + 3 * j + q];
+  for (int j = 0; j < l.n_im; ++j)
+    for (int q = 0; q < 3; ++q) grad[k++] = all[26 + 3 * j + q];
+  (void)n_grad;
+  return SSFM_OK;
+}
+
+// Effective lens on beam b: filter |U|^2 through the pass kernels, then the
+// pointwise lens where the filtered intensity reaches the trimming level.
+template <typename R>
+int do_apply_lens(ssfm_ctx* c, int b, const ssfm_lens& l) {
+  const ssfm_instance_desc& d = c->desc[b];
+  if (int r = flush_pending<R>(c)) return r;
+  std::vector<unsigned char> blob;
+  if (int r = upload_lens_filter<R>(c, b, l.l_dif, &blob)) return r;
+  HIP_TRY(launch_lens_prep<R>(c->field(c->L.S), c->field(c->L.Wk), c->L.field_elems, c->stream));
+  if (int r = lens_filter_passes<R>(c)) return r;
+  const LensDev p = lens_dev(d, l);
   const int64_t off = c->inst[b].off;
   HIP_TRY(launch_lens_apply<R>(static_cast<char*>(c->field(c->L.S)) + off * c->el,
                                static_cast<const char*>(c->field(c->L.Wk)) + off * c->el,
@@ -1722,9 +1777,8 @@ int ssfm_set_subharmonics(ssfm_ctx* c, int32_t inst, int32_t levels) {
   return SSFM_OK;
 }
 
-int ssfm_apply_lens(ssfm_ctx* c, int32_t inst, const ssfm_lens* lens) {
-  if (int r = check_inst(c, inst)) return r;
-  if (int r = lie_only(c, "the effective lens")) return r;
+namespace {
+int check_lens(const ssfm_lens* lens) {
   if (!lens) return fail(SSFM_EINVAL, "lens is NULL");
   const ssfm_lens& l = *lens;
   if (!(l.l_dif >= 0.0) || !std::isfinite(l.l_dif) || !std::isfinite(l.w_l) ||
@@ -1744,7 +1798,29 @@ int ssfm_apply_lens(ssfm_ctx* c, int32_t inst, const ssfm_lens* lens) {
       lo = seg[j][0];
     }
   }
-  return SSFM_DISPATCH(c, do_apply_lens, c, inst, l);
+  return SSFM_OK;
+}
+}  // namespace
+
+int ssfm_apply_lens(ssfm_ctx* c, int32_t inst, const ssfm_lens* lens) {
+  if (int r = check_inst(c, inst)) return r;
+  if (int r = lie_only(c, "the effective lens")) return r;
+  if (int r = check_lens(lens)) return r;
+  return SSFM_DISPATCH(c, do_apply_lens, c, inst, *lens);
+}
+
+int ssfm_lens_vjp(ssfm_ctx* c, int32_t inst, const ssfm_lens* lens, const void* u_in,
+                  const void* g_out, void* g_in, double* grad, int32_t n_grad) {
+  if (int r = check_inst(c, inst)) return r;
+  if (int r = check_lens(lens)) return r;
+  if (!u_in || !g_out || !g_in || !grad)
+    return fail(SSFM_EINVAL, "u_in, g_out, g_in and grad must not be NULL");
+  const int need = 2 + 3 * (lens->n_re + lens->n_im);
+  if (n_grad < need)
+    return fail(SSFM_EINVAL, "grad holds %d values, the lens has %d parameters", n_grad, need);
+  return SSFM_DISPATCH(c, do_lens_vjp, c, inst, *lens, static_cast<const double*>(u_in),
+                       static_cast<const double*>(g_out), static_cast<double*>(g_in), grad,
+                       n_grad);
 }
 
 int ssfm_hot_areas(ssfm_ctx* c, const double* w, int32_t n, double threshold, int32_t periodic,

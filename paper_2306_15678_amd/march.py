@@ -237,6 +237,24 @@ class Propagator:
         """Apply the effective-lens screen to instance i's current field."""
         L.call("ssfm_apply_lens", self.ctx, i, ctypes.byref(lens))
 
+    def lens_vjp(self, i: int, lens: L.LensParams, u_in, g_out):
+        """(g_in, grad) of the lens applied to u_in, for the output cotangent
+        g_out (G = dL/dRe U + i dL/dIm U): g_in on the device, grad =
+        dL/d(c1, c2, then amplitude, frequency, phase of each real segment,
+        then of each imaginary one)."""
+        n = self._n(i)
+        u = torch.as_tensor(u_in).to(self.device, torch.complex128).contiguous()
+        g = torch.as_tensor(g_out).to(self.device, torch.complex128).contiguous()
+        if u.shape != (n, n) or g.shape != (n, n):
+            raise ValueError(f"u_in and g_out must be {n} x {n}")
+        g_in = torch.empty_like(u)
+        k = 2 + 3 * (lens.n_re + lens.n_im)
+        grad = (ctypes.c_double * k)()
+        torch.cuda.synchronize(self.device)     # inputs written on torch's streams
+        L.call("ssfm_lens_vjp", self.ctx, i, ctypes.byref(lens), ctypes.c_void_p(u.data_ptr()),
+               ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(g_in.data_ptr()), grad, k)
+        return g_in, np.array(list(grad))
+
     def hot_areas(self, w: torch.Tensor, threshold: float, periodic: bool = True) -> int:
         """Number of hot areas: 4-connected regions with w >= threshold
         [W/m^2] of an n x n float64 fluence on this device."""

@@ -130,3 +130,84 @@ def test_lens_ends_the_recorded_march_and_rejects_bad_parameters():
         p.apply_lens(0, _to_gpu(LN.Lens(-1.0, 0, -1, 0, [], [])))
     assert e.value.status == EINVAL
     p.close()
+
+
+def _vjp_setup(precision):
+    inst = W.config1()[0]
+    p = _prop([inst], precision, max_steps=40, ckpt_every=10)
+    p.set_field(0, W.initial_field(inst))
+    p.propagate(100)
+    u = p.field(0)
+    return inst, p, u, _lens_params(inst, u, True)
+
+
+@pytest.mark.parametrize("precision,tol_g,tol_p", [(64, 1e-12, 1e-11), (32, 2e-5, 1e-4)])
+def test_lens_vjp_matches_oracle(precision, tol_g, tol_p):
+    inst, p, u, lens = _vjp_setup(precision)
+    rng = np.random.default_rng(7)
+    g = rng.standard_normal(u.shape) + 1j * rng.standard_normal(u.shape)
+    g_in, grad = p.lens_vjp(0, _to_gpu(lens), u, g)
+    want_g, want_p = LN.lens_vjp(u, g, inst.length, lens)
+    err_g = float(np.linalg.norm(g_in.cpu().numpy() - want_g) / np.linalg.norm(want_g))
+    err_p = np.abs(grad - want_p) / np.abs(want_p)
+    print(f"lens vjp fp{precision}: g_in {err_g:.2e}, parameter gradients max rel "
+          f"{err_p.max():.2e} ({len(grad)} values)", flush=True)
+    assert err_g < tol_g and err_p.max() < tol_p
+    # the context's own field is untouched
+    assert np.array_equal(p.field(0), u)
+    p.close()
+
+
+def test_lens_vjp_composes_with_the_recorded_march():
+    """FP64: march 60 steps -> lens -> recorded march 20 steps -> fluence
+    loss.  backward gives the cotangent at the lens output, lens_vjp the
+    lens-parameter gradients and the cotangent at its input, a re-recorded
+    first march with that cotangent the gradient in the initial field; all
+    against central finite differences of the whole pipeline."""
+    inst = W.config1()[0]
+    u0 = W.initial_field(inst)
+    target = W.synthetic_target(inst, 3)
+    p = _prop([inst], 64, max_steps=60, ckpt_every=20)
+    p.set_field(0, u0)
+    p.propagate(60)
+    u1 = p.field(0)
+    base = _lens_params(inst, u1, True)
+
+    def loss(lens, start=u0):
+        p.set_field(0, start)
+        p.propagate(60)
+        p.apply_lens(0, _to_gpu(lens))
+        p.forward_record(20)
+        return p.fluence_loss(0, target)
+
+    loss(base)
+    p.backward()
+    g_out = p.grad_field(0)
+    g_in, grad = p.lens_vjp(0, _to_gpu(base), u1, g_out)
+    # parameters: c2, the real amplitude and the imaginary frequency
+    for k, name in ((1, "c2"), (2, "re.a"), (6, "im.nu")):
+        vals = [base.c1, base.c2, *base.re[0][1:], *base.im[0][1:]]
+        h = 1e-6 * abs(vals[k])
+
+        def shifted(dv):
+            v = list(vals)
+            v[k] += dv
+            return LN.Lens(base.l_dif, base.w_l, v[0], v[1], [(base.re[0][0], v[2], v[3], v[4])],
+                           [(base.im[0][0], v[5], v[6], v[7])])
+
+        fd = (loss(shifted(h)) - loss(shifted(-h))) / (2 * h)
+        print(f"lens gradient {name}: adjoint {grad[k]:.6e} finite difference {fd:.6e}", flush=True)
+        assert abs(fd / grad[k] - 1) < 1e-5
+    # the initial field, through the lens input cotangent
+    p.set_field(0, u0)
+    p.forward_record(60)
+    p.set_cotangent(0, g_in)
+    p.backward()
+    g0 = p.grad_field(0)
+    d = np.random.default_rng(5).standard_normal(u0.shape) * np.abs(u0)
+    h = 1e-6
+    fd = (loss(base, u0 + h * d) - loss(base, u0 - h * d)) / (2 * h)
+    adj = float(np.real(np.sum(np.conj(g0) * d)))
+    print(f"dL/dU0 along a direction: adjoint {adj:.6e} finite difference {fd:.6e}", flush=True)
+    assert abs(fd / adj - 1) < 1e-5
+    p.close()
