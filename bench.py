@@ -266,8 +266,18 @@ def time_diagnostics(p, inst, args):
     for _ in range(reps):
         p.apply_lens(0, lens)
     t_lens = (time.perf_counter() - t0) / reps
+    # its vector-Jacobian product (input cotangent and parameter gradients)
+    import torch
+    u = p.field(0, device=True)
+    g = torch.ones_like(u)
+    p.lens_vjp(0, lens, u, g)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p.lens_vjp(0, lens, u, g)
+    t_vjp = (time.perf_counter() - t0) / reps
     out = {"grid": inst.n, "threshold_of_peak": 0.01, "hot_areas": count,
-           "hot_areas_us": t_hot * 1e6, "moment_us": t_mom * 1e6, "lens_us": t_lens * 1e6}
+           "hot_areas_us": t_hot * 1e6, "moment_us": t_mom * 1e6, "lens_us": t_lens * 1e6,
+           "lens_vjp_us": t_vjp * 1e6}
     if not args.no_cpu:
         from oracle import diagnostics as D
         wh = w.cpu().numpy()
