@@ -210,3 +210,26 @@ def test_state_handling_and_refusals():
         q.set_finite_difference(4)
     assert e.value.status == EUNSUPPORTED
     q.close()
+
+
+def test_mixed_size_batch_equals_each_beam_alone():
+    """Beams of 128^2 and 256^2 in one context run as two size groups (one
+    launch per group and pass, on forked streams): each beam's field and
+    diagnostics equal its own single-beam march bitwise."""
+    a = W.config1()[0]
+    b = _strong(W.KPM, n=256)
+    insts = [a, b, a]
+    u = [W.initial_field(i) for i in insts]
+    p = _fd(insts, 32, 4)
+    for k, x in enumerate(u):
+        p.set_field(k, x)
+    p.propagate(12)
+    got = [(p.field(k), p.diag(k, 12)) for k in range(3)]
+    p.close()
+    for k, inst in enumerate(insts):
+        q = _fd([inst], 32, 4)
+        q.set_field(0, u[k])
+        q.propagate(12)
+        assert np.array_equal(q.field(0), got[k][0])
+        assert all(np.array_equal(x, y) for x, y in zip(q.diag(0, 12), got[k][1]))
+        q.close()

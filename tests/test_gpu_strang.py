@@ -129,3 +129,24 @@ def test_lie_only_entry_points_refuse_strang():
     p.set_field(0, W.initial_field(inst))
     p.forward_record(10)
     p.close()
+
+
+def test_strang_mixed_size_batch_equals_each_beam_alone():
+    small = W.config1()[0]
+    big = [b for b in W.config3() if b.n == 256][0]
+    insts = [big, small]
+    u = [W.initial_field(i) for i in insts]
+    p = _strang(insts, 32)
+    p.gen_screens()
+    for k, x in enumerate(u):
+        p.set_field(k, x)
+    p.propagate(30)
+    got = [p.field(k) for k in range(2)]
+    p.close()
+    for k, inst in enumerate(insts):
+        q = _strang([inst], 32)
+        q.gen_screens()
+        q.set_field(0, u[k])
+        q.propagate(30)
+        assert np.array_equal(q.field(0), got[k])
+        q.close()

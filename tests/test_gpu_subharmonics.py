@@ -135,3 +135,26 @@ def test_zero_levels_leave_screens_unchanged_and_range_is_checked():
             p.set_subharmonics(0, bad)
         assert e.value.status == EINVAL
     p.close()
+
+
+def test_mixed_batch_screens_equal_each_beam_alone():
+    """Three beams of different grids, each with its own level count, in one
+    context: every screen equals the one its beam gets alone (the scratch of
+    one beam's pair does not reach another's)."""
+    by_n = {}
+    for b in W.config3():
+        by_n.setdefault(b.n, b)
+    insts = [by_n[256], by_n[512], by_n[768]]
+    levels = [3, 0, 5]
+    p = Propagator([desc_of(i) for i in insts], precision=32)
+    for k, lv in enumerate(levels):
+        p.set_subharmonics(k, lv)
+    p.gen_screens()
+    for k, inst in enumerate(insts):
+        q = Propagator([desc_of(inst)], precision=32)
+        q.set_subharmonics(0, levels[k])
+        q.gen_screens()
+        for s in range(inst.n_screens):
+            assert np.array_equal(q.screen(0, s), p.screen(k, s)), (k, s)
+        q.close()
+    p.close()
