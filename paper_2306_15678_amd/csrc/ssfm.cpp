@@ -1149,7 +1149,7 @@ LensDev lens_dev(const ssfm_instance_desc& d, const ssfm_lens& l) {
 // and the fixed-order parameter sums (partials and sums in the staging area).
 template <typename R>
 int do_lens_vjp(ssfm_ctx* c, int b, const ssfm_lens& l, const double* u, const double* g_out,
-                double* g_in, double* grad, int n_grad) {
+                double* g_in, double* grad) {
   const ssfm_instance_desc& d = c->desc[b];
   const int64_t n2 = int64_t(d.n) * d.n;
   void* wk = static_cast<char*>(c->field(c->L.Wk)) + c->inst[b].off * int64_t(c->el);
@@ -1173,7 +1173,6 @@ int do_lens_vjp(ssfm_ctx* c, int b, const ssfm_lens& l, const double* u, const d
     for (int q = 0; q < 3; ++q) grad[k++] = all[2 + 3 * j + q];
   for (int j = 0; j < l.n_im; ++j)
     for (int q = 0; q < 3; ++q) grad[k++] = all[26 + 3 * j + q];
-  (void)n_grad;
   return SSFM_OK;
 }
 
@@ -1819,8 +1818,7 @@ int ssfm_lens_vjp(ssfm_ctx* c, int32_t inst, const ssfm_lens* lens, const void* 
   if (n_grad < need)
     return fail(SSFM_EINVAL, "grad holds %d values, the lens has %d parameters", n_grad, need);
   return SSFM_DISPATCH(c, do_lens_vjp, c, inst, *lens, static_cast<const double*>(u_in),
-                       static_cast<const double*>(g_out), static_cast<double*>(g_in), grad,
-                       n_grad);
+                       static_cast<const double*>(g_out), static_cast<double*>(g_in), grad);
 }
 
 int ssfm_hot_areas(ssfm_ctx* c, const double* w, int32_t n, double threshold, int32_t periodic,
