@@ -108,15 +108,17 @@ def _check(name, precision, got, ref, u0, inst, steps, iters):
     assert err < bounds[0] and perr < bounds[1] and kerr < bounds[2]
 
 
-@pytest.mark.parametrize("precision", [64, 32])
-def test_kerr_beam_matches_oracle(precision):
+@pytest.mark.parametrize("precision,iters", [(64, 4), (32, 4), (64, 1), (32, 1)])
+def test_kerr_beam_matches_oracle(precision, iters):
+    """K = 4, and K = 1: one solve per step, the linearly implicit limit."""
     inst = W.config1()[0]                      # 128^2, 5 P_cr, Kerr
     u0 = W.initial_field(inst)
-    ref = FD.fd_march(u0, inst, 50, iterations=4)
-    p = _fd([inst], precision, 4)
+    ref = FD.fd_march(u0, inst, 50, iterations=iters)
+    p = _fd([inst], precision, iters)
     p.set_field(0, u0)
     p.propagate(50)
-    _check("kerr 50 steps", precision, (p.field(0), p.diag(0, 50)), ref, u0, inst, 50, 4)
+    _check(f"kerr 50 steps K={iters}", precision, (p.field(0), p.diag(0, 50)), ref, u0, inst,
+           50, iters)
     p.close()
 
 
@@ -233,3 +235,24 @@ def test_mixed_size_batch_equals_each_beam_alone():
         assert np.array_equal(q.field(0), got[k][0])
         assert all(np.array_equal(x, y) for x, y in zip(q.diag(0, 12), got[k][1]))
         q.close()
+
+
+def test_largest_grid_conserves_power():
+    """4096^2 (the largest plan), the multifilamentation beam's shape on a
+    window of 4096 cells, Kerr and plasma, FP64 with converged iterations:
+    power conserved to rounding over 3 steps."""
+    base = W.config2()[0]
+    inst = dataclasses.replace(base, n=4096, dz=2e-3,
+                               medium=dataclasses.replace(base.medium,
+                                                          terms=W.TERM_KERR | W.TERM_PLASMA))
+    u0 = W.initial_field(inst)
+    p = _fd([inst], 64, 12)
+    p.set_field(0, u0)
+    p.propagate(3)
+    pw, _ = p.diag(0, 3)
+    p0 = float(np.sum(np.abs(u0) ** 2)) * inst.dx ** 2
+    drift = float(np.max(np.abs(pw / p0 - 1)))
+    moved = M.rel_l2(p.field(0), u0)
+    print(f"fd fp64 4096^2: power drift {drift:.2e}, field moved {moved:.2e}", flush=True)
+    assert drift < 1e-12 and moved > 1e-4
+    p.close()

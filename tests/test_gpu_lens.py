@@ -211,3 +211,14 @@ def test_lens_vjp_composes_with_the_recorded_march():
     print(f"dL/dU0 along a direction: adjoint {adj:.6e} finite difference {fd:.6e}", flush=True)
     assert abs(fd / adj - 1) < 1e-5
     p.close()
+
+
+def test_lens_without_segments_has_an_identity_vjp():
+    """No profile segments: f = 0 everywhere, so E = 1, the input cotangent
+    is the output cotangent and the two gradients (c1, c2) vanish."""
+    inst, p, u, lens = _vjp_setup(64)
+    empty = LN.Lens(lens.l_dif, lens.w_l, lens.c1, lens.c2, [], [])
+    g = np.random.default_rng(8).standard_normal(u.shape) + 0j
+    g_in, grad = p.lens_vjp(0, _to_gpu(empty), u, g)
+    assert np.array_equal(g_in.cpu().numpy(), g) and len(grad) == 2 and not grad.any()
+    p.close()

@@ -158,3 +158,20 @@ def test_mixed_batch_screens_equal_each_beam_alone():
             assert np.array_equal(q.screen(0, s), p.screen(k, s)), (k, s)
         q.close()
     p.close()
+
+
+def test_eight_levels_on_the_smallest_grid():
+    """The maximum level count on a 128^2 grid (whose work-buffer slice is
+    the smallest scratch): the low part against the oracle in FP64.  Level 8
+    modes are ~1500x level 1's and nearly constant over the window, so the
+    cancellation against the mean leaves their rounding: 1e-11 of the low
+    part's range."""
+    inst = dataclasses.replace(_inst(), n=128)
+    with_sh = _screens(inst, 64, 8)
+    without = _screens(inst, 64, 0)
+    want = T.subharmonic_pair(inst.n, inst.length, _modes(inst, 8), inst.seed, 0)
+    for k in range(2):
+        got = with_sh[k] - without[k]
+        err = float(np.max(np.abs(got - want[k])) / np.max(np.abs(want[k])))
+        print(f"8 levels, 128^2, screen {k}: maxrel={err:.2e}", flush=True)
+        assert err < 1e-11
