@@ -428,8 +428,8 @@ def main():
                          "tuning them (FP32 march only)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the march of one beam or a "
-              "batch lives on one device; no multi-GPU path is built)", file=sys.stderr)
+        print("bench.py: measures one GPU only (the march of one beam or a batch lives "
+              "on one device; there is no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     import workloads as W
     inst = W.config2()[0]
