@@ -222,3 +222,56 @@ def test_lens_without_segments_has_an_identity_vjp():
     g_in, grad = p.lens_vjp(0, _to_gpu(empty), u, g)
     assert np.array_equal(g_in.cpu().numpy(), g) and len(grad) == 2 and not grad.any()
     p.close()
+
+
+def test_torch_autograd_through_march_lens_march():
+    """march 60 -> lens -> march 20 -> a fluence loss written in torch, all
+    through torch autograd (two contexts, FP64): gradients of two lens
+    parameters and of U0 along a direction against central differences."""
+    import torch
+
+    from paper_2306_15678_amd import autograd as AG
+
+    inst = W.config1()[0]
+    dev = torch.device("cuda", 0)
+    u0 = torch.from_numpy(W.initial_field(inst)).to(dev)
+    target = torch.from_numpy(W.synthetic_target(inst, 3)).to(dev)
+    theta = torch.zeros(8, dtype=torch.float64)
+    p1 = _prop([inst], 64, max_steps=60, ckpt_every=20)
+    p2 = _prop([inst], 64, max_steps=20, ckpt_every=20)
+    p1.set_field(0, u0)
+    p1.propagate(60)
+    template = _to_gpu(_lens_params(inst, p1.field(0), True))
+    base = AG.lens_params_vector(template)
+
+    def pipeline(u, params):
+        u1 = AG.march(u, theta, p1, 60)
+        u2 = AG.lens(u1, params, p2, 0, template)
+        u3 = AG.march(u2, theta, p2, 20)
+        return torch.sum((u3.abs() ** 2 - target) ** 2) / torch.sum(target ** 2)
+
+    u = u0.clone().requires_grad_(True)
+    params = torch.tensor(base, dtype=torch.float64, requires_grad=True)
+    pipeline(u, params).backward()
+    with torch.no_grad():
+        for k, name in ((1, "c2"), (2, "re.a")):
+            h = 1e-6 * abs(base[k])
+            up, dn = list(base), list(base)
+            up[k] += h
+            dn[k] -= h
+            fd = (pipeline(u0, torch.tensor(up, dtype=torch.float64))
+                  - pipeline(u0, torch.tensor(dn, dtype=torch.float64))).item() / (2 * h)
+            got = params.grad[k].item()
+            print(f"torch lens gradient {name}: autograd {got:.6e} finite difference {fd:.6e}",
+                  flush=True)
+            assert abs(fd / got - 1) < 1e-5
+        d = torch.from_numpy(np.random.default_rng(6).standard_normal(u0.shape)).to(dev) * u0.abs()
+        h = 1e-6
+        p_base = torch.tensor(base, dtype=torch.float64)
+        fd = (pipeline(u0 + h * d, p_base) - pipeline(u0 - h * d, p_base)).item() / (2 * h)
+        adj = torch.sum(torch.real(torch.conj(u.grad) * d)).item()
+        print(f"torch dL/dU0 along a direction: autograd {adj:.6e} finite difference {fd:.6e}",
+              flush=True)
+        assert abs(fd / adj - 1) < 1e-5
+    p1.close()
+    p2.close()
