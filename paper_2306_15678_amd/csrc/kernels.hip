@@ -583,34 +583,35 @@ template hipError_t launch_noise<float>(const InstDev*, int, int, int, uint64_t,
 template hipError_t launch_noise<double>(const InstDev*, int, int, int, uint64_t, double, int,
                                          double, double, void*, hipStream_t);
 
-// Subharmonic part of one screen pair in two kernels.  Setup (one
-// workgroup): thread t < 8 levels draws mode t (level p = t / 8 + 1, cell q =
-// the t % 8-th of the 3 x 3 cells around f = 0 without the centre, (mx, my) =
-// (q % 3 - 1, q / 3 - 1), spacing df = 1 / (3^p L)) from Philox counter
-// (q, p, pair, 1) and stores w = c sqrt(density) df; thread 0 forms the grid
-// mean of sum w e^{2 pi i f.x} (the mean of exp(2 pi i m df x) over the
-// cell-centred grid x_j = (j + 1/2 - n/2) L/n is sin(pi/3^p) /
-// (n sin(pi/(3^p n))) for |m| = 1, 1 for m = 0); all threads fill the axis
-// table e_p[j] = exp(2 pi i (j + 1/2 - n/2) / (3^p n)), the same for rows and
-// columns of the square grid.  Apply: every point adds Re / Im of
+// Subharmonic part of the screens, for all beams at once.  Coefficients
+// (grid: pairs x beams, one workgroup each): thread t < 8 levels draws mode t
+// (level p = t / 8 + 1, cell q = the t % 8-th of the 3 x 3 cells around f = 0
+// without the centre, (mx, my) = (q % 3 - 1, q / 3 - 1), spacing df =
+// 1 / (3^p L)) from Philox counter (q, p, pair, 1) and stores w = c
+// sqrt(density) df; the grid mean of sum w e^{2 pi i f.x} is formed from
+// the w (the mean of exp(2 pi i m df x) over the cell-centred grid x_j =
+// (j + 1/2 - n/2) L/n is g_p = sin(pi/3^p) / (n sin(pi/(3^p n))) for |m| = 1,
+// 1 for m = 0), each mode's share by its own thread, summed in fixed order.
+// Tables (grid: blocks x beams): e_p[j] = exp(2 pi i (j + 1/2 - n/2) /
+// (3^p n)), the same for rows and columns of the square grid.  Apply (grid:
+// blocks x beams, one launch per pair): every point adds Re / Im of
 // sum w e_p[col]^mx e_p[row]^my - mean to its two planes, in FP64.
-// Scratch layout (doubles): w (re, im) at [0, 128), mean at [128, 130), the
-// axis tables (re, im) from kSubTab on, level-major.
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_subharm_setup(const InstDev* inst, int b, int pair,
-                                                      uint32_t k0, uint32_t k1,
-                                                      SubharmonicSpec sp,
-                                                      double* __restrict__ scr) {
-  __shared__ double wre[8 * kMaxSubharmonicLevels], wim[8 * kMaxSubharmonicLevels];
-  const int n = inst[b].n;
+__global__ void __launch_bounds__(256) k_subharm_coef(const SubBeam* __restrict__ beams,
+                                                     double* __restrict__ region) {
+  __shared__ double sre[8 * kMaxSubharmonicLevels], sim[8 * kMaxSubharmonicLevels];
+  const SubBeam sb = beams[blockIdx.y];
+  const int pair = blockIdx.x;
+  if (pair >= sb.pairs) return;
+  const SubharmonicSpec& sp = sb.sp;
+  const int n = sb.n;
   const int nm = 8 * sp.levels;
   const int t = threadIdx.x;
+  double* blk = region + sb.coef_off + int64_t(kSubPair) * pair;
   if (t < nm) {
     const int p = t / 8 + 1, j = t % 8, q = (j < 4) ? j : j + 1;
     const int mx = q % 3 - 1, my = q / 3 - 1;
     uint32_t c[4] = {uint32_t(q), uint32_t(p), uint32_t(pair), 1u};
-    philox4x32_10(c, k0, k1);
+    philox4x32_10(c, sb.k0, sb.k1);
     const double u1 = (double(c[0]) + 0.5) * 2.3283064365386962890625e-10;
     const double u2 = (double(c[1]) + 0.5) * 2.3283064365386962890625e-10;
     const double rr = sqrt(-2.0 * log(u1));
@@ -631,50 +632,61 @@ __global__ void __launch_bounds__(256) k_subharm_setup(const InstDev* inst, int 
         a = sqrt(0.023 * pow(sp.r0, -5.0 / 3.0) * pow(hypot(fx, fy), -11.0 / 3.0)) * df;
       }
     }
-    wre[t] = rr * cs * a;
-    wim[t] = rr * sn * a;
-    scr[2 * t] = wre[t];
-    scr[2 * t + 1] = wim[t];
+    const double wr = rr * cs * a, wi = rr * sn * a;
+    blk[2 * t] = wr;
+    blk[2 * t + 1] = wi;
+    const double g = sinpi(1.0 / pow3) / (double(n) * sinpi(1.0 / (pow3 * n)));
+    const double f = ((mx == 0) ? 1.0 : g) * ((my == 0) ? 1.0 : g);
+    sre[t] = wr * f;
+    sim[t] = wi * f;
   }
   __syncthreads();
   if (t == 0) {
     double mre = 0.0, mim = 0.0;
     for (int m = 0; m < nm; ++m) {
-      const int p = m / 8 + 1, j = m % 8, q = (j < 4) ? j : j + 1;
-      double pow3 = 1.0;
-      for (int i = 0; i < p; ++i) pow3 *= 3.0;
-      const double g = sinpi(1.0 / pow3) / (double(n) * sinpi(1.0 / (pow3 * n)));
-      const double f = ((q % 3 == 1) ? 1.0 : g) * ((q / 3 == 1) ? 1.0 : g);
-      mre += wre[m] * f;
-      mim += wim[m] * f;
+      mre += sre[m];
+      mim += sim[m];
     }
-    scr[128] = mre;
-    scr[129] = mim;
+    blk[128] = mre;
+    blk[129] = mim;
   }
-  for (int k = t; k < sp.levels * n; k += blockDim.x) {
-    const int p = k / n, j = k - p * n;
+}
+
+__global__ void __launch_bounds__(256) k_subharm_table(const SubBeam* __restrict__ beams,
+                                                      double* __restrict__ region) {
+  const SubBeam sb = beams[blockIdx.y];
+  const int n = sb.n;
+  const int64_t total = int64_t(sb.sp.levels) * n;
+  double* tab = region + sb.tab_off;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < total;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    const int p = int(k / n), j = int(k - int64_t(p) * n);
     double pow3 = 3.0;
     for (int i = 0; i < p; ++i) pow3 *= 3.0;
     double sn, cs;
     sincospi(2.0 * (double(j) + 0.5 - 0.5 * n) / (pow3 * n), &sn, &cs);
-    scr[kSubTab + 2 * k] = cs;
-    scr[kSubTab + 2 * k + 1] = sn;
+    tab[2 * k] = cs;
+    tab[2 * k + 1] = sn;
   }
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_subharm_apply(const InstDev* inst, int b, int pair,
-                                                      int levels, const double* __restrict__ scr,
+__global__ void __launch_bounds__(256) k_subharm_apply(const SubBeam* __restrict__ beams,
+                                                      const InstDev* __restrict__ inst, int pair,
+                                                      const double* __restrict__ region,
                                                       R* __restrict__ planes) {
-  __shared__ double w[2 * 8 * kMaxSubharmonicLevels + 2];
-  const InstDev& in = inst[b];
-  const int n = in.n;
-  const int nw = 2 * 8 * levels;
-  for (int k = threadIdx.x; k < nw; k += blockDim.x) w[k] = scr[k];
-  if (threadIdx.x < 2) w[2 * 8 * kMaxSubharmonicLevels + threadIdx.x] = scr[128 + threadIdx.x];
+  __shared__ double w[kSubPair];
+  const SubBeam sb = beams[blockIdx.y];
+  if (pair >= sb.pairs) return;
+  const InstDev& in = inst[sb.inst];
+  const int n = sb.n;
+  const int levels = sb.sp.levels;
+  const double* blk = region + sb.coef_off + int64_t(kSubPair) * pair;
+  for (int k = threadIdx.x; k < 16 * levels; k += blockDim.x) w[k] = blk[k];
+  if (threadIdx.x < 2) w[128 + threadIdx.x] = blk[128 + threadIdx.x];
   __syncthreads();
-  const double mre = w[2 * 8 * kMaxSubharmonicLevels], mim = w[2 * 8 * kMaxSubharmonicLevels + 1];
-  const double* __restrict__ tab = scr + kSubTab;
+  const double mre = w[128], mim = w[129];
+  const double* __restrict__ tab = region + sb.tab_off;
   const int64_t n2 = int64_t(n) * n;
   R* pre = planes + in.screen_off + int64_t(2 * pair) * n2;
   R* pim = pre + n2;
@@ -686,8 +698,8 @@ __global__ void __launch_bounds__(256) k_subharm_apply(const InstDev* inst, int 
     for (int p = 0; p < levels; ++p) {
       const double xr = tab[2 * (p * n + col)], xi = tab[2 * (p * n + col) + 1];
       const double yr = tab[2 * (p * n + row)], yi = tab[2 * (p * n + row) + 1];
-      // e^{i a} for the 3 x-exponents (-1, 0, 1) and y-exponents, combined
-      // per cell; cells in the order q = 0..8 without q = 4
+      // e^{i a} for the x-exponents (-1, 0, 1) and y-exponents, combined per
+      // cell; cells in the order q = 0..8 without q = 4
       const double exr[3] = {xr, 1.0, xr}, exi[3] = {-xi, 0.0, xi};
       const double eyr[3] = {yr, 1.0, yr}, eyi[3] = {-yi, 0.0, yi};
       const double* wp = w + 16 * p;
@@ -706,23 +718,28 @@ __global__ void __launch_bounds__(256) k_subharm_apply(const InstDev* inst, int 
   }
 }
 
-template <typename R>
-hipError_t launch_subharmonics(const InstDev* inst, int b, int n, int pair, uint64_t seed,
-                               const SubharmonicSpec& spec, void* planes, void* scratch,
-                               hipStream_t s) {
-  if (spec.levels < 1 || spec.levels > kMaxSubharmonicLevels) return hipErrorInvalidValue;
-  double* scr = static_cast<double*>(scratch);
-  hipLaunchKernelGGL((k_subharm_setup<R>), dim3(1), dim3(256), 0, s, inst, b, pair,
-                     uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32), spec, scr);
-  hipLaunchKernelGGL((k_subharm_apply<R>), dim3(grid_for(int64_t(n) * n, 256)), dim3(256), 0, s,
-                     inst, b, pair, int(spec.levels), static_cast<const double*>(scr),
-                     static_cast<R*>(planes));
+hipError_t launch_subharmonic_setup(const SubBeam* beams, int n_beams, int max_pairs,
+                                    int64_t max_table, double* region, hipStream_t s) {
+  if (n_beams <= 0 || max_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_subharm_coef, dim3(max_pairs, n_beams), dim3(256), 0, s, beams, region);
+  hipLaunchKernelGGL(k_subharm_table, dim3(grid_for(max_table, 256), n_beams), dim3(256), 0, s,
+                     beams, region);
   return hipGetLastError();
 }
-template hipError_t launch_subharmonics<float>(const InstDev*, int, int, int, uint64_t,
-                                               const SubharmonicSpec&, void*, void*, hipStream_t);
-template hipError_t launch_subharmonics<double>(const InstDev*, int, int, int, uint64_t,
-                                                const SubharmonicSpec&, void*, void*, hipStream_t);
+
+template <typename R>
+hipError_t launch_subharmonic_apply(const SubBeam* beams, int n_beams, const InstDev* inst,
+                                    int pair, int64_t max_n2, const double* region, void* planes,
+                                    hipStream_t s) {
+  if (n_beams <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_subharm_apply<R>), dim3(std::min(grid_for(max_n2, 256), 4096), n_beams),
+                     dim3(256), 0, s, beams, inst, pair, region, static_cast<R*>(planes));
+  return hipGetLastError();
+}
+template hipError_t launch_subharmonic_apply<float>(const SubBeam*, int, const InstDev*, int,
+                                                    int64_t, const double*, void*, hipStream_t);
+template hipError_t launch_subharmonic_apply<double>(const SubBeam*, int, const InstDev*, int,
+                                                     int64_t, const double*, void*, hipStream_t);
 
 template <typename R>
 __global__ void k_plane_f64(const R* __restrict__ p, int64_t n, double* __restrict__ d) {

@@ -91,7 +91,7 @@ struct Layout {
   size_t inst, steps, work, wbegin_row, wbegin_col, tables;
   size_t S, Wk, Wk2, Lam, ckpt, stack, screens, stage, diag_part, diag, theta_acc,
       theta_out, seed_loss, seed_theta, scal, sumsq_part, lens_inst, half_inst, back_inst,
-      fd_inst;
+      fd_inst, subh, subh_beams;
   size_t total;
   int64_t field_elems;  // sum n^2
   int64_t table_elems;
@@ -129,6 +129,7 @@ struct ssfm_ctx {
   bool fd = false;
   int fd_iters = 4;
   std::vector<int64_t> fd_off;
+  std::vector<SubBeam> sub_beams;  // host copy of the last uploaded subharmonic list
   struct Spectrum {
     int kind = SSFM_SPECTRUM_KOLMOGOROV;
     double tau = 0.0, kappa_h = 0.0;
@@ -323,7 +324,7 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
     nc_max += max_items(true, d[b].n, precision == SSFM_FP64);
   }
   Layout l{};
-  int64_t fe = 0, te = 0, se = 0, nsteps = 0;
+  int64_t fe = 0, te = 0, se = 0, nsteps = 0, subh_doubles = 0;
   int max_n = 0;
   std::vector<int> tw_done;
   for (int b = 0; b < n_inst; ++b) {
@@ -338,6 +339,7 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
     if (d[b].terms & SSFM_TURB) {
       se += int64_t(d[b].n_screens) * d[b].n * d[b].n;
       nsteps += d[b].n_screens;
+      subh_doubles += subharmonic_region_doubles(d[b].n, (d[b].n_screens + 1) / 2);
     }
   }
   l.field_elems = fe;
@@ -394,6 +396,9 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
   l.half_inst = take(sizeof(InstDev) * n_inst);
   l.back_inst = take(sizeof(InstDev) * n_inst);
   l.fd_inst = take(sizeof(InstDev) * n_inst);
+  // subharmonic tables and coefficients of every turbulent beam, its beam list
+  l.subh = take(sizeof(double) * size_t(subh_doubles));
+  l.subh_beams = take(sizeof(SubBeam) * n_inst);
   l.total = off;
   if (groups_out) *groups_out = groups;
   if (work_out) *work_out = work;
@@ -923,6 +928,51 @@ int do_gen_screens(ssfm_ctx* c) {
   int max_pairs = 0;
   for (auto& d : c->desc)
     if ((d.terms & SSFM_TURB) && d.n_screens > 0) max_pairs = std::max(max_pairs, (d.n_screens + 1) / 2);
+  // beams with subharmonic levels: coefficients, means and axis tables for
+  // all their pairs up front (the region is laid out over every turbulent
+  // beam in order), then one apply launch per pair after its inverse DFT
+  std::vector<SubBeam>& sub = c->sub_beams;
+  // the previous list may still be in an asynchronous upload
+  if (!sub.empty()) HIP_TRY(hipStreamSynchronize(c->stream));
+  sub.clear();
+  int64_t region_off = 0, max_table = 0, max_n2 = 0;
+  int sub_pairs = 0;
+  for (size_t b = 0; b < c->desc.size(); ++b) {
+    const ssfm_instance_desc& d = c->desc[b];
+    if (!(d.terms & SSFM_TURB) || d.n_screens <= 0) continue;
+    const int pairs = (d.n_screens + 1) / 2;
+    const int64_t off = region_off;
+    region_off += subharmonic_region_doubles(d.n, pairs);
+    const ssfm_ctx::Spectrum& sp = c->spectrum[b];
+    if (sp.subharmonics == 0 || (sp.kind != SSFM_SPECTRUM_STEP && !(d.cn2 > 0))) continue;
+    SubBeam e{};
+    e.inst = int32_t(b);
+    e.n = d.n;
+    e.pairs = pairs;
+    e.k0 = uint32_t(d.seed & 0xffffffffu);
+    e.k1 = uint32_t(d.seed >> 32);
+    e.sp.levels = sp.subharmonics;
+    e.sp.kind = sp.kind;
+    const double k0 = 2.0 * M_PI / d.wavelength;
+    e.sp.r0 = (sp.kind == SSFM_SPECTRUM_STEP) ? 0.0
+                                               : std::pow(0.423 * k0 * k0 * d.cn2 * d.screen_dz, -0.6);
+    e.sp.tau = sp.tau;
+    e.sp.kappa_h = sp.kappa_h;
+    e.sp.length = d.length;
+    e.tab_off = off;
+    e.coef_off = off + 2 * int64_t(kMaxSubharmonicLevels) * d.n;
+    sub.push_back(e);
+    max_table = std::max<int64_t>(max_table, int64_t(sp.subharmonics) * d.n);
+    max_n2 = std::max<int64_t>(max_n2, int64_t(d.n) * d.n);
+    sub_pairs = std::max(sub_pairs, pairs);
+  }
+  const int n_sub = int(sub.size());
+  if (n_sub > 0) {
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.subh_beams, sub.data(), sizeof(SubBeam) * sub.size(),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(launch_subharmonic_setup(c->at<SubBeam>(c->L.subh_beams), n_sub, sub_pairs, max_table,
+                                     c->at<double>(c->L.subh), c->stream));
+  }
   for (int p = 0; p < max_pairs; ++p) {
     for (size_t b = 0; b < c->desc.size(); ++b) {
       const ssfm_instance_desc& d = c->desc[b];
@@ -952,29 +1002,11 @@ int do_gen_screens(ssfm_ctx* c) {
     b.planes_out = c->at<R>(c->L.screens);
     b.pair = p;
     if (int r = run_pass<R>(c, COL_INV, b)) return r;
-    // the low-frequency part below 1/L, added to the pair's planes
-    for (size_t bi = 0; bi < c->desc.size(); ++bi) {
-      const ssfm_instance_desc& d = c->desc[bi];
-      const ssfm_ctx::Spectrum& sp = c->spectrum[bi];
-      if (!(d.terms & SSFM_TURB) || 2 * p >= d.n_screens || sp.subharmonics == 0) continue;
-      if (sp.kind != SSFM_SPECTRUM_STEP && !(d.cn2 > 0)) continue;
-      SubharmonicSpec ss{};
-      ss.levels = sp.subharmonics;
-      ss.kind = sp.kind;
-      const double k0 = 2.0 * M_PI / d.wavelength;
-      ss.r0 = (sp.kind == SSFM_SPECTRUM_STEP) ? 0.0
-                                               : std::pow(0.423 * k0 * k0 * d.cn2 * d.screen_dz, -0.6);
-      ss.tau = sp.tau;
-      ss.kappa_h = sp.kappa_h;
-      ss.length = d.length;
-      // scratch: this beam's slice of the work buffer, idle until the next pair
-      const InstDev& in = c->inst[bi];
-      if (subharmonic_scratch_bytes(d.n, ss.levels) > size_t(d.n) * d.n * c->el)
-        return fail(SSFM_EINVAL, "grid %d too small for %d subharmonic levels", d.n, ss.levels);
-      void* scr = static_cast<char*>(c->field(c->L.Wk)) + in.off * int64_t(c->el);
-      HIP_TRY(launch_subharmonics<R>(c->at<InstDev>(c->L.inst), int(bi), d.n, p, d.seed, ss,
-                                     c->at<R>(c->L.screens), scr, c->stream));
-    }
+    if (n_sub > 0)
+      HIP_TRY(launch_subharmonic_apply<R>(c->at<SubBeam>(c->L.subh_beams), n_sub,
+                                          c->at<InstDev>(c->L.inst), p, max_n2,
+                                          c->at<double>(c->L.subh), c->at<R>(c->L.screens),
+                                          c->stream));
   }
   return SSFM_OK;
 }

@@ -11,9 +11,9 @@
 namespace ssfm {
 
 constexpr int kMaxSubharmonicLevels = 8;
-// offset (in doubles) of the axis tables in a pair's scratch, after the
-// 8 kMaxSubharmonicLevels coefficients (re, im) and the mean
-constexpr int kSubTab = 256;
+// doubles per screen pair's coefficient block: the 8 kMaxSubharmonicLevels
+// coefficients (re, im) at [0, 128), the grid mean at [128, 130)
+constexpr int kSubPair = 256;
 
 // Spectrum of one beam's subharmonic modes: kind 0 Kolmogorov with Fried
 // parameter r0, kind 1 the step spectrum (tau per FFT cell, i.e. density
@@ -27,18 +27,35 @@ struct SubharmonicSpec {
   double length;
 };
 
-// Adds the subharmonic part of screen pair `pair` of beam b to its screen
-// planes (real part to plane 2 pair, imaginary part to plane 2 pair + 1 when
-// the beam has it).  1 <= spec.levels <= kMaxSubharmonicLevels.  scratch:
-// device memory of at least subharmonic_scratch_bytes(n, levels) bytes,
-// 8-byte aligned (coefficients, mean and axis tables of this pair).
-template <typename R>
-hipError_t launch_subharmonics(const InstDev* inst, int b, int n, int pair, uint64_t seed,
-                               const SubharmonicSpec& spec, void* planes, void* scratch,
-                               hipStream_t s);
+// One beam with subharmonics: its axis table (levels x n complex, FP64) at
+// tab_off and its pairs' coefficient blocks at coef_off (doubles into the
+// subharmonic region of the workspace).
+struct SubBeam {
+  int32_t inst;
+  int32_t n;
+  int32_t pairs;
+  uint32_t k0, k1;  // Philox key (the beam's seed)
+  int32_t pad;
+  SubharmonicSpec sp;
+  int64_t tab_off;
+  int64_t coef_off;
+};
 
-inline size_t subharmonic_scratch_bytes(int n, int levels) {
-  return sizeof(double) * (kSubTab + 2 * size_t(levels) * size_t(n));
+// Doubles of a beam's region: tables for the maximum level count and one
+// coefficient block per pair.
+inline int64_t subharmonic_region_doubles(int n, int pairs) {
+  return 2 * int64_t(kMaxSubharmonicLevels) * n + int64_t(kSubPair) * pairs;
 }
+
+// Coefficients, means and axis tables of every listed beam and pair (two
+// launches).  max_pairs, max_table: the largest pair count and levels x n.
+hipError_t launch_subharmonic_setup(const SubBeam* beams, int n_beams, int max_pairs,
+                                    int64_t max_table, double* region, hipStream_t s);
+// Adds pair `pair`'s low-frequency part to the screen planes of every listed
+// beam that has that pair (one launch).  max_n2: the largest n^2.
+template <typename R>
+hipError_t launch_subharmonic_apply(const SubBeam* beams, int n_beams, const InstDev* inst,
+                                    int pair, int64_t max_n2, const double* region, void* planes,
+                                    hipStream_t s);
 
 }  // namespace ssfm
