@@ -168,7 +168,9 @@ int ssfm_set_splitting(ssfm_ctx* ctx, int32_t scheme);
  * then U+ = 2 Ubar - U.  Converged, a step conserves power exactly without
  * absorption.  The per-step power and peak are those of U+.  Returns
  * SSFM_EUNSUPPORTED when a beam has the ansatz term or turbulence screens;
- * forward only, like Strang.  Zeroes every field. */
+ * forward only like Strang (the recorded march, its adjoint, the fluence
+ * loss and the lens return SSFM_EUNSUPPORTED), while ssfm_fluence_mismatch
+ * works on its fields.  Zeroes every field. */
 int ssfm_set_fd_iterations(ssfm_ctx* ctx, int32_t iterations);  /* 1..64 */
 
 /* Screen spectrum of instance inst for the next ssfm_gen_screens:
@@ -239,7 +241,8 @@ int ssfm_fluence_loss(ssfm_ctx* ctx, int32_t inst, const void* target,
 /* The same normalised fluence mismatch as ssfm_fluence_loss for the
  * current field of instance inst, after any march (propagate or record),
  * without seeding the adjoint or touching a recorded march's state: for
- * fitness evaluations (a population of beams in one context).
+ * fitness evaluations (a population of beams in one context).  Lie and
+ * finite-difference schemes; SSFM_EUNSUPPORTED under Strang.
  * Synchronises. */
 int ssfm_fluence_mismatch(ssfm_ctx* ctx, int32_t inst, const void* target,
                           int32_t where, double* loss);

@@ -1623,7 +1623,10 @@ int ssfm_fluence_mismatch(ssfm_ctx* c, int32_t inst, const void* target, int32_t
                           double* loss) {
   if (int r = check_inst(c, inst)) return r;
   if (!loss) return fail(SSFM_EINVAL, "loss is NULL");
-  if (int r = lie_only(c, "fluence_mismatch")) return r;
+  // the finite-difference state is U itself; Strang holds L(dz/2) U
+  if (c->strang)
+    return fail(SSFM_EUNSUPPORTED, "fluence_mismatch needs the Lie or the finite-difference "
+                                   "scheme (Strang holds L(dz/2) U)");
   const int n = c->desc[inst].n;
   const double* dt;
   if (int r = stage_in(c, target, where, 8 * size_t(n) * n, &dt)) return r;

@@ -256,3 +256,19 @@ def test_largest_grid_conserves_power():
     print(f"fd fp64 4096^2: power drift {drift:.2e}, field moved {moved:.2e}", flush=True)
     assert drift < 1e-12 and moved > 1e-4
     p.close()
+
+
+def test_fluence_mismatch_after_a_finite_difference_march():
+    """The fitness entry point reads the finite-difference state (U itself):
+    it equals the oracle's fluence loss of the oracle's FD march."""
+    inst = W.config1()[0]
+    u0 = W.initial_field(inst)
+    target = W.synthetic_target(inst, 2)
+    ref = FD.fd_march(u0, inst, 20, iterations=4)
+    p = _fd([inst], 64, 4)
+    p.set_field(0, u0)
+    p.propagate(20)
+    got = p.fluence_mismatch(0, target)
+    want = M.fluence_loss(ref.field, target)[0]
+    assert abs(got / want - 1) < 1e-11, (got, want)
+    p.close()
