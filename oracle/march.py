@@ -242,7 +242,7 @@ def fluence_loss(u: np.ndarray, target: np.ndarray):
 def gradient(u0: np.ndarray, inst, n_steps: Optional[int] = None,
              theta: Optional[Sequence[float]] = None,
              screens: Optional[Dict[int, np.ndarray]] = None,
-             cotangent: Optional[Callable] = None):
+             cotangent: Optional[Callable] = None, strang: bool = False):
     """Exact discrete adjoint of ``march``.
 
     ``cotangent(U_N) -> (loss, G_N)`` gives the loss and G = dL/dRe U_N +
@@ -253,17 +253,32 @@ def gradient(u0: np.ndarray, inst, n_steps: Optional[int] = None,
       dL/dth_p += Re(conj(lam) U' dlnE/dth_p)    (U' = V E, linear in th)
       lam_V = lam conj(E + I E') + conj(lam) V^2 E'   (E' = dE/dI)
       lam <- F^-1 conj(P) F lam_V                (adjoint diffraction)
+    With strang=True the step is U' = P_h (V E T), V = P_h U, so the adjoint
+    half-step diffraction comes before and after the same screen adjoint.
     """
     n_steps = inst.n_steps if n_steps is None else n_steps
-    res = march(u0, inst, n_steps, theta, screens, keep_pre_screen=True)
-    loss, lam = cotangent(res.field)
-    prop = propagator(inst.n, inst.length, inst.dz,
-                      2.0 * math.pi / inst.medium.wavelength)
+    k0 = 2.0 * math.pi / inst.medium.wavelength
     scr = Screen.of(inst, theta)
     turb = screens if (inst.medium.terms & TURB) else None
+    if strang:
+        prop = propagator(inst.n, inst.length, inst.dz / 2, k0)
+        u = np.array(u0, dtype=np.complex128)
+        pre = []
+        for n in range(n_steps):
+            v = diffract(u, prop)
+            pre.append(v)
+            u = diffract(apply_screen(v, scr, turb.get(n) if turb else None), prop)
+        loss, lam = cotangent(u)
+    else:
+        prop = propagator(inst.n, inst.length, inst.dz, k0)
+        res = march(u0, inst, n_steps, theta, screens, keep_pre_screen=True)
+        pre = res.pre_screen
+        loss, lam = cotangent(res.field)
     g_theta = np.zeros(8)
     for n in reversed(range(n_steps)):
-        v = res.pre_screen[n]
+        if strang:
+            lam = diffract_adjoint(lam, prop)
+        v = pre[n]
         phi = turb.get(n) if turb else None
         if phi is not None:
             lam = lam * np.exp(-1j * phi)

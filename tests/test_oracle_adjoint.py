@@ -104,6 +104,38 @@ def test_gradient_matches_finite_differences(with_turb):
 
 
 @pytest.mark.parametrize("with_turb", [False, True])
+def test_strang_gradient_matches_finite_differences(with_turb):
+    """The adjoint of the Strang march (half-step adjoints around the same
+    screen adjoint) against central differences of the Strang march; it is
+    not the Lie gradient."""
+    terms = W.KPM | W.TERM_ANSATZ
+    inst, u0, target, screens = _case(terms, with_turb)
+    loss, g_u0, g_th = M.gradient(u0, inst, screens=screens, cotangent=_loss_fn(target),
+                                  strang=True)
+
+    def f(u, th):
+        r = M.march(u, inst, theta=th, screens=screens, strang=True)
+        return M.fluence_loss(r.field, target)[0]
+
+    th0 = np.array(inst.theta)
+    assert abs(loss - f(u0, th0)) <= 1e-14 * loss
+    for p in range(8):
+        h = 1e-6 * max(1.0, abs(th0[p]))
+        e = np.zeros(8)
+        e[p] = h
+        fd = (f(u0, th0 + e) - f(u0, th0 - e)) / (2 * h)
+        assert abs(fd - g_th[p]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g_th).max())
+    rng = np.random.default_rng(19)
+    for _ in range(3):
+        d = rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape)
+        h = 1e-6 * np.abs(u0).max() / np.abs(d).max()
+        fd = (f(u0 + h * d, th0) - f(u0 - h * d, th0)) / (2 * h)
+        assert abs(fd - _ip(g_u0, d)) <= 1e-6 * abs(fd)
+    _, g_lie, _ = M.gradient(u0, inst, screens=screens, cotangent=_loss_fn(target))
+    assert np.linalg.norm(g_lie - g_u0) > 1e-3 * np.linalg.norm(g_u0)
+
+
+@pytest.mark.parametrize("with_turb", [False, True])
 def test_gradient_taylor_remainder_is_second_order(with_turb):
     """Taylor test along a joint random direction d = (dU0, dtheta):
     r(h) = |L(x + h d) - L(x) - h <grad L, d>| falls 4x per halving of h
