@@ -143,12 +143,16 @@ int ssfm_gen_screens(ssfm_ctx* ctx);
  * the screen.  SSFM_STRANG: L(dz/2), screen, L(dz/2), second order in dz
  * (a scheme variant; the paper does not state its splitting).  A Strang
  * context keeps V = L(dz/2) U between steps (one extra half step when a
- * field is set, one backward half step when it is read); it marches and
- * reads out fields, intensities, per-step diagnostics and screens, while
- * the recorded march, its adjoint, the fluence loss and mismatch and the
- * effective lens return SSFM_EUNSUPPORTED.  Its per-step power is exact;
- * its per-step peak is that of L(dz/2) U.  Changing the scheme zeroes
- * every field: call it before ssfm_set_field. */
+ * field is set, one backward half step when it is read).  It marches,
+ * reads out fields, intensities, per-step diagnostics and screens, and
+ * records and differentiates: in V the step is V' = L(dz) S_n(V), the Lie
+ * recurrence with each step's own screen acting on load, so the adjoint is
+ * the Lie adjoint with that screen, preceded by the adjoint of the read-out
+ * (the cotangent of U_N is taken to L(dz/2) of it) and followed by that of
+ * the set-field half step (dL/dU_0 = L(-dz/2) dL/dV_0).  The fluence
+ * mismatch and the effective lens return SSFM_EUNSUPPORTED.  Its per-step
+ * power is exact; its per-step peak is that of L(dz/2) U.  Changing the
+ * scheme zeroes every field: call it before ssfm_set_field. */
 enum { SSFM_LIE = 0, SSFM_STRANG = 1, SSFM_FD = 2 };
 int ssfm_set_splitting(ssfm_ctx* ctx, int32_t scheme);
 

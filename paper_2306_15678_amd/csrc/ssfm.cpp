@@ -757,6 +757,17 @@ int half_steps(ssfm_ctx* c, bool forward) {
   return run_pass<R>(c, COL_FWD, a);
 }
 
+// Lam <- L(+-dz/2) Lam in place (the half-step tables, no screen).
+template <typename R>
+int half_step_lam(ssfm_ctx* c, bool forward) {
+  PassArgs<R> a = base_args<R>(c);
+  a.inst = c->at<InstDev>(forward ? c->L.half_inst : c->L.back_inst);
+  a.src = c->field(c->L.Lam);
+  a.dst = c->field(c->L.Lam);
+  if (int r = run_pass<R>(c, ROW_FWD, a)) return r;
+  return run_pass<R>(c, COL_FWD, a);
+}
+
 // Apply the pending screen in place (state becomes U_n).
 template <typename R>
 int flush_pending(ssfm_ctx* c) {
@@ -775,6 +786,13 @@ int flush_pending(ssfm_ctx* c) {
   }
   c->pending = false;
   return SSFM_OK;
+}
+
+// Screen applied on load by step `step` of a record starting at step0: Lie
+// the previous step's (none for the first), Strang the step's own.
+int64_t rec_pending(const ssfm_ctx* c, int64_t step0, int64_t step) {
+  if (c->strang) return step;
+  return (step == step0) ? -1 : step - 1;
 }
 
 // Location of s_i during a record of n steps (i in [0, n]).
@@ -798,7 +816,7 @@ int enqueue_record(ssfm_ctx* c, int64_t n, int64_t step0, int64_t i0, int64_t i1
   for (int64_t i = i0; i < i1; ++i) {
     const int slot = int((i - i0) % kDiagChunk);
     double* part = c->at<double>(c->L.diag_part) + size_t(slot) * 2 * c->L.n_widx_cols;
-    const int64_t pend = (i == 0) ? -1 : step0 + i - 1;
+    const int64_t pend = rec_pending(c, step0, step0 + i);
     if (int r = fwd_step<R>(c, rec_slot(c, i, n), rec_slot(c, i + 1, n), pend, part, nullptr,
                             nullptr, ts))
       return r;
@@ -823,7 +841,7 @@ int do_record(ssfm_ctx* c, int64_t n) {
                       });
   if (r) return r;
   c->step += n;
-  c->pending = true;
+  c->pending = !c->strang;
   c->diag_valid = std::min<int64_t>(n, c->L.diag_cap);
   c->rec_steps = n;
   c->rec_step0 = step0;
@@ -857,12 +875,16 @@ int enqueue_backward(ssfm_ctx* c) {
     const int64_t len = std::min<int64_t>(M, n - s0);
     for (int64_t i = 0; i + 1 < len; ++i) {
       const int64_t g = s0 + i;
-      const int64_t pend = (g == 0) ? -1 : step0 + g - 1;
+      const int64_t pend = rec_pending(c, step0, step0 + g);
       if (int r = fwd_step<R>(c, sv(k, i), slot(k, i), pend, nullptr, work, st)) return r;
     }
     return SSFM_OK;
   };
   HIP_TRY(launch_fill_f64(c->at<double>(c->L.theta_acc), 8 * c->L.n_widx_rows, 0.0, c->stream));
+  // Strang: the seed is the cotangent of U_N = L(-dz/2) V_N, so the march's
+  // adjoint starts from L(dz/2) of it (the adjoint of the read-out)
+  if (c->strang)
+    if (int r = half_step_lam<R>(c, true)) return r;
   if (!stored) {
     if (int r = recompute(n_seg - 1, c->field(c->L.Wk), c->stream)) return r;
   }
@@ -878,11 +900,14 @@ int enqueue_backward(ssfm_ctx* c) {
     const int64_t len = std::min<int64_t>(M, n - s0);
     for (int64_t i = len - 1; i >= 0; --i) {
       const int64_t g = s0 + i;
-      const int64_t pend = (g == 0) ? -1 : step0 + g - 1;
+      const int64_t pend = rec_pending(c, step0, step0 + g);
       if (int r = adj_step<R>(c, sv(k, i), pend)) return r;
     }
     if (overlap) HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join, 0));
   }
+  // Strang: V_0 = L(dz/2) U_0, so dL/dU_0 = L(-dz/2) dL/dV_0
+  if (c->strang)
+    if (int r = half_step_lam<R>(c, false)) return r;
   HIP_TRY(launch_reduce_rows(c->at<double>(c->L.theta_acc), 8, c->at<int32_t>(c->L.wbegin_row),
                              int(c->desc.size()), c->at<double>(c->L.theta_out), c->stream));
   return SSFM_OK;
@@ -912,8 +937,18 @@ int do_seed(ssfm_ctx* c, int b, int mode, const double* target_dev, const double
                          c->at<double>(c->L.scal), c->stream));
   }
   const double gs = (mode == 0) ? d.i_ref : std::sqrt(d.i_ref);
-  HIP_TRY(launch_seed<R>(mode, c->field(c->L.S), c->at<InstDev>(c->L.inst), b, in.n,
-                         c->at<R>(c->L.screens), c->at<int64_t>(c->L.steps), pend, target_dev,
+  const void* state = c->field(c->L.S);
+  int64_t seed_pend = pend;
+  if (c->strang) {
+    // U_N = L(-dz/2) V_N into the work buffer; nothing pending
+    seed_pend = -1;
+    if (mode == 0) {
+      if (int r = half_steps<R>(c, false)) return r;
+      state = c->field(c->L.Wk);
+    }
+  }
+  HIP_TRY(launch_seed<R>(mode, state, c->at<InstDev>(c->L.inst), b, in.n,
+                         c->at<R>(c->L.screens), c->at<int64_t>(c->L.steps), seed_pend, target_dev,
                          c->at<double>(c->L.scal), g_dev, gs, c->field(c->L.Lam), loss, th,
                          in.n, c->stream));
   return SSFM_OK;
@@ -1526,6 +1561,13 @@ int ssfm_set_splitting(ssfm_ctx* c, int32_t scheme) {
 }
 
 namespace {
+int split_step_only(ssfm_ctx* c, const char* what) {
+  if (c->fd)
+    return fail(SSFM_EUNSUPPORTED, "%s needs a split-step scheme (the finite-difference scheme "
+                                   "marches forward only)", what);
+  return SSFM_OK;
+}
+
 int lie_only(ssfm_ctx* c, const char* what) {
   if (c->strang || c->fd)
     return fail(SSFM_EUNSUPPORTED, "%s needs the Lie split-step scheme (%s marches forward only)",
@@ -1577,14 +1619,14 @@ int ssfm_get_diag(ssfm_ctx* c, int32_t inst, double* power, double* peak, int64_
 
 int ssfm_forward_record(ssfm_ctx* c, int64_t n_steps) {
   if (int r = check_ctx(c)) return r;
-  if (int r = lie_only(c, "forward_record")) return r;
+  if (int r = split_step_only(c, "forward_record")) return r;
   if (n_steps < 1) return fail(SSFM_EINVAL, "n_steps must be >= 1");
   return SSFM_DISPATCH(c, do_record, c, n_steps);
 }
 
 int ssfm_set_cotangent(ssfm_ctx* c, int32_t inst, const void* g, int32_t where) {
   if (int r = check_inst(c, inst)) return r;
-  if (int r = lie_only(c, "set_cotangent")) return r;
+  if (int r = split_step_only(c, "set_cotangent")) return r;
   if (!c->rec_valid) return fail(SSFM_ESTATE, "set_cotangent needs a preceding forward_record");
   const int n = c->desc[inst].n;
   const double* dg;
@@ -1598,7 +1640,7 @@ int ssfm_set_cotangent(ssfm_ctx* c, int32_t inst, const void* g, int32_t where) 
 
 int ssfm_fluence_loss(ssfm_ctx* c, int32_t inst, const void* target, int32_t where, double* loss) {
   if (int r = check_inst(c, inst)) return r;
-  if (int r = lie_only(c, "fluence_loss")) return r;
+  if (int r = split_step_only(c, "fluence_loss")) return r;
   if (!c->rec_valid) return fail(SSFM_ESTATE, "fluence_loss needs a preceding forward_record");
   const int n = c->desc[inst].n;
   const double* dt;
@@ -1663,7 +1705,7 @@ int ssfm_fluence_mismatch(ssfm_ctx* c, int32_t inst, const void* target, int32_t
 
 int ssfm_backward(ssfm_ctx* c) {
   if (int r = check_ctx(c)) return r;
-  if (int r = lie_only(c, "backward")) return r;
+  if (int r = split_step_only(c, "backward")) return r;
   return SSFM_DISPATCH(c, do_backward, c);
 }
 

@@ -115,19 +115,24 @@ def test_strang_state_handling():
     p.close()
 
 
-def test_lie_only_entry_points_refuse_strang():
+def test_strang_refuses_the_mismatch_and_the_lens():
+    """The fluence mismatch and the effective lens read or change U, which a
+    Strang context holds as L(dz/2) U: both refuse; the recorded march and
+    its adjoint work (tests below)."""
+    from paper_2306_15678_amd.march import make_lens
     inst = W.config1()[0]
     p = _strang([inst], 32, max_steps=10, ckpt_every=5)
     p.set_field(0, W.initial_field(inst))
-    with pytest.raises(SsfmError) as e:
-        p.forward_record(10)
-    assert e.value.status == EUNSUPPORTED
+    p.forward_record(10)
     with pytest.raises(SsfmError) as e:
         p.fluence_mismatch(0, np.ones((inst.n, inst.n)))
     assert e.value.status == EUNSUPPORTED
+    with pytest.raises(SsfmError) as e:
+        p.apply_lens(0, make_lens(0.0, 1.0, -1.0, 1e-12))
+    assert e.value.status == EUNSUPPORTED
     p.set_splitting(False)
     p.set_field(0, W.initial_field(inst))
-    p.forward_record(10)
+    p.fluence_mismatch(0, np.ones((inst.n, inst.n)))
     p.close()
 
 
@@ -150,3 +155,59 @@ def test_strang_mixed_size_batch_equals_each_beam_alone():
         q.propagate(30)
         assert np.array_equal(q.field(0), got[k])
         q.close()
+
+
+def _grad_case(turb):
+    """256^2, Kerr + MPA + plasma + ansatz, 200 P_cr, 8 steps; with
+    turbulence, screens after steps 1, 4 and 7 (the last)."""
+    terms = W.KPM | W.TERM_ANSATZ
+    kw = {}
+    if turb:
+        terms |= W.TERM_TURB
+        kw = dict(cn2=3e-13, screen_dz=0.03, n_screens=3)
+    theta = tuple(np.array(W.THETA0) + W.random_theta(7, 0.1))
+    return W.Instance(n=256, length=4e-3, dz=0.01, n_steps=8, medium=W.Medium(terms=terms),
+                      w0=0.5e-3, power=200 * W.P_CR, sigma=0.2, seed=356, theta=theta, **kw)
+
+
+def _strang_grads(inst, precision, ckpt, target):
+    p = _strang([inst], precision, max_steps=inst.n_steps, ckpt_every=ckpt)
+    if inst.medium.terms & W.TERM_TURB:
+        p.gen_screens()
+    p.set_field(0, W.initial_field(inst))
+    p.set_theta(0, inst.theta)
+    p.forward_record(inst.n_steps)
+    loss = p.fluence_loss(0, target)
+    p.backward()
+    out = (loss, p.grad_field(0), p.grad_theta(0))
+    p.close()
+    return out
+
+
+@pytest.mark.parametrize("turb", [False, True])
+@pytest.mark.parametrize("precision,ckpt", [(64, 3), (64, 100), (32, 3)])
+def test_strang_gradient_matches_oracle(precision, ckpt, turb):
+    """The recorded Strang march and its adjoint against the oracle's Strang
+    adjoint (checkpointed with recompute, M = 3, or all steps stored)."""
+    inst = _grad_case(turb)
+    u0 = W.initial_field(inst)
+    target = W.synthetic_target(inst, 5)
+    screens = T.instance_screens(inst) if turb else None
+    loss, g_u0, g_th = M.gradient(u0, inst, screens=screens, strang=True,
+                                  cotangent=lambda u: M.fluence_loss(u, target))
+    gl, gg, gt = _strang_grads(inst, precision, ckpt, target)
+    lerr = abs(gl / loss - 1)
+    ferr = M.rel_l2(gg, g_u0)
+    terr = float(np.max(np.abs(gt - g_th)) / np.max(np.abs(g_th)))
+    print(f"strang grad fp{precision} M={ckpt} turb={turb}: loss {lerr:.2e} dL/dU0 {ferr:.2e} "
+          f"dL/dtheta {terr:.2e}", flush=True)
+    tol = 1e-10 if precision == 64 else 1e-4
+    assert lerr < tol and ferr < tol and terr < tol
+
+
+def test_strang_checkpointed_and_stored_adjoints_are_bitwise_equal():
+    inst = _grad_case(True)
+    target = W.synthetic_target(inst, 5)
+    a = _strang_grads(inst, 32, 3, target)
+    b = _strang_grads(inst, 32, 100, target)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
