@@ -211,3 +211,30 @@ def test_strang_checkpointed_and_stored_adjoints_are_bitwise_equal():
     a = _strang_grads(inst, 32, 3, target)
     b = _strang_grads(inst, 32, 100, target)
     assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_torch_autograd_through_a_strang_context():
+    """autograd.march on a Strang context: a fluence loss written in torch,
+    gradients in U0 and theta against the oracle's Strang adjoint."""
+    import torch
+
+    from paper_2306_15678_amd import autograd as AG
+
+    inst = _grad_case(False)
+    u0 = W.initial_field(inst)
+    target = W.synthetic_target(inst, 5)
+    _, g_u0, g_th = M.gradient(u0, inst, strang=True,
+                               cotangent=lambda u: M.fluence_loss(u, target))
+    dev = torch.device("cuda", 0)
+    p = _strang([inst], 64, max_steps=inst.n_steps, ckpt_every=3)
+    u = torch.from_numpy(u0).to(dev).requires_grad_(True)
+    th = torch.tensor(inst.theta, dtype=torch.float64, requires_grad=True)
+    t = torch.from_numpy(target).to(dev)
+    out = AG.march(u, th, p, inst.n_steps)
+    loss = torch.sum((out.abs() ** 2 - t) ** 2) / torch.sum(t ** 2)
+    loss.backward()
+    ferr = M.rel_l2(u.grad.cpu().numpy(), g_u0)
+    terr = float(np.max(np.abs(th.grad.numpy() - g_th)) / np.max(np.abs(g_th)))
+    print(f"strang autograd fp64: dL/dU0 {ferr:.2e} dL/dtheta {terr:.2e}", flush=True)
+    assert ferr < 1e-10 and terr < 1e-10
+    p.close()
