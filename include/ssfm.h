@@ -149,8 +149,8 @@ int ssfm_gen_screens(ssfm_ctx* ctx);
  * recurrence with each step's own screen acting on load, so the adjoint is
  * the Lie adjoint with that screen, preceded by the adjoint of the read-out
  * (the cotangent of U_N is taken to L(dz/2) of it) and followed by that of
- * the set-field half step (dL/dU_0 = L(-dz/2) dL/dV_0).  The fluence
- * mismatch and the effective lens return SSFM_EUNSUPPORTED.  Its per-step
+ * the set-field half step (dL/dU_0 = L(-dz/2) dL/dV_0).  The effective
+ * lens returns SSFM_EUNSUPPORTED.  Its per-step
  * power is exact; its per-step peak is that of L(dz/2) U.  Changing the
  * scheme zeroes every field: call it before ssfm_set_field. */
 enum { SSFM_LIE = 0, SSFM_STRANG = 1, SSFM_FD = 2 };
@@ -245,8 +245,8 @@ int ssfm_fluence_loss(ssfm_ctx* ctx, int32_t inst, const void* target,
 /* The same normalised fluence mismatch as ssfm_fluence_loss for the
  * current field of instance inst, after any march (propagate or record),
  * without seeding the adjoint or touching a recorded march's state: for
- * fitness evaluations (a population of beams in one context).  Lie and
- * finite-difference schemes; SSFM_EUNSUPPORTED under Strang.
+ * fitness evaluations (a population of beams in one context); under
+ * Strang on U = L(-dz/2) V (the work buffer holds it afterwards).
  * Synchronises. */
 int ssfm_fluence_mismatch(ssfm_ctx* ctx, int32_t inst, const void* target,
                           int32_t where, double* loss);

@@ -163,7 +163,7 @@ k_seed(int mode, const cx<R>* __restrict__ state, const InstDev* inst, int b,
       gu = {R(g_ext[2 * i] * g_scale), R(g_ext[2 * i + 1] * g_scale)};
     }
     const cx<R> out = (pending >= 0) ? screen_adjoint(sc, v, gu, pt, g) : gu;
-    lam[in.off + i] = out;
+    if (lam) lam[in.off + i] = out;  // null: the loss alone (fitness evaluations)
   }
   block_reduce<1, 256, false>(loss, red);
   __syncthreads();

@@ -1665,28 +1665,32 @@ int ssfm_fluence_mismatch(ssfm_ctx* c, int32_t inst, const void* target, int32_t
                           double* loss) {
   if (int r = check_inst(c, inst)) return r;
   if (!loss) return fail(SSFM_EINVAL, "loss is NULL");
-  // the finite-difference state is U itself; Strang holds L(dz/2) U
-  if (c->strang)
-    return fail(SSFM_EUNSUPPORTED, "fluence_mismatch needs the Lie or the finite-difference "
-                                   "scheme (Strang holds L(dz/2) U)");
   const int n = c->desc[inst].n;
   const double* dt;
   if (int r = stage_in(c, target, where, 8 * size_t(n) * n, &dt)) return r;
-  // the seed kernel in loss mode, with its cotangent and gradient partials
-  // sent to scratch: the work buffer and the staging area past the target
+  // the seed kernel in loss mode without a cotangent output; its gradient
+  // partials go to the staging area past the target
   double* scratch = c->at<double>(c->L.stage) + size_t(n) * n;
   double* th = scratch;
   double* part = scratch + 8 * size_t(n);
   const InstDev& in = c->inst[inst];
   const ssfm_instance_desc& d = c->desc[inst];
-  const int64_t pend = c->pending ? c->step - 1 : -1;
   auto run = [&]<typename R>(R*) -> int {
+    // the field U: the state with its pending screen (Lie), the state itself
+    // (finite differences), or L(-dz/2) of it in the work buffer (Strang)
+    const void* state = c->field(c->L.S);
+    int64_t pend = c->pending ? c->step - 1 : -1;
+    if (c->strang) {
+      if (int r = half_steps<R>(c, false)) return r;
+      state = c->field(c->L.Wk);
+      pend = -1;
+    }
     HIP_TRY(launch_sumsq(dt, int64_t(n) * n, 1.0, c->at<double>(c->L.sumsq_part),
                          c->at<double>(c->L.scal), c->stream));
-    HIP_TRY(launch_seed<R>(0, c->field(c->L.S), c->at<InstDev>(c->L.inst), inst, in.n,
+    HIP_TRY(launch_seed<R>(0, state, c->at<InstDev>(c->L.inst), inst, in.n,
                            c->at<R>(c->L.screens), c->at<int64_t>(c->L.steps), pend, dt,
-                           c->at<double>(c->L.scal), nullptr, d.i_ref, c->field(c->L.Wk), part,
-                           th, in.n, c->stream));
+                           c->at<double>(c->L.scal), nullptr, d.i_ref, nullptr, part, th, in.n,
+                           c->stream));
     return SSFM_OK;
   };
   if (int r = (c->precision == SSFM_FP64) ? run((double*)nullptr) : run((float*)nullptr))

@@ -115,24 +115,26 @@ def test_strang_state_handling():
     p.close()
 
 
-def test_strang_refuses_the_mismatch_and_the_lens():
-    """The fluence mismatch and the effective lens read or change U, which a
-    Strang context holds as L(dz/2) U: both refuse; the recorded march and
-    its adjoint work (tests below)."""
+def test_strang_mismatch_and_lens():
+    """The fluence mismatch evaluates U = L(-dz/2) V: it equals the oracle's
+    loss of its Strang march (and leaves the state alone); the effective
+    lens, which would change U, is refused."""
     from paper_2306_15678_amd.march import make_lens
     inst = W.config1()[0]
-    p = _strang([inst], 32, max_steps=10, ckpt_every=5)
-    p.set_field(0, W.initial_field(inst))
-    p.forward_record(10)
-    with pytest.raises(SsfmError) as e:
-        p.fluence_mismatch(0, np.ones((inst.n, inst.n)))
-    assert e.value.status == EUNSUPPORTED
+    u0 = W.initial_field(inst)
+    target = W.synthetic_target(inst, 2)
+    ref = M.march(u0, inst, n_steps=30, strang=True)
+    p = _strang([inst], 64, max_steps=10, ckpt_every=5)
+    p.set_field(0, u0)
+    p.propagate(30)
+    before = p.field(0)
+    got = p.fluence_mismatch(0, target)
+    want = M.fluence_loss(ref.field, target)[0]
+    assert abs(got / want - 1) < 1e-11, (got, want)
+    assert np.array_equal(p.field(0), before)
     with pytest.raises(SsfmError) as e:
         p.apply_lens(0, make_lens(0.0, 1.0, -1.0, 1e-12))
     assert e.value.status == EUNSUPPORTED
-    p.set_splitting(False)
-    p.set_field(0, W.initial_field(inst))
-    p.fluence_mismatch(0, np.ones((inst.n, inst.n)))
     p.close()
 
 
