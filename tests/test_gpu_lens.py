@@ -275,3 +275,24 @@ def test_torch_autograd_through_march_lens_march():
         assert abs(fd / adj - 1) < 1e-5
     p1.close()
     p2.close()
+
+
+def test_lens_vjp_at_1024():
+    """The lens and its VJP on the 1024^2 multifilamentation field after 200
+    steps (FP64), lens scaled to its filtered intensity: against the oracle."""
+    inst = W.config2()[0]
+    p = _prop([inst], 64)
+    p.set_field(0, W.initial_field(inst))
+    p.propagate(200)
+    u = p.field(0)
+    lens = _lens_params(inst, u, True)
+    g = np.random.default_rng(9).standard_normal(u.shape) + 0.5j
+    g_in, grad = p.lens_vjp(0, _to_gpu(lens), u, g)
+    want_g, want_p = LN.lens_vjp(u, g, inst.length, lens)
+    err_g = float(np.linalg.norm(g_in.cpu().numpy() - want_g) / np.linalg.norm(want_g))
+    err_p = float(np.max(np.abs(grad - want_p) / np.abs(want_p)))
+    _, _, active = LN.lens_exponent(u, inst.length, lens)
+    print(f"lens vjp 1024^2 fp64: g_in {err_g:.2e}, gradients {err_p:.2e}, "
+          f"{int(active.sum())} active points", flush=True)
+    assert active.sum() > 0 and err_g < 1e-12 and err_p < 1e-10
+    p.close()

@@ -240,3 +240,22 @@ def test_torch_autograd_through_a_strang_context():
     print(f"strang autograd fp64: dL/dU0 {ferr:.2e} dL/dtheta {terr:.2e}", flush=True)
     assert ferr < 1e-10 and terr < 1e-10
     p.close()
+
+
+def test_strang_full_size_matches_oracle():
+    """The 1024^2 multifilamentation beam (Kerr, MPA, plasma), FP64, 20 Strang
+    steps against the oracle's Strang march; FP32 against the same oracle at
+    the FP32 rounding level of this short horizon."""
+    inst = W.config2()[0]
+    u0 = W.initial_field(inst)
+    ref = M.march(u0, inst, n_steps=20, strang=True)
+    for precision, tol in ((64, 1e-12), (32, 2e-5)):
+        p = _strang([inst], precision)
+        p.set_field(0, u0)
+        p.propagate(20)
+        err = M.rel_l2(p.field(0), ref.field)
+        pw, _ = p.diag(0, 20)
+        perr = float(np.max(np.abs(pw / ref.power - 1)))
+        print(f"strang 1024^2 fp{precision} 20 steps: field={err:.2e} power={perr:.2e}", flush=True)
+        assert err < tol and perr < tol
+        p.close()

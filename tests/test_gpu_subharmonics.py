@@ -175,3 +175,17 @@ def test_eight_levels_on_the_smallest_grid():
         err = float(np.max(np.abs(got - want[k])) / np.max(np.abs(want[k])))
         print(f"8 levels, 128^2, screen {k}: maxrel={err:.2e}", flush=True)
         assert err < 1e-11
+
+
+def test_low_part_at_1024():
+    """A 1024^2 beam of the independent-beam workload, 3 levels, FP64: the low
+    part of its first pair against the oracle."""
+    inst = dataclasses.replace([b for b in W.config3() if b.n == 1024][0], n_steps=60)
+    with_sh = _screens(inst, 64, 3)
+    without = _screens(inst, 64, 0)
+    want = T.subharmonic_pair(inst.n, inst.length, _modes(inst, 3), inst.seed, 0)
+    for k in range(2):
+        got = with_sh[k] - without[k]
+        err = float(np.max(np.abs(got - want[k])) / np.max(np.abs(want[k])))
+        print(f"subharmonic low part 1024^2 screen {k}: maxrel={err:.2e}", flush=True)
+        assert err < 1e-13
