@@ -44,17 +44,27 @@ __device__ __forceinline__ ScreenConst<R> screen_const(const InstDev& in) {
   return s;
 }
 
-// Turbulence plane applied after `step` (nullptr if none).
+// Turbulence plane applied after `step` (nullptr if none): the first screen
+// whose step equals `step`, by lower-bound search of the beam's
+// nondecreasing step list (a workgroup-uniform chain of log2(n_screens)
+// scalar loads instead of one per screen).
 template <typename R>
 __device__ __forceinline__ const R* find_plane(const R* screens, const int64_t* steps,
                                                const InstDev& in, int64_t step) {
   if (step < 0 || !(in.terms & T_TURB) || in.n_screens <= 0 || screens == nullptr)
     return nullptr;
   const int64_t* st = steps + in.steps_off;
-  for (int s = 0; s < in.n_screens; ++s) {
-    if (st[s] == step) return screens + in.screen_off + int64_t(s) * in.n * in.n;
+  int lo = 0, hi = in.n_screens - 1;
+  if (step < st[lo] || step > st[hi]) return nullptr;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (st[mid] < step)
+      lo = mid + 1;
+    else
+      hi = mid;
   }
-  return nullptr;
+  if (st[lo] != step) return nullptr;
+  return screens + in.screen_off + int64_t(lo) * in.n * in.n;
 }
 
 // Deterministic workgroup reduction of NV doubles (sum or max); the result
