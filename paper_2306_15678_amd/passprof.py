@@ -1,6 +1,6 @@
 """Short eager marches of every compiled tile variant, for hardware counters.
 
-    python -m paper_2306_15678_amd.passprof [--precision 32] [--steps 4]
+    python -m paper_2306_15678_amd.passprof [--precision 32] [--steps 4] [--large]
 
 On the 1024 x 1024 multifilamentation beam it selects each forward row-pass
 variant in turn (column variant 0), then each column-pass variant (row
@@ -12,8 +12,10 @@ read and written) against which byte counters can be scaled.
 
 Variants appear in index order: the k-th distinct forward row-pass kernel
 name in dispatch order is row variant k, likewise for columns.  Last comes
-an eager march of the finite-difference scheme (variant 0 plans).  Prints
-one line per phase; ``--out`` writes the layout as JSON.
+an eager march of the finite-difference scheme (variant 0 plans).  With
+``--large`` the beam is the 4096^2 large-aperture one (its Kerr, MPA and
+plasma terms) and the finite-difference march is left out.  Prints one line
+per phase; ``--out`` writes the layout as JSON.
 """
 from __future__ import annotations
 
@@ -50,12 +52,22 @@ def main(argv=None) -> int:
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--large", action="store_true",
+                    help="the 4096^2 large-aperture beam (Kerr, MPA, plasma; no screens) "
+                         "instead of the 1024^2 one, without the finite-difference march")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import dataclasses
+
     import workloads as W
     from .march import Propagator, desc_of, plan_variants
 
-    inst = W.config2()[0]
+    if args.large:
+        base = W.config5()[0]
+        inst = dataclasses.replace(base, medium=dataclasses.replace(base.medium, terms=W.KPM),
+                                   n_screens=0)
+    else:
+        inst = W.config2()[0]
     n = inst.n
     p = Propagator([desc_of(inst)], precision=args.precision, max_steps=args.steps,
                    ckpt_every=args.steps)
@@ -71,15 +83,16 @@ def main(argv=None) -> int:
             p.synchronize()
             order.append([kind, v])
             print(f"{kind} variant {v}: {args.steps} steps", flush=True)
-    # the finite-difference scheme's passes (variant 0 plans): one starting
-    # row pass, then per step FD_ITERS column passes and as many row passes
-    p.select_plan(n, 0, 0)
-    p.set_finite_difference(FD_ITERS)
-    p.set_field(0, u0)
-    p.propagate(args.steps)
-    p.synchronize()
-    order.append(["fd", 0])
-    print(f"finite differences: {args.steps} steps, {FD_ITERS} iterations", flush=True)
+    if not args.large:
+        # the finite-difference scheme's passes (variant 0 plans): one starting
+        # row pass, then per step FD_ITERS column passes and as many row passes
+        p.select_plan(n, 0, 0)
+        p.set_finite_difference(FD_ITERS)
+        p.set_field(0, u0)
+        p.propagate(args.steps)
+        p.synchronize()
+        order.append(["fd", 0])
+        print(f"finite differences: {args.steps} steps, {FD_ITERS} iterations", flush=True)
     p.close()
     info = {"grid": n, "precision": args.precision, "steps": args.steps,
             "n_row": n_row, "n_col": n_col, "order": order, "fd_iters": FD_ITERS,
