@@ -97,13 +97,31 @@ def kolmogorov_amplitude(n: int, length: float, r0: float) -> np.ndarray:
     return np.sqrt(psd) / length
 
 
+def band_q2(length: float, k_h: float) -> float:
+    """Squared radius of the Eq. (10) band in mode-index units, with a
+    relative slack of 2^-40: q2 = (k_h L / 2 pi)^2 (1 + 2^-40).  A mode
+    (mx, my) of spatial frequency (mx, my)/L has kappa = 2 pi |m| / L, so
+    kappa <= k_h reads |m|^2 <= (k_h L / 2 pi)^2; the slack keeps a ring
+    that k_h was placed on (k_h = 2 pi M / L) inside whatever the rounding
+    of that product, so the edge is decided on integers."""
+    q = k_h * length / (2.0 * math.pi)
+    return q * q * (1.0 + 2.0 ** -40)
+
+
+def mode_indices(n: int) -> np.ndarray:
+    """Signed integer mode index m of each FFT sample (fftfreq order)."""
+    m = np.arange(n, dtype=np.int64)
+    return np.where(m <= n // 2, m, m - n)
+
+
 def step_amplitude(n: int, length: float, tau: float, k_h: float) -> np.ndarray:
-    """Eq. (10) read as a low-pass step: sqrt(tau) for 0 < kappa <= k_h,
-    decided on squares (kx^2 + ky^2 <= k_h^2) so that the inclusive edge
-    rests on correctly rounded products and sums only."""
-    k = 2.0 * math.pi * np.fft.fftfreq(n, d=length / n)
-    kap2 = k[None, :] * k[None, :] + k[:, None] * k[:, None]
-    return np.where((kap2 > 0) & (kap2 <= k_h * k_h), math.sqrt(tau), 0.0)
+    """Eq. (10) read as a low-pass step: sqrt(tau) for 0 < kappa <= k_h.
+    The band is decided on the integer mode indices, 0 < mx^2 + my^2 <= q2
+    (``band_q2``), so no rounding of a wavenumber enters the decision."""
+    m = mode_indices(n)
+    m2 = m[None, :] ** 2 + m[:, None] ** 2
+    q2 = band_q2(length, k_h)
+    return np.where((m2 > 0) & (m2 <= q2), math.sqrt(tau), 0.0)
 
 
 def screen_pair(n: int, length: float, amp: np.ndarray, seed: int,
@@ -115,16 +133,23 @@ def screen_pair(n: int, length: float, amp: np.ndarray, seed: int,
 
 
 def kolmogorov_density(r0: float):
-    """Phase spectral density Phi(fx, fy) = 0.023 r0^(-5/3) f^(-11/3) [rad^2 m^2]."""
-    return lambda fx, fy: 0.023 * r0 ** (-5.0 / 3.0) * math.hypot(fx, fy) ** (-11.0 / 3.0)
+    """Phase spectral density Phi(fx, fy) = 0.023 r0^(-5/3) f^(-11/3) [rad^2 m^2]
+    (called as dens(fx, fy, (p, mx, my)); the mode indices are not used)."""
+    return lambda fx, fy, idx=None: (0.023 * r0 ** (-5.0 / 3.0)
+                                     * math.hypot(fx, fy) ** (-11.0 / 3.0))
 
 
 def step_density(length: float, tau: float, k_h: float):
     """The Eq. (10) step as a density: tau per FFT cell of area 1/L^2, i.e.
-    tau L^2, for kappa^2 = (2 pi fx)^2 + (2 pi fy)^2 <= k_h^2."""
-    def dens(fx, fy):
-        kx, ky = 2.0 * math.pi * fx, 2.0 * math.pi * fy
-        return tau * length * length if kx * kx + ky * ky <= k_h * k_h else 0.0
+    tau L^2, inside the band.  Subharmonic modes sit at f = (mx, my)/(3^p L),
+    so kappa <= k_h reads mx^2 + my^2 <= 9^p q2 with the integer indices
+    and the same q2 as the FFT modes (``band_q2``).  Called as
+    dens(fx, fy, (p, mx, my))."""
+    q2 = band_q2(length, k_h)
+
+    def dens(fx, fy, idx):
+        p, mx, my = idx
+        return tau * length * length if mx * mx + my * my <= q2 * 9 ** p else 0.0
     return dens
 
 
@@ -143,7 +168,7 @@ def subharmonic_modes(length: float, levels: int, density):
                 continue
             mx, my = q % 3 - 1, q // 3 - 1
             fx, fy = mx * df, my * df
-            out.append((p, q, fx, fy, math.sqrt(density(fx, fy)) * df))
+            out.append((p, q, fx, fy, math.sqrt(density(fx, fy, (p, mx, my))) * df))
     return out
 
 
@@ -173,6 +198,9 @@ def instance_screens(inst, step_spectrum=None, subharmonics: int = 0) -> Dict[in
     same spectrum is added to every screen."""
     if inst.n_screens <= 0:
         return {}
+    if not inst.screen_dz >= inst.dz:
+        # closer screens could fall on one step (or before the first)
+        raise ValueError("screen spacing %g m is below the step %g m" % (inst.screen_dz, inst.dz))
     if step_spectrum is not None:
         amp = step_amplitude(inst.n, inst.length, *step_spectrum)
         dens = step_density(inst.length, *step_spectrum)

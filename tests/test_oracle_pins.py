@@ -284,3 +284,96 @@ def test_theta0_matches_fit_script():
     spec.loader.exec_module(mod)
     fit = mod.fit_theta0()
     assert np.allclose(fit, np.array(W.THETA0), rtol=1e-7, atol=1e-7)
+
+
+# --------------------------------------------- loss pieces on hand arrays
+def test_block_mean_of_hand_built_array():
+    """8 x 8 block means of the dense fluence onto the sparse grid (the
+    discrepancy target): rows are y, columns x; a transposed or mis-strided
+    reshape moves the values below."""
+    w = np.arange(1.0, 17.0).reshape(4, 4)
+    assert np.array_equal(M.block_mean(w, 2), np.array([[3.5, 5.5], [11.5, 13.5]]))
+    w6 = np.zeros((6, 6))
+    w6[0:3, 3:6] = 9.0          # top right block (y < 3, x >= 3)
+    w6[4, 1] = 18.0             # one point in the bottom left block
+    assert np.array_equal(M.block_mean(w6, 3), np.array([[0.0, 9.0], [2.0, 0.0]]))
+    assert np.array_equal(M.block_mean(w6, 1), w6)
+    assert M.block_mean(w6, 6)[0, 0] == pytest.approx(w6.mean(), rel=1e-15)
+
+
+def test_fluence_loss_value_and_cotangent_on_a_2x2_case():
+    """L = sum (|U|^2 - w)^2 / sum w^2 and G = 4 (|U|^2 - w) U / sum w^2 by
+    hand: |U|^2 = [[1, 1], [4, 0]], w = [[2, 1], [1, 1]], so the mismatch
+    is [[-1, 0], [3, -1]], L = 11/7 and G = [[-4/7, 0], [24/7, 0]]."""
+    u = np.array([[1.0, 1j], [2.0, 0.0]])
+    w = np.array([[2.0, 1.0], [1.0, 1.0]])
+    loss, g = M.fluence_loss(u, w)
+    assert loss == pytest.approx(11.0 / 7.0, rel=1e-15)
+    assert np.allclose(g, np.array([[-4.0 / 7.0, 0.0], [24.0 / 7.0, 0.0]]), rtol=0, atol=1e-15)
+    # the normalisation: scaling the target and |U|^2 together leaves L
+    l2, _ = M.fluence_loss(3.0 * u, 9.0 * w)
+    assert l2 == pytest.approx(loss, rel=1e-14)
+    assert M.fluence_loss(u, np.abs(u) ** 2 + 0.0)[0] == 0.0
+
+
+# ------------------------------ R9: saturating plasma, by its own properties
+def _phase_per_unit(terms, x):
+    """Phase of one step divided by k0 n2 I_a dz, at x = I / I_a."""
+    inst = _inst(terms=terms)
+    scr = M.Screen.of(inst)
+    ph, dph = scr.phase(np.asarray(x, dtype=float) * W.I_A)
+    kn = scr.k0 * scr.n2 * scr.dz
+    return ph / (kn * W.I_A), dph / kn
+
+
+def test_saturating_plasma_caps_the_total_index():
+    """With the plasma term Kerr + plasma is n2 I / (1 + x^(K-1)) (K = 8):
+    it peaks at x* = 6^(-1/7) with the value (6/7) 6^(-1/7) = 0.6636 n2 I_a,
+    the reading's bounded per-step phase.  An exponent off by one, a dropped
+    I_a or a sign flip moves the peak or removes it."""
+    kp = W.TERM_KERR | W.TERM_PLASMA
+    xs = 6.0 ** (-1.0 / 7.0)
+    ph, dph = _phase_per_unit(kp, [xs])
+    assert xs == pytest.approx(0.77417, abs=1e-5)
+    assert ph[0] == pytest.approx(6.0 / 7.0 * xs, rel=1e-14)
+    assert ph[0] == pytest.approx(0.6636, abs=1e-4)
+    assert abs(dph[0]) < 1e-13              # stationary at x*
+    grid = np.linspace(0.0, 5.0, 50001)
+    g, _ = _phase_per_unit(kp, grid)
+    assert g.max() <= ph[0] * (1 + 1e-15)
+    assert grid[np.argmax(g)] == pytest.approx(xs, abs=1e-4)
+    # above the peak the index falls like x^-(K-2): x/(1+x^7) at x = 4 over x = 2
+    big, _ = _phase_per_unit(kp, [2.0, 4.0])
+    assert big[1] / big[0] == pytest.approx(2.0 * 129.0 / 16385.0, rel=1e-12)
+
+
+def test_plasma_term_scales_as_i_to_the_k_at_low_intensity():
+    """The plasma phase alone is -x^K/(1 + x^(K-1)) per unit: at low
+    intensity the power law of Eq. (3) with K = 8 and a negative sign."""
+    ph, _ = _phase_per_unit(W.TERM_PLASMA, [1e-3, 2e-3])
+    assert ph[0] < 0 and ph[1] < 0
+    slope = math.log(ph[1] / ph[0]) / math.log(2.0)
+    assert slope == pytest.approx(W.K_MPA, abs=1e-5)
+    assert ph[0] == pytest.approx(-(1e-3) ** 8 / (1 + (1e-3) ** 7), rel=1e-14)
+
+
+# ------------------------------------------ R10: the ansatz at hand points
+@pytest.mark.parametrize("theta,x,re,im", [
+    ((1, 0, 0, 0, 0, 0, 0, 0), 1.0, 0.5, 0.0),              # x/(1+x^4)
+    ((0, 2, 0, 0, 0, 0, 0, 0), 2.0, 8.0 / 17.0, 0.0),       # 2 x^2/(1+x^4)
+    ((1, 1, 1, 1, 0, 0, 0, 0), 1.0, 2.0, 0.0),              # (x+x^2+x^3+x^4)/2
+    ((0, 0, 0, 0, 0, 0, 0, 3), 0.5, 0.0, 3.0 / 17.0),       # 3 x^4/(1+x^4)
+    ((0, 0, 0, 0, 4, 0, -1, 0), 2.0, 0.0, 0.0),             # (4x - x^3)/(1+x^4)
+    ((0, 0, 2, 0, 1, 0, 0, 0), 3.0, 54.0 / 82.0, 3.0 / 82.0),
+])
+def test_ansatz_at_hand_computed_points(theta, x, re, im):
+    """f(x) = [sum_p th_p x^p + i sum_p th_{4+p} x^p] / (1 + x^4) applied as
+    phase k0 n2 I_a dz Re f and log-amplitude -k0 n2 I_a dz Im f; the
+    values are fractions worked out by hand."""
+    inst = _inst(terms=W.TERM_ANSATZ, theta=theta)
+    scr = M.Screen.of(inst)
+    kn_ia = scr.k0 * scr.n2 * scr.dz * W.I_A
+    ph, _ = scr.phase(np.array([x * W.I_A]))
+    la, _ = scr.log_amp(np.array([x * W.I_A]))
+    assert ph[0] == pytest.approx(kn_ia * re, rel=1e-14, abs=1e-300)
+    assert la[0] == pytest.approx(-kn_ia * im, rel=1e-14, abs=1e-300)

@@ -234,3 +234,49 @@ def test_instance_screens_with_subharmonics_add_the_low_part():
     assert all(np.array_equal(base[s], same[s]) for s in steps)
     assert np.allclose(more[steps[0]] - base[steps[0]], lre, atol=1e-12, rtol=0)
     assert np.allclose(more[steps[1]] - base[steps[1]], lim, atol=1e-12, rtol=0)
+
+
+def _ring(q2):
+    """Brute-force count of integer modes with 0 < mx^2 + my^2 <= q2."""
+    r = int(math.isqrt(int(q2))) + 1
+    return sum(1 for mx in range(-r, r + 1) for my in range(-r, r + 1)
+               if 0 < mx * mx + my * my <= q2)
+
+
+@pytest.mark.parametrize("length", [0.06, 0.05, 8e-3, 0.12, 1.0])
+def test_step_band_edge_is_decided_on_integer_modes(length):
+    """Eq. (10) band, low-pass reading: a k_h placed on the |m| = 5 ring
+    (k_h = 2 pi 5 / L, formed the way a caller would) keeps all 12 modes of
+    that ring (m^2 = 25: (+-5, 0), (0, +-5), (+-3, +-4), (+-4, +-3)) for any
+    window; one part in 1e9 less drops them.  The decision is on integers,
+    so it cannot depend on how a wavenumber was rounded."""
+    n = 64
+    val = 1.0 / (n * (length / n))
+    for k_h in (2.0 * math.pi * (5 * val), 2.0 * math.pi * 5 / length):
+        amp = T.step_amplitude(n, length, 1e-3, k_h)
+        assert int((amp > 0).sum()) == _ring(25) == 80
+        below = T.step_amplitude(n, length, 1e-3, k_h * (1 - 1e-9))
+        assert int((below > 0).sum()) == _ring(24) == 80 - 12
+    m = T.mode_indices(n)
+    assert m[0] == 0 and m[5] == 5 and m[-5] == -5 and m[n // 2] == n // 2
+
+
+def test_band_radius_in_mode_units():
+    """q2 = (k_h L / 2 pi)^2 up to the 2^-40 slack."""
+    assert T.band_q2(2.0, 2 * math.pi * 3 / 2.0) == pytest.approx(9.0, rel=1e-12)
+    assert 9.0 <= T.band_q2(2.0, 2 * math.pi * 3 / 2.0) < 9.0 * (1 + 2e-12)
+    assert T.band_q2(0.5, 2 * math.pi) == pytest.approx(0.25, rel=1e-12)
+
+
+def test_screens_closer_than_a_step_are_refused():
+    """A screen spacing below dz would put two screens on one step (or one
+    before the first step): refused rather than silently merged."""
+    import workloads as W
+    inst = W.Instance(n=16, length=0.01, dz=0.1, n_steps=9, medium=W.Medium(terms=W.TERM_TURB),
+                      w0=1e-3, power=1.0, sigma=0.0, seed=0, cn2=1e-14,
+                      screen_dz=0.05, n_screens=4)
+    with pytest.raises(ValueError):
+        T.instance_screens(inst)
+    # at screen_dz = dz every screen has its own step, starting at step 0
+    inst.screen_dz = 0.1
+    assert sorted(T.instance_screens(inst)) == [0, 1, 2, 3]
