@@ -126,17 +126,33 @@ int ssfm_create(const ssfm_instance_desc* desc, int32_t n_inst,
 /* Release the context's host objects (not the workspace).  Synchronises. */
 int ssfm_destroy(ssfm_ctx* ctx);
 
-/* Load instance inst's field U [sqrt(W/m^2)], complex128 n*n from host or
- * device memory; resets that instance's step counter to 0. */
+/* Initial field of instance inst: the beam entering the medium (Math and
+ * Equations: the problem starts from a given input field; Eq. (7) is the
+ * paper's Gaussian beam, U = A exp(-(r/r_n)^2)).  src: n*n complex128
+ * U [sqrt(W/m^2)] in host or device memory (where), row-major [y][x],
+ * read before return (host) or on the stream (device); the caller keeps
+ * ownership.  The instance's own step count, which places its turbulence
+ * screens, restarts at 0; the other instances keep their fields (with any
+ * pending screen applied) and their step counts.  Drops a recorded march
+ * and its cotangents.  SSFM_EINVAL for inst out of range or src NULL. */
 int ssfm_set_field(ssfm_ctx* ctx, int32_t inst, const void* src, int32_t where);
 
-/* Ansatz parameters theta[8] of instance inst (Eq. (6)/(9) stand-in):
- * f_theta(x) = [sum_p theta_p x^p + i sum_p theta_{4+p} x^p] / (1 + x^4). */
+/* Ansatz parameters theta[8] of instance inst, the sparse-grid stand-in for
+ * the effective screen f_lens[U, D] of Eq. (2) and its parameters D (Math
+ * and Equations, Eq. (2), (6), (9)):
+ * f_theta(x) = [sum_p theta_p x^p + i sum_p theta_{4+p} x^p] / (1 + x^4),
+ * x = I / I_a, applied as exp(i k0 n2 I_a dz f_theta) every step.  theta:
+ * host double[8], copied.  Drops a recorded march (its stored fields were
+ * made with the old theta).  SSFM_EINVAL for a non-finite entry. */
 int ssfm_set_theta(ssfm_ctx* ctx, int32_t inst, const double* theta);
 
-/* Generate every instance's turbulence phase screens on the device
- * (Philox4x32-10 white noise, Kolmogorov spectrum or the instance's step
- * spectrum, inverse FFT). */
+/* Generate every instance's turbulence phase screens eps_t on the device
+ * by the spectral method of Eq. (9)-(10) (Multiple filamentation regime in
+ * turbulent air): Philox4x32-10 white noise per Fourier mode, shaped by the
+ * Kolmogorov phase spectrum (r0 from cn2 and screen_dz) or the instance's
+ * Eq. (10) step spectrum, inverse FFT; one draw gives two screens (its real
+ * and imaginary parts).  Screens live in the workspace.  Drops a recorded
+ * march (it used the previous screens). */
 int ssfm_gen_screens(ssfm_ctx* ctx);
 
 /* Splitting of each z step.  SSFM_LIE (default): diffraction L(dz), then
@@ -182,8 +198,10 @@ int ssfm_set_fd_iterations(ssfm_ctx* ctx, int32_t iterations);  /* 1..64 */
  * r0 from cn2 and screen_dz, Eq. (9)), or SSFM_SPECTRUM_STEP, Eq. (10) read
  * as a low-pass step: every Fourier mode with 0 < kappa <= kappa_h
  * [rad/m] gets amplitude sqrt(tau) (tau [rad^2] per mode), the others 0.
- * kx = 2 pi (m (1 / (n (L / n)))) per axis in FP64, and the band is decided
- * as kx^2 + ky^2 <= kappa_h^2 with correctly rounded products and sums. */
+ * The mode of integer indices (mx, my) has kappa = 2 pi |m| / L, so the band
+ * is decided on the integers: 0 < mx^2 + my^2 <= q2 with
+ * q2 = (kappa_h L / 2 pi)^2 (1 + 2^-40), formed once in FP64 (the slack
+ * keeps a ring that kappa_h was placed on, kappa_h = 2 pi M / L, inside). */
 enum { SSFM_SPECTRUM_KOLMOGOROV = 0, SSFM_SPECTRUM_STEP = 1 };
 int ssfm_set_screen_spectrum(ssfm_ctx* ctx, int32_t inst, int32_t kind, double tau,
                              double kappa_h);
@@ -195,7 +213,7 @@ int ssfm_set_screen_spectrum(ssfm_ctx* ctx, int32_t inst, int32_t kind, double t
  * the low end to the implementation) adds, to every screen pair, the modes
  * f = (mx, my) / (3^p L) for p = 1..P and (mx, my) in {-1, 0, 1}^2 without
  * (0, 0), with amplitude sqrt(density(f)) / (3^p L) (density: the
- * Kolmogorov Phi, or tau L^2 inside kappa^2 <= kappa_h^2 for the step
+ * Kolmogorov Phi, or tau L^2 inside mx^2 + my^2 <= 9^p q2 for the step
  * spectrum) and coefficient c = z0 + i z1 from Philox4x32-10 counter
  * (q, p, pair, 1), q = 3 (my + 1) + (mx + 1), key = seed; the sum over the
  * cell-centred grid, minus its grid mean, adds its real part to screen
@@ -207,38 +225,60 @@ int ssfm_set_subharmonics(ssfm_ctx* ctx, int32_t inst, int32_t levels);
 int ssfm_get_screen(ssfm_ctx* ctx, int32_t inst, int32_t s, void* dst,
                     int32_t where);
 
-/* March every instance n_steps further (asynchronous).  Per-step power and
- * peak intensity are accumulated in FP64 for ssfm_get_diag(). */
+/* March every instance n_steps further by the split-step method (Math and
+ * Equations: Eq. (1) with the Eq. (3) terms, Eq. (9) in turbulent air):
+ * per step, exact diffraction exp(-i (kx^2 + ky^2) dz / 2k0) in Fourier
+ * space, then the pointwise screen of the instance's terms, then its
+ * turbulence screen if one is scheduled.  Asynchronous on the context's
+ * stream.  Per-step power and peak intensity are accumulated in FP64 for
+ * ssfm_get_diag().  SSFM_EINVAL for n_steps < 0; 0 does nothing. */
 int ssfm_propagate(ssfm_ctx* ctx, int64_t n_steps);
 
-/* Current field of instance inst, complex128 SI, to host or device. */
+/* Current field U of instance inst (Eq. (1)): n*n complex128
+ * [sqrt(W/m^2)], row-major [y][x], written to the caller's host or device
+ * buffer dst.  Synchronises when dst is on the host. */
 int ssfm_get_field(ssfm_ctx* ctx, int32_t inst, void* dst, int32_t where);
 
-/* Current intensity (fluence proxy, w = U U*) of instance inst [W/m^2],
- * float64 n*n, to host or device. */
+/* Current fluence w = U U* of instance inst (the stationary model's
+ * fluence, Math and Equations before Eq. (4); EL benchmarking) [W/m^2]:
+ * n*n float64 to the caller's host or device buffer dst.  Synchronises
+ * when dst is on the host. */
 int ssfm_get_intensity(ssfm_ctx* ctx, int32_t inst, void* dst, int32_t where);
 
-/* Power sum |U|^2 dx^2 [W] and peak intensity [W/m^2] after each of the
- * last n steps of the most recent propagate/record call (FP64, host arrays
- * of length n).  Synchronises.  Returns SSFM_ENONFINITE if a power is not
- * finite. */
+/* The monitored beam quantities (Math and Equations: the drop of the pulse
+ * energy and the maximum intensity along the path; EL benchmarking, Fig. 3
+ * and 6): power sum |U|^2 dx^2 [W] and peak intensity [W/m^2] after each of
+ * the last n steps of the most recent propagate/record call, reduced in
+ * FP64 in a fixed order.  power, peak: host double[n] (either may be NULL).
+ * Synchronises.  SSFM_EINVAL if n exceeds the steps kept; SSFM_ENONFINITE if
+ * a power is not finite. */
 int ssfm_get_diag(ssfm_ctx* ctx, int32_t inst, double* power, double* peak,
                   int64_t n);
 
-/* Forward march of n_steps (<= max_steps) from the current fields that keeps
- * what the adjoint needs: the field at the start of every segment of M steps
- * (or every pre-screen field when M >= n_steps). */
+/* The march of ssfm_propagate (Eq. (1), (3), (9)) over n_steps (<=
+ * max_steps) from the current fields, keeping what its adjoint needs for
+ * fitting the screen parameters to a discrepancy (Math and Equations: the
+ * effective screen's parameters minimise the residual against the dense
+ * solution): the field at the start of every segment of M steps, or every
+ * pre-screen field when M >= n_steps.  Drops earlier cotangents.
+ * SSFM_EINVAL if n_steps exceeds max_steps or is < 1. */
 int ssfm_forward_record(ssfm_ctx* ctx, int64_t n_steps);
 
-/* Cotangent of the final field of instance inst,
- * G = dL/dRe U_N + i dL/dIm U_N [1/sqrt(W/m^2)], complex128 from host or
- * device. */
+/* Cotangent of the recorded march's final field for instance inst, for a
+ * discrepancy L chosen by the caller (Math and Equations leaves the measure
+ * to the problem): G = dL/dRe U_N + i dL/dIm U_N [1/sqrt(W/m^2)], n*n
+ * complex128 from host or device.  SSFM_ESTATE without a recorded march. */
 int ssfm_set_cotangent(ssfm_ctx* ctx, int32_t inst, const void* g, int32_t where);
 
-/* Fluence-mismatch loss of instance inst against a target w [W/m^2]
- * (float64 n*n, host or device):
+/* The discrepancy between the sparse-grid fluence and a target (Math and
+ * Equations: the residual between the true dense-grid solution and the
+ * effective one; here the L2 fluence mismatch) for instance inst, target
+ * w [W/m^2] n*n float64 on host or device (e.g. a dense fluence block-
+ * averaged by ssfm_block_mean):
  *   L = sum (|U_N|^2 - w)^2 / sum w^2,
- * which also sets the cotangent of U_N.  Writes L to *loss (synchronises). */
+ * which also sets the cotangent of U_N for ssfm_backward.  Writes L to
+ * *loss (may be NULL); synchronises.  SSFM_ESTATE without a recorded
+ * march. */
 int ssfm_fluence_loss(ssfm_ctx* ctx, int32_t inst, const void* target,
                       int32_t where, double* loss);
 
@@ -251,8 +291,13 @@ int ssfm_fluence_loss(ssfm_ctx* ctx, int32_t inst, const void* target,
 int ssfm_fluence_mismatch(ssfm_ctx* ctx, int32_t inst, const void* target,
                           int32_t where, double* loss);
 
-/* Exact discrete adjoint of the recorded march back to its first step
- * (recomputing each segment from its checkpoint when M < n_steps). */
+/* Exact discrete adjoint of the recorded march (the Eq. (1), (3), (9)
+ * split steps in reverse) back to its first step, recomputing each segment
+ * from its checkpoint when M < n_steps; gives dL/dU_0 and dL/dtheta for
+ * fitting the screen parameters by gradients (Math and Equations fits them
+ * with a genetic algorithm).  Instances without a cotangent since the
+ * record contribute nothing to L: their gradients are zero.  SSFM_ESTATE
+ * without a record or without any cotangent. */
 int ssfm_backward(ssfm_ctx* ctx);
 
 /* Gradient of L w.r.t. instance inst's initial field (complex128 SI, same
@@ -267,7 +312,10 @@ int ssfm_get_grad_field(ssfm_ctx* ctx, int32_t inst, void* dst, int32_t where);
 int ssfm_get_grad_theta(ssfm_ctx* ctx, int32_t inst, double* g);
 
 /* Block mean of a float64 n*n device array into (n/b)*(n/b) (device to
- * device), used to average a dense reference fluence onto a sparse grid. */
+ * device): the dense-grid fluence averaged onto the sparse grid of the
+ * effective solution (Math and Equations: dense true solutions against
+ * sparse effective ones).  dst[i][j] = mean of src over rows b i .. b i +
+ * b - 1 and columns b j .. b j + b - 1.  SSFM_EINVAL unless b divides n. */
 int ssfm_block_mean(ssfm_ctx* ctx, const double* src, int32_t n, int32_t b,
                     double* dst);
 
@@ -326,6 +374,7 @@ int ssfm_lens_vjp(ssfm_ctx* ctx, int32_t inst, const ssfm_lens* lens, const void
  * the labelling's bounded union loop hit its cap (not expected). */
 int ssfm_hot_areas(ssfm_ctx* ctx, const double* w, int32_t n, double threshold,
                    int32_t periodic, int64_t* count);
+
 
 /* Spatial moment of a fluence (Eq. (8) family, read as Q(p, m) = sum over
  * the cell-centred grid of w^p (x^2 + y^2)^m dx^2, dx = length / n,

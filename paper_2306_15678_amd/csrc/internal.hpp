@@ -16,6 +16,8 @@ struct InstDev {
   int64_t prop_off;    // element offset of its propagator table (n entries)
   int64_t tw_off;      // element offset of the twiddle table for n
   int64_t steps_off;   // offset of its screen step list in the step table
+  int64_t step_base;   // context step at which this beam's field was last set:
+                       // its own step index (screens) is the context's minus this
   double cK;           // k0 n2 I_a dz
   double cM;           // (K-1) beta_K I_a^(K-1) dz
   double inv2k1;       // 1 / (2 (K-1))

@@ -437,45 +437,63 @@ template hipError_t launch_copy<double>(const void*, void*, int64_t, hipStream_t
 
 // One thread per (beam, step): fixed-order sum / max over the beam's
 // column work items.
-__global__ void k_diag_finalize(const double* __restrict__ part, int n_work,
-                                const int32_t* __restrict__ wbegin, int steps,
-                                double* __restrict__ diag, int64_t ring0, int64_t cap) {
-  const int b = blockIdx.y;
-  const int step = blockIdx.x * blockDim.x + threadIdx.x;
-  if (step >= steps) return;
+// One workgroup per (beam, step): thread t sums the beam's work items
+// t, t + 256, ... in order, then a fixed tree across the workgroup, so the
+// result depends only on the beam's own item count (a beam in a batch sums
+// exactly as it does alone).
+__global__ void __launch_bounds__(256)
+k_diag_finalize(const double* __restrict__ part, int n_work, const int32_t* __restrict__ wbegin,
+                double* __restrict__ diag, int64_t ring0, int64_t cap) {
+  __shared__ double red[8];
+  const int b = blockIdx.x;
+  const int step = blockIdx.y;
   const double* p = part + int64_t(step) * n_work * 2;
-  double s = 0.0, m = 0.0;
-  for (int w = wbegin[b]; w < wbegin[b + 1]; ++w) {
-    s += p[2 * w];
-    m = fmax(m, p[2 * w + 1]);
+  double s[1] = {0.0}, m[1] = {0.0};
+  for (int w = wbegin[b] + int(threadIdx.x); w < wbegin[b + 1]; w += 256) {
+    s[0] += p[2 * w];
+    m[0] = fmax(m[0], p[2 * w + 1]);
   }
-  const int64_t slot = (ring0 + step) % cap;
-  diag[(int64_t(b) * cap + slot) * 2 + 0] = s;
-  diag[(int64_t(b) * cap + slot) * 2 + 1] = m;
+  block_reduce<1, 256, false>(s, red);
+  block_reduce<1, 256, true>(m, red + 4);
+  if (threadIdx.x == 0) {
+    const int64_t slot = (ring0 + step) % cap;
+    diag[(int64_t(b) * cap + slot) * 2 + 0] = s[0];
+    diag[(int64_t(b) * cap + slot) * 2 + 1] = m[0];
+  }
 }
 
 hipError_t launch_diag_finalize(const double* part, int n_work, const int32_t* wbegin,
                                 int n_beams, int steps, double* diag, int64_t ring0,
                                 int64_t cap, double, hipStream_t s) {
   if (steps <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_diag_finalize, dim3((steps + 63) / 64, n_beams), dim3(64), 0, s, part,
-                     n_work, wbegin, steps, diag, ring0, cap);
+  hipLaunchKernelGGL(k_diag_finalize, dim3(n_beams, steps), dim3(256), 0, s, part, n_work,
+                     wbegin, diag, ring0, cap);
   return hipGetLastError();
 }
 
-__global__ void k_reduce_rows(const double* __restrict__ part, int width,
-                              const int32_t* __restrict__ begin, double* __restrict__ out) {
+// Per beam (one workgroup each), the column sums of its rows of a
+// [rows][width] array, width <= 8: strided partial sums then a fixed tree.
+__global__ void __launch_bounds__(256)
+k_reduce_rows(const double* __restrict__ part, int width, const int32_t* __restrict__ begin,
+              double* __restrict__ out) {
+  __shared__ double red[4 * 8];
   const int b = blockIdx.x;
-  const int k = threadIdx.x;
-  if (k >= width) return;
-  double s = 0.0;
-  for (int r = begin[b]; r < begin[b + 1]; ++r) s += part[int64_t(r) * width + k];
-  out[int64_t(b) * width + k] = s;
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int r = begin[b] + int(threadIdx.x); r < begin[b + 1]; r += 256) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < width) s[k] += part[int64_t(r) * width + k];
+  }
+  block_reduce<8, 256, false>(s, red);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < width; ++k) out[int64_t(b) * width + k] = s[k];
+  }
 }
 
 hipError_t launch_reduce_rows(const double* part, int width, const int32_t* begin,
                               int n_beams, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_rows, dim3(n_beams), dim3(64), 0, s, part, width, begin, out);
+  if (width < 1 || width > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_rows, dim3(n_beams), dim3(256), 0, s, part, width, begin, out);
   return hipGetLastError();
 }
 
@@ -492,17 +510,18 @@ k_sumsq_part(const double* __restrict__ x, int64_t n, double inv_scale, double* 
   if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
-__global__ void k_sum_small(const double* part, int n, double* out) {
-  if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int i = 0; i < n; ++i) s += part[i];
-  out[0] = s;
+// Sum of n <= 256 partials: one per thread, then a fixed tree.
+__global__ void __launch_bounds__(256) k_sum_small(const double* part, int n, double* out) {
+  __shared__ double red[4];
+  double s[1] = {int(threadIdx.x) < n ? part[threadIdx.x] : 0.0};
+  block_reduce<1, 256, false>(s, red);
+  if (threadIdx.x == 0) out[0] = s[0];
 }
 
 hipError_t launch_sumsq(const double* x, int64_t n, double inv_scale, double* partial,
                         double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_sumsq_part, dim3(256), dim3(256), 0, s, x, n, inv_scale, partial);
-  hipLaunchKernelGGL(k_sum_small, dim3(1), dim3(64), 0, s, partial, 256, out);
+  hipLaunchKernelGGL(k_sum_small, dim3(1), dim3(256), 0, s, partial, 256, out);
   return hipGetLastError();
 }
 
@@ -534,8 +553,7 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 // Phi(f) df^2 = amp0^2 * m^(-11/3) with m = |(signed col, signed row)|.
 template <typename R>
 __global__ void k_noise(const InstDev* inst, int b, int pair, uint32_t k0, uint32_t k1,
-                        double amp0, int kind, double kappa_h, double freq_unit,
-                        cx<R>* __restrict__ dst) {
+                        double amp0, int kind, double band_q2, cx<R>* __restrict__ dst) {
   const InstDev& in = inst[b];
   const int n = in.n;
   const int64_t n2 = int64_t(n) * n;
@@ -551,18 +569,13 @@ __global__ void k_noise(const InstDev* inst, int b, int pair, uint32_t k0, uint3
     sincospi(2.0 * u2, &sn, &cs);
     const int mx = (col <= n / 2) ? col : col - n;
     const int my = (row <= n / 2) ? row : row - n;
+    // |m|^2 is an exact integer (at most n^2 / 2)
+    const double m2 = double(int64_t(mx) * mx + int64_t(my) * my);
     double a;
     if (kind == 1) {
-      // each product and sum rounded on its own (no contraction into an
-      // fma): the same FP64 operations as the wavenumber grid
-      // 2 pi fftfreq(n, L / n), and the band edge decided on squares
-#pragma clang fp contract(off)
-      const double kx = 6.283185307179586 * (double(mx) * freq_unit);
-      const double ky = 6.283185307179586 * (double(my) * freq_unit);
-      const double kap2 = kx * kx + ky * ky;
-      a = (kap2 > 0.0 && kap2 <= kappa_h * kappa_h) ? amp0 : 0.0;
+      // Eq. (10) band on the integer mode indices: 0 < |m|^2 <= q2
+      a = (m2 > 0.0 && m2 <= band_q2) ? amp0 : 0.0;
     } else {
-      const double m2 = double(mx) * mx + double(my) * my;
       a = (m2 > 0.0) ? amp0 * pow(m2, -11.0 / 12.0) : 0.0;
     }
     dst[in.off + i] = {R(a * rr * cs), R(a * rr * sn)};
@@ -571,17 +584,16 @@ __global__ void k_noise(const InstDev* inst, int b, int pair, uint32_t k0, uint3
 
 template <typename R>
 hipError_t launch_noise(const InstDev* inst, int b, int n, int pair, uint64_t seed,
-                        double amp0, int kind, double kappa_h, double freq_unit, void* dst,
-                        hipStream_t s) {
+                        double amp0, int kind, double band_q2, void* dst, hipStream_t s) {
   hipLaunchKernelGGL((k_noise<R>), dim3(grid_for(int64_t(n) * n, 256)), dim3(256), 0, s,
                      inst, b, pair, uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32), amp0,
-                     kind, kappa_h, freq_unit, static_cast<cx<R>*>(dst));
+                     kind, band_q2, static_cast<cx<R>*>(dst));
   return hipGetLastError();
 }
 template hipError_t launch_noise<float>(const InstDev*, int, int, int, uint64_t, double, int,
-                                        double, double, void*, hipStream_t);
+                                        double, void*, hipStream_t);
 template hipError_t launch_noise<double>(const InstDev*, int, int, int, uint64_t, double, int,
-                                         double, double, void*, hipStream_t);
+                                         double, void*, hipStream_t);
 
 // Subharmonic part of the screens, for all beams at once.  Coefficients
 // (grid: pairs x beams, one workgroup each): thread t < 8 levels draws mode t
@@ -621,16 +633,14 @@ __global__ void __launch_bounds__(256) k_subharm_coef(const SubBeam* __restrict_
     for (int i = 0; i < p; ++i) pow3 *= 3.0;
     const double df = 1.0 / (pow3 * sp.length);
     double a;
-    {
-#pragma clang fp contract(off)
+    if (sp.kind == 1) {
+      // f = m / (3^p L): kappa <= kappa_h reads |m|^2 <= 9^p q2 on the
+      // integer indices (one correctly rounded product, 9^p exact)
+      const double m2 = double(mx * mx + my * my);
+      a = (m2 <= sp.band_q2 * (pow3 * pow3)) ? sqrt(sp.tau * sp.length * sp.length) * df : 0.0;
+    } else {
       const double fx = double(mx) * df, fy = double(my) * df;
-      if (sp.kind == 1) {
-        const double kx = 6.283185307179586 * fx, ky = 6.283185307179586 * fy;
-        const double kap2 = kx * kx + ky * ky;
-        a = (kap2 <= sp.kappa_h * sp.kappa_h) ? sqrt(sp.tau * sp.length * sp.length) * df : 0.0;
-      } else {
-        a = sqrt(0.023 * pow(sp.r0, -5.0 / 3.0) * pow(hypot(fx, fy), -11.0 / 3.0)) * df;
-      }
+      a = sqrt(0.023 * pow(sp.r0, -5.0 / 3.0) * pow(hypot(fx, fy), -11.0 / 3.0)) * df;
     }
     const double wr = rr * cs * a, wi = rr * sn * a;
     blk[2 * t] = wr;

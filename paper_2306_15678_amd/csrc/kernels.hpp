@@ -127,11 +127,11 @@ hipError_t launch_sumsq(const double* x, int64_t n, double inv_scale,
                         double* partial, double* out, hipStream_t s);
 
 // White noise shaped by the screen spectrum: kind 0 Kolmogorov (amp0 (m^2)^(-11/12)),
-// kind 1 step (amp0 where 0 < kappa <= kappa_h, kappa = 2 pi m freq_unit per axis).
+// kind 1 step (amp0 where 0 < mx^2 + my^2 <= band_q2, integer mode indices).
 template <typename R>
 hipError_t launch_noise(const InstDev* inst, int b, int n, int pair,
-                        uint64_t seed, double amp0, int kind, double kappa_h,
-                        double freq_unit, void* dst, hipStream_t s);
+                        uint64_t seed, double amp0, int kind, double band_q2,
+                        void* dst, hipStream_t s);
 
 template <typename R>
 hipError_t launch_screen_to_f64(const R* plane, int64_t n_elem, double* dst,
@@ -165,5 +165,6 @@ hipError_t launch_moment(const double* w, int n, double dx, double p, int m, dou
 
 hipError_t launch_block_mean(const double* src, int n, int b, double* dst,
                              hipStream_t s);
+
 
 }  // namespace ssfm

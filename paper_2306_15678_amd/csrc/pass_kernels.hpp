@@ -44,15 +44,17 @@ __device__ __forceinline__ ScreenConst<R> screen_const(const InstDev& in) {
   return s;
 }
 
-// Turbulence plane applied after `step` (nullptr if none): the first screen
-// whose step equals `step`, by lower-bound search of the beam's
-// nondecreasing step list (a workgroup-uniform chain of log2(n_screens)
-// scalar loads instead of one per screen).
+// Turbulence plane applied after context step `step` (nullptr if none): the
+// screen whose step equals the beam's own step index (the context step
+// minus the step at which the beam's field was set), by lower-bound search
+// of the beam's increasing step list (a workgroup-uniform chain of
+// log2(n_screens) scalar loads instead of one per screen).
 template <typename R>
 __device__ __forceinline__ const R* find_plane(const R* screens, const int64_t* steps,
                                                const InstDev& in, int64_t step) {
   if (step < 0 || !(in.terms & T_TURB) || in.n_screens <= 0 || screens == nullptr)
     return nullptr;
+  step -= in.step_base;
   const int64_t* st = steps + in.steps_off;
   int lo = 0, hi = in.n_screens - 1;
   if (step < st[lo] || step > st[hi]) return nullptr;

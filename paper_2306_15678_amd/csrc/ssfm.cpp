@@ -82,6 +82,9 @@ int validate_desc(const ssfm_instance_desc* d, int32_t n_inst, int32_t precision
       return fail(SSFM_EINVAL, "instance %d: n_screens out of range", i);
     if ((x.terms & SSFM_TURB) && x.n_screens > 0 && (!(x.screen_dz > 0) || !(x.cn2 >= 0)))
       return fail(SSFM_EINVAL, "instance %d: turbulence needs screen_dz > 0, cn2 >= 0", i);
+    // closer screens could fall on one step (or before the first one)
+    if ((x.terms & SSFM_TURB) && x.n_screens > 0 && !(x.screen_dz >= x.dz))
+      return fail(SSFM_EINVAL, "instance %d: screen_dz %g below dz %g", i, x.screen_dz, x.dz);
   }
   return SSFM_OK;
 }
@@ -151,6 +154,7 @@ struct ssfm_ctx {
   // adjoint record
   int64_t rec_steps = 0, rec_step0 = 0;
   bool rec_valid = false, seeded = false, grads_valid = false;
+  std::vector<char> seeded_beam;  // per beam: cotangent set since the record
   bool use_graphs = true;
   std::map<std::tuple<int, int64_t, int64_t, int64_t, int64_t>, hipGraphExec_t> graphs;
   // Sampled pass timing (0: off): with timing_every = m, step s of a
@@ -166,11 +170,11 @@ struct ssfm_ctx {
   // second stream (default priority) and events for the overlapped backward
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  // per-chain streams and events for running the grid-size groups of one
-  // pass concurrently ([0]: main chain, [1]: auxiliary chain)
-  std::vector<hipStream_t> gstream[2];
-  std::vector<hipEvent_t> gjoin[2];
-  hipEvent_t gfork[2] = {nullptr, nullptr};
+  // streams and events for running the grid-size groups of one pass
+  // concurrently on the main chain (group g > 0 on gstream[g - 1])
+  std::vector<hipStream_t> gstream;
+  std::vector<hipEvent_t> gjoin;
+  hipEvent_t gfork = nullptr;
 
   template <typename T>
   T* at(size_t off) const {
@@ -191,11 +195,9 @@ struct ssfm_ctx {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (aux) (void)hipStreamDestroy(aux);
-    for (int k = 0; k < 2; ++k) {
-      for (auto s : gstream[k]) (void)hipStreamDestroy(s);
-      for (auto e : gjoin[k]) (void)hipEventDestroy(e);
-      if (gfork[k]) (void)hipEventDestroy(gfork[k]);
-    }
+    for (auto s : gstream) (void)hipStreamDestroy(s);
+    for (auto e : gjoin) (void)hipEventDestroy(e);
+    if (gfork) (void)hipEventDestroy(gfork);
   }
 };
 
@@ -212,6 +214,18 @@ std::vector<int64_t> screen_step_list(const ssfm_instance_desc& d) {
     out.push_back(int64_t(std::floor(zs / d.dz + 0.5)) - 1);
   }
   return out;
+}
+
+// Eq. (10) band in mode-index units: the Fourier mode m = (mx, my) of a
+// window of side L has kappa = 2 pi |m| / L, so kappa <= kappa_h reads
+// |m|^2 <= (kappa_h L / 2 pi)^2.  That bound is formed once here, with a
+// relative slack of 2^-40 so that a kappa_h placed on a ring of modes keeps
+// the ring whatever the rounding; the kernels then decide on the exact
+// integer |m|^2.
+double band_q2(double length, double kappa_h) {
+#pragma clang fp contract(off)
+  const double q = kappa_h * length / (2.0 * M_PI);
+  return q * q * (1.0 + 0x1p-40);
 }
 
 // Groups by grid size in first-appearance order.
@@ -453,6 +467,24 @@ int check_inst(ssfm_ctx* c, int32_t i) {
   return SSFM_OK;
 }
 
+// Forget a recorded march, its cotangents and gradients (the fields or
+// parameters it was recorded with have changed).
+void drop_record(ssfm_ctx* c) {
+  c->rec_valid = false;
+  c->seeded = false;
+  c->grads_valid = false;
+  c->seeded_beam.assign(c->desc.size(), 0);
+}
+
+// Copy beam table entries [b0, b1) to the device (stream-ordered; waits,
+// the host table may change right after).
+int upload_inst(ssfm_ctx* c, size_t b0, size_t b1) {
+  HIP_TRY(hipMemcpyAsync(c->ws + c->L.inst + sizeof(InstDev) * b0, &c->inst[b0],
+                         sizeof(InstDev) * (b1 - b0), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return SSFM_OK;
+}
+
 // ---------------------------------------------------------------- passes
 template <typename R>
 PassArgs<R> base_args(ssfm_ctx* c) {
@@ -465,35 +497,38 @@ PassArgs<R> base_args(ssfm_ctx* c) {
   return a;
 }
 
-// One pass over every beam: one launch per grid-size group.  With several
-// groups the launches run concurrently (group g > 0 on its own stream,
-// forked from and joined back to st), so their ramps and tails overlap.
+// One pass over every beam: one launch per grid-size group.  On the main
+// chain (the context's stream, the primary stream of a graph capture) the
+// groups run concurrently (group g > 0 on its own stream, forked from and
+// joined back to st), so their ramps and tails overlap.  On the auxiliary
+// chain (the checkpoint recompute, itself a fork of the main chain) they
+// run in sequence on that stream: a stream capture must join every fork
+// to its primary stream, and a fork of a fork would be joined to the
+// auxiliary stream instead.
 template <typename R>
 int run_pass(ssfm_ctx* c, int kind, PassArgs<R> a, hipStream_t st = nullptr,
              const hipEvent_t* ev = nullptr) {
   const bool col = is_col_kind(kind);
   if (!st) st = c->stream;
-  const int chain = (st == c->aux) ? 1 : 0;
   const size_t ng = c->groups.size();
-  const bool fork = ng > 1 && c->gstream[chain].size() + 1 >= ng;
+  const bool fork = st != c->aux && ng > 1 && c->gstream.size() + 1 >= ng;
   if (fork) {
-    HIP_TRY(hipEventRecord(c->gfork[chain], st));
-    for (size_t g = 1; g < ng; ++g)
-      HIP_TRY(hipStreamWaitEvent(c->gstream[chain][g - 1], c->gfork[chain], 0));
+    HIP_TRY(hipEventRecord(c->gfork, st));
+    for (size_t g = 1; g < ng; ++g) HIP_TRY(hipStreamWaitEvent(c->gstream[g - 1], c->gfork, 0));
   }
   for (size_t gi = 0; gi < ng; ++gi) {
     const Group& g = c->groups[gi];
     a.work = c->at<WorkItem>(c->L.work) + (col ? g.col_work_off : g.row_work_off);
     const int nb = col ? g.col_blocks : g.row_blocks;
     const int v = col ? g.col_var : g.row_var;
-    hipStream_t sg = (fork && gi > 0) ? c->gstream[chain][gi - 1] : st;
+    hipStream_t sg = (fork && gi > 0) ? c->gstream[gi - 1] : st;
     const LaunchEv le = ev ? LaunchEv{ev[2 * gi], ev[2 * gi + 1]} : LaunchEv{nullptr, nullptr};
     HIP_TRY(launch_pass<R>(kind, g.n, v, nb, a, sg, ev ? &le : nullptr));
   }
   if (fork) {
     for (size_t g = 1; g < ng; ++g) {
-      HIP_TRY(hipEventRecord(c->gjoin[chain][g - 1], c->gstream[chain][g - 1]));
-      HIP_TRY(hipStreamWaitEvent(st, c->gjoin[chain][g - 1], 0));
+      HIP_TRY(hipEventRecord(c->gjoin[g - 1], c->gstream[g - 1]));
+      HIP_TRY(hipStreamWaitEvent(st, c->gjoin[g - 1], 0));
     }
   }
   return SSFM_OK;
@@ -729,6 +764,7 @@ int do_propagate(ssfm_ctx* c, int64_t n) {
     c->diag_valid = std::min<int64_t>(n, c->L.diag_cap);
     c->rec_valid = false;
     c->seeded = false;
+    c->seeded_beam.assign(c->desc.size(), 0);
     return SSFM_OK;
   }
   int r = run_forward(c, 0, step0 * 2 + (pend ? 1 : 0), n, step0,
@@ -741,6 +777,7 @@ int do_propagate(ssfm_ctx* c, int64_t n) {
   c->diag_valid = std::min<int64_t>(n, c->L.diag_cap);
   c->rec_valid = false;
   c->seeded = false;
+  c->seeded_beam.assign(c->desc.size(), 0);
   return SSFM_OK;
 }
 
@@ -845,9 +882,8 @@ int do_record(ssfm_ctx* c, int64_t n) {
   c->diag_valid = std::min<int64_t>(n, c->L.diag_cap);
   c->rec_steps = n;
   c->rec_step0 = step0;
+  drop_record(c);
   c->rec_valid = true;
-  c->seeded = false;
-  c->grads_valid = false;
   return SSFM_OK;
 }
 
@@ -917,6 +953,18 @@ template <typename R>
 int do_backward(ssfm_ctx* c) {
   if (!c->rec_valid) return fail(SSFM_ESTATE, "backward needs a preceding ssfm_forward_record");
   if (!c->seeded) return fail(SSFM_ESTATE, "backward needs a cotangent (set_cotangent/fluence_loss)");
+  // a beam without a cotangent contributes nothing to the loss: its
+  // cotangent and its seed-step theta partials are zero (else the adjoint
+  // would march whatever an earlier backward left there)
+  for (size_t b = 0; b < c->desc.size(); ++b) {
+    if (c->seeded_beam[b]) continue;
+    const int64_t n2 = int64_t(c->inst[b].n) * c->inst[b].n;
+    HIP_TRY(launch_fill_f64(reinterpret_cast<double*>(static_cast<char*>(c->field(c->L.Lam)) +
+                                                      c->inst[b].off * c->el),
+                            n2 * int64_t(c->el / 8), 0.0, c->stream));
+    HIP_TRY(launch_fill_f64(c->at<double>(c->L.seed_theta) + size_t(b) * 8 * c->L.max_n,
+                            8 * int64_t(c->inst[b].n), 0.0, c->stream));
+  }
   int r = maybe_graph(c, 2, c->rec_step0, c->rec_steps, 0, 0,
                       [&] { return enqueue_backward<R>(c); });
   if (r) return r;
@@ -992,7 +1040,7 @@ int do_gen_screens(ssfm_ctx* c) {
     e.sp.r0 = (sp.kind == SSFM_SPECTRUM_STEP) ? 0.0
                                                : std::pow(0.423 * k0 * k0 * d.cn2 * d.screen_dz, -0.6);
     e.sp.tau = sp.tau;
-    e.sp.kappa_h = sp.kappa_h;
+    e.sp.band_q2 = band_q2(d.length, sp.kappa_h);
     e.sp.length = d.length;
     e.tab_off = off;
     e.coef_off = off + 2 * int64_t(kMaxSubharmonicLevels) * d.n;
@@ -1023,9 +1071,8 @@ int do_gen_screens(ssfm_ctx* c) {
         const double r0 = std::pow(0.423 * k0 * k0 * d.cn2 * d.screen_dz, -0.6);
         amp0 = std::sqrt(0.023) * std::pow(d.length / r0, 5.0 / 6.0);
       }
-      const double freq_unit = 1.0 / (d.n * (d.length / d.n));
       HIP_TRY(launch_noise<R>(c->at<InstDev>(c->L.inst), int(b), d.n, p, d.seed, amp0, sp.kind,
-                              sp.kappa_h, freq_unit, c->field(c->L.Wk), c->stream));
+                              band_q2(d.length, sp.kappa_h), c->field(c->L.Wk), c->stream));
     }
     PassArgs<R> a = base_args<R>(c);
     a.src = c->field(c->L.Wk);
@@ -1259,9 +1306,7 @@ int do_apply_lens(ssfm_ctx* c, int b, const ssfm_lens& l) {
                                static_cast<const char*>(c->field(c->L.Wk)) + off * c->el,
                                int64_t(d.n) * d.n, p, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));  // the filter table above is a host temporary
-  c->rec_valid = false;
-  c->seeded = false;
-  c->grads_valid = false;
+  drop_record(c);
   return SSFM_OK;
 }
 
@@ -1321,13 +1366,22 @@ int do_set_field(ssfm_ctx* c, int b, const void* src, int32_t where) {
                            static_cast<char*>(c->field(c->L.S)) + off, int64_t(n) * n,
                            c->stream));
   }
-  c->step = 0;
+  // beam b starts its own step count (its screen schedule) here; the other
+  // beams keep theirs.  Once every beam has been set at the same step, the
+  // context count restarts at 0 (so marches from fresh fields reuse their
+  // captured graphs).
   c->pending = false;
   c->diag_valid = 0;
-  c->rec_valid = false;
-  c->seeded = false;
-  c->grads_valid = false;
-  return SSFM_OK;
+  drop_record(c);
+  c->inst[b].step_base = c->step;
+  bool same = true;
+  for (const InstDev& in : c->inst) same = same && (in.step_base == c->step);
+  if (same) {
+    for (InstDev& in : c->inst) in.step_base = 0;
+    c->step = 0;
+    return upload_inst(c, 0, c->inst.size());
+  }
+  return upload_inst(c, b, b + 1);
 }
 
 int do_select(ssfm_ctx* c, int32_t n, int32_t rv, int32_t cv) {
@@ -1418,6 +1472,7 @@ int ssfm_create(const ssfm_instance_desc* desc, int32_t n_inst, int32_t precisio
   c->precision = precision;
   c->el = precision == SSFM_FP64 ? 16 : 8;
   c->desc.assign(desc, desc + n_inst);
+  c->seeded_beam.assign(n_inst, 0);
   c->max_steps = max_steps;
   c->ckpt_every = ckpt_every;
   c->stream = static_cast<hipStream_t>(stream);
@@ -1433,16 +1488,14 @@ int ssfm_create(const ssfm_instance_desc* desc, int32_t n_inst, int32_t precisio
   HIP_TRY(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-  for (int k = 0; k < 2; ++k) {
-    HIP_TRY(hipEventCreateWithFlags(&c->gfork[k], hipEventDisableTiming));
-    for (size_t g = 1; g < c->groups.size(); ++g) {
-      hipStream_t sg;
-      hipEvent_t ej;
-      HIP_TRY(hipStreamCreateWithFlags(&sg, hipStreamNonBlocking));
-      HIP_TRY(hipEventCreateWithFlags(&ej, hipEventDisableTiming));
-      c->gstream[k].push_back(sg);
-      c->gjoin[k].push_back(ej);
-    }
+  HIP_TRY(hipEventCreateWithFlags(&c->gfork, hipEventDisableTiming));
+  for (size_t g = 1; g < c->groups.size(); ++g) {
+    hipStream_t sg;
+    hipEvent_t ej;
+    HIP_TRY(hipStreamCreateWithFlags(&sg, hipStreamNonBlocking));
+    c->gstream.push_back(sg);
+    HIP_TRY(hipEventCreateWithFlags(&ej, hipEventDisableTiming));
+    c->gjoin.push_back(ej);
   }
   int r = SSFM_DISPATCH(c, upload_plan, c.get());
   if (r) return r;
@@ -1469,14 +1522,15 @@ int ssfm_set_theta(ssfm_ctx* c, int32_t inst, const double* theta) {
     if (!std::isfinite(theta[p])) return fail(SSFM_EINVAL, "theta[%d] not finite", p);
     c->inst[inst].theta[p] = theta[p];
   }
-  HIP_TRY(hipMemcpyAsync(c->ws + c->L.inst + sizeof(InstDev) * inst, &c->inst[inst],
-                         sizeof(InstDev), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return SSFM_OK;
+  // a recorded march (its stored fields, the screen its adjoint applies)
+  // belongs to the old parameters
+  drop_record(c);
+  return upload_inst(c, inst, inst + 1);
 }
 
 int ssfm_gen_screens(ssfm_ctx* c) {
   if (int r = check_ctx(c)) return r;
+  drop_record(c);  // the recorded march used the previous screens
   return SSFM_DISPATCH(c, do_gen_screens, c);
 }
 
@@ -1554,10 +1608,9 @@ int ssfm_set_splitting(ssfm_ctx* c, int32_t scheme) {
   c->step = 0;
   c->pending = false;
   c->diag_valid = 0;
-  c->rec_valid = false;
-  c->seeded = false;
-  c->grads_valid = false;
-  return SSFM_OK;
+  drop_record(c);
+  for (InstDev& in : c->inst) in.step_base = 0;
+  return upload_inst(c, 0, c->inst.size());
 }
 
 namespace {
@@ -1635,6 +1688,7 @@ int ssfm_set_cotangent(ssfm_ctx* c, int32_t inst, const void* g, int32_t where) 
   if (r) return r;
   if (where == SSFM_HOST) HIP_TRY(hipStreamSynchronize(c->stream));
   c->seeded = true;
+  c->seeded_beam[inst] = 1;
   return SSFM_OK;
 }
 
@@ -1658,6 +1712,7 @@ int ssfm_fluence_loss(ssfm_ctx* c, int32_t inst, const void* target, int32_t whe
   for (int i = 0; i < n; ++i) s += part[i];
   if (loss) *loss = s / wsum;
   c->seeded = true;
+  c->seeded_beam[inst] = 1;
   return SSFM_OK;
 }
 

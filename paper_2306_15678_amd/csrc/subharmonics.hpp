@@ -17,13 +17,14 @@ constexpr int kSubPair = 256;
 
 // Spectrum of one beam's subharmonic modes: kind 0 Kolmogorov with Fried
 // parameter r0, kind 1 the step spectrum (tau per FFT cell, i.e. density
-// tau L^2, inside kappa^2 <= kappa_h^2).
+// tau L^2, inside the band: |m|^2 <= 9^p band_q2 for the level-p mode
+// f = m / (3^p L), band_q2 = (kappa_h L / 2 pi)^2 (1 + 2^-40)).
 struct SubharmonicSpec {
   int32_t levels;
   int32_t kind;
   double r0;
   double tau;
-  double kappa_h;
+  double band_q2;
   double length;
 };
 

@@ -79,6 +79,23 @@ def test_workspace_bytes_rejects_bad_arguments():
     assert h.ssfm_workspace_bytes(None, 1, 32, 0, 1, ctypes.byref(out)) == L.EINVAL
 
 
+def test_screens_closer_than_a_step_are_refused():
+    """Turbulence screens spaced below dz could share a step (or land before
+    the first one): refused, as the oracle refuses them; at screen_dz = dz
+    every screen has a step of its own."""
+    c3 = W.config3(1)[0]
+    arr = (L.InstanceDesc * 1)(desc_of(c3))
+    d = arr[0]
+    out = ctypes.c_size_t()
+    h = L.lib()
+    assert h.ssfm_workspace_bytes(arr, 1, 32, 0, 1, ctypes.byref(out)) == L.OK
+    d.screen_dz = 0.5 * d.dz
+    assert h.ssfm_workspace_bytes(arr, 1, 32, 0, 1, ctypes.byref(out)) == L.EINVAL
+    assert b"screen_dz" in h.ssfm_last_error()
+    d.screen_dz = d.dz
+    assert h.ssfm_workspace_bytes(arr, 1, 32, 0, 1, ctypes.byref(out)) == L.OK
+
+
 def test_create_checks_workspace_before_touching_the_device():
     c1 = W.config1()[0]
     arr = (L.InstanceDesc * 1)(desc_of(c1))

@@ -1,0 +1,175 @@
+"""Batched forward + adjoint (several beams of different grid sizes in one
+context, recorded and differentiated together) against the FP64 oracle, and
+the context's state rules around a recorded march.
+
+Beams come from the independent-beam workload (Kolmogorov screens every
+10 m) shortened to 8 steps of 0.1 m with denser screens so that every beam
+meets two screens, with the ansatz term on.  Each beam's gradient is checked
+against the oracle's FP64 adjoint of the same beam (1e-10 in FP64, 1e-4 in
+FP32 as for the single-beam gradients) and bitwise against the same beam
+recorded and differentiated alone.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import march as M
+from oracle import turbulence as T
+from paper_2306_15678_amd._lib import ESTATE, SsfmError
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 8
+
+
+def _prop(insts, precision, **kw):
+    from paper_2306_15678_amd.march import Propagator, desc_of
+    return Propagator([desc_of(i) for i in insts], precision=precision, **kw)
+
+
+def _report(name, **vals):
+    print(name, " ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}"
+                         for k, v in vals.items()), flush=True)
+
+
+def _beams():
+    """Four config-3 beams of sizes 256, 512, 768, 1024 (one of each), with
+    the ansatz and screens after steps 1 and 4 (screen_dz = 0.35 m, dz =
+    0.1 m: z_s = 0.175, 0.525 m, no rounding ties)."""
+    insts = W.config3()
+    out, seen = [], set()
+    for k, b in enumerate(insts):
+        if b.n in seen:
+            continue
+        seen.add(b.n)
+        th = tuple(np.array(W.THETA0) + W.random_theta(50 + k, 0.1))
+        terms = b.medium.terms | W.TERM_ANSATZ
+        out.append(dataclasses.replace(
+            b, n_steps=STEPS, screen_dz=0.35, n_screens=2, cn2=b.cn2 * 1e3,
+            theta=th, sigma=0.05, medium=dataclasses.replace(b.medium, terms=terms)))
+    assert sorted(i.n for i in out) == [256, 512, 768, 1024]
+    return out
+
+
+@pytest.fixture(scope="module")
+def oracle_grads():
+    out = []
+    for k, inst in enumerate(_beams()):
+        u0 = W.initial_field(inst)
+        tgt = W.synthetic_target(inst, 70 + k)
+        scr = T.instance_screens(inst)
+        assert sorted(scr) == [1, 4]
+        out.append((u0, tgt, M.gradient(u0, inst, screens=scr,
+                                        cotangent=lambda u, t=tgt: M.fluence_loss(u, t))))
+    return out
+
+
+def _record_backward(p, insts, data, seeded):
+    p.gen_screens()
+    for b, inst in enumerate(insts):
+        p.set_field(b, data[b][0])
+        p.set_theta(b, inst.theta)
+    p.forward_record(STEPS)
+    losses = {}
+    for b in seeded:
+        losses[b] = p.fluence_loss(b, data[b][1])
+    p.backward()
+    return losses
+
+
+@pytest.mark.parametrize("precision,ckpt", [(64, 3), (64, 100), (32, 3)])
+def test_batched_gradients_match_oracle_and_each_beam_alone(oracle_grads, precision, ckpt):
+    insts = _beams()
+    p = _prop(insts, precision, max_steps=STEPS, ckpt_every=ckpt)
+    losses = _record_backward(p, insts, oracle_grads, range(len(insts)))
+    tol = 1e-10 if precision == 64 else 1e-4
+    for b, inst in enumerate(insts):
+        u0, tgt, (loss, g_u0, g_th) = oracle_grads[b]
+        gu, gt = p.grad_field(b), p.grad_theta(b)
+        lerr = abs(losses[b] / loss - 1)
+        ferr = M.rel_l2(gu, g_u0)
+        terr = float(np.max(np.abs(gt - g_th)) / np.max(np.abs(g_th)))
+        _report(f"batched grad fp{precision} M={ckpt} beam {b} n={inst.n}",
+                loss=lerr, g_u0=ferr, g_theta=terr)
+        assert lerr < tol and ferr < tol and terr < tol, b
+        q = _prop([inst], precision, max_steps=STEPS, ckpt_every=ckpt)
+        _record_backward(q, [inst], [oracle_grads[b]], [0])
+        assert np.array_equal(gu, q.grad_field(0)), b
+        assert np.array_equal(gt, q.grad_theta(0)), b
+        q.close()
+    p.close()
+
+
+def test_unseeded_beam_gets_zero_gradient(oracle_grads):
+    """Only beams 0 and 2 carry a loss: their gradients are those of the
+    full batch, and beams 1 and 3 get exact zeros, also after an earlier
+    backward left other cotangents in the context."""
+    insts = _beams()
+    p = _prop(insts, 64, max_steps=STEPS, ckpt_every=3)
+    _record_backward(p, insts, oracle_grads, range(len(insts)))   # every beam seeded
+    _record_backward(p, insts, oracle_grads, [0, 2])               # now two of them
+    for b in range(len(insts)):
+        gu, gt = p.grad_field(b), p.grad_theta(b)
+        if b in (0, 2):
+            _, _, (loss, g_u0, g_th) = oracle_grads[b]
+            assert M.rel_l2(gu, g_u0) < 1e-10
+            assert np.max(np.abs(gt - g_th)) < 1e-10 * np.max(np.abs(g_th))
+        else:
+            assert not np.any(gu) and not np.any(gt), b
+    p.close()
+
+
+def test_changed_parameters_invalidate_the_record(oracle_grads):
+    """theta or the screens changed between record and backward: the
+    record no longer matches, so the adjoint refuses (no silently wrong
+    gradient)."""
+    insts = _beams()[:2]
+    p = _prop(insts, 64, max_steps=STEPS, ckpt_every=3)
+    for change in ("theta", "screens"):
+        _record_backward(p, insts, oracle_grads, [0, 1])
+        p.forward_record(STEPS)
+        p.fluence_loss(0, oracle_grads[0][1])
+        if change == "theta":
+            p.set_theta(1, np.array(insts[1].theta) * 1.01)
+        else:
+            p.gen_screens()
+        with pytest.raises(SsfmError) as e:
+            p.backward()
+        assert e.value.status == ESTATE
+        with pytest.raises(SsfmError):
+            p.fluence_loss(0, oracle_grads[0][1])
+    p.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-11), (32, 2e-5)])
+def test_setting_one_beam_mid_march_keeps_the_others_schedule(precision, tol):
+    """Two turbulent beams; after 3 steps beam 1 gets a new field and both
+    march 6 more.  Beam 0 meets its screens at its own steps 1, 4 and 8
+    (it was never reset); beam 1 restarts its own step count, so it meets
+    screens at its steps 1 and 4 of the new march (context steps 4 and 7;
+    at context step 4 beam 0 meets one too, at 8 only beam 0)."""
+    base = _beams()[0]
+    a = dataclasses.replace(base, n_screens=3, n_steps=9)
+    b = dataclasses.replace(base, n_screens=3, n_steps=6, seed=base.seed + 17,
+                            power=base.power * 0.8)
+    ua, ub, ub2 = W.initial_field(a), W.initial_field(b), W.initial_field(
+        dataclasses.replace(b, seed=b.seed + 1))
+    sa, sb = T.instance_screens(a), T.instance_screens(b)
+    assert sorted(sa) == [1, 4, 8]
+    ref_a = M.march(ua, a, n_steps=9, screens=sa).field
+    ref_b = M.march(ub2, b, n_steps=6, screens=sb).field
+    p = _prop([a, b], precision)
+    p.gen_screens()
+    p.set_field(0, ua)
+    p.set_field(1, ub)
+    p.set_theta(0, a.theta)
+    p.set_theta(1, b.theta)
+    p.propagate(3)
+    p.set_field(1, ub2)
+    p.propagate(6)
+    ea, eb = M.rel_l2(p.field(0), ref_a), M.rel_l2(p.field(1), ref_b)
+    _report(f"mid-march set_field fp{precision}", beam0=ea, beam1=eb)
+    assert ea < tol and eb < tol
+    p.close()

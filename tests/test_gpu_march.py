@@ -24,6 +24,20 @@ def _prop(insts, precision, **kw):
     return Propagator([desc_of(i) for i in insts], precision=precision, **kw)
 
 
+def _maxrel(a, b):
+    """Largest pointwise error over the largest reference magnitude: where a
+    localised error shows that a global relative L2 norm would dilute."""
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+# Bound of _maxrel beside a relative-L2 tolerance.  Rounding spreads over
+# the beam, so the pointwise maximum sits 2.5-10x above the relative L2
+# (measured: 2.6-10 in FP32, 5.7 in FP64 on the 1024^2 batch beam); an error
+# confined to a few points instead leaves the L2 norm near its floor while
+# its pointwise maximum exceeds this bound.
+MAX_OVER_L2 = 10.0
+
+
 def _report(name, **vals):
     print(name, " ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}"
                          for k, v in vals.items()), flush=True)
@@ -64,9 +78,10 @@ def test_config1_full_march(precision):
         pk_all += list(pk / ref.peak - 1)
         err = M.rel_l2(got, ref.field)
         ferr = M.rel_l2(np.abs(got) ** 2, np.abs(ref.field) ** 2)
-        _report(f"c1 fp{precision} step {stop}", field=err, fluence=ferr)
+        emax = _maxrel(got, ref.field)
+        _report(f"c1 fp{precision} step {stop}", field=err, fluence=ferr, field_max=emax)
         tf, tw = C1_TOL[precision][stop]
-        assert err < tf and ferr < tw
+        assert err < tf and ferr < tw and emax < MAX_OVER_L2 * tf
     perr = float(np.max(np.abs(pw_all)))
     _report(f"c1 fp{precision}", power=perr, peak=float(np.max(np.abs(pk_all))))
     assert perr < (1e-12 if precision == 64 else 1e-4)
@@ -96,12 +111,14 @@ def test_every_size_all_screen_terms(n, precision):
     p.propagate(inst.n_steps)
     got = p.field(0)
     err = M.rel_l2(got, ref.field)
+    emax = _maxrel(got, ref.field)
     pw, pk = p.diag(0, inst.n_steps)
     perr = float(np.max(np.abs(pw / ref.power - 1)))
-    _report(f"n={n} fp{precision}", field=err, power=perr,
+    _report(f"n={n} fp{precision}", field=err, field_max=emax, power=perr,
             peak_x=float(ref.peak.max() / W.I_A))
     tol = 1e-11 if precision == 64 else 2e-5
     assert err < tol
+    assert emax < MAX_OVER_L2 * tol
     assert perr < (1e-12 if precision == 64 else 2e-6)
 
 
@@ -365,9 +382,12 @@ def test_config3_batched_march_matches_oracle(c3_oracle, precision):
         p.set_field(b, W.initial_field(inst))
     p.propagate(100)
     for b, tol in C3_BEAMS.items():
-        err = M.rel_l2(p.field(b), ref[b][0])
-        _report(f"c3 beam {b} n={insts[b].n} fp{precision}", field=err)
-        assert err < (tol[0] if precision == 32 else tol[1]), (b, err)
+        got = p.field(b)
+        err = M.rel_l2(got, ref[b][0])
+        emax = _maxrel(got, ref[b][0])
+        _report(f"c3 beam {b} n={insts[b].n} fp{precision}", field=err, field_max=emax)
+        t = tol[0] if precision == 32 else tol[1]
+        assert err < t and emax < MAX_OVER_L2 * t, (b, err, emax)
 
 
 def test_config3_batch_equals_each_beam_alone():
@@ -435,6 +455,45 @@ def test_config4_gradient_matches_oracle(c4_oracle, precision, steps):
     tol = C4_TOL.get((precision, steps))
     if tol is not None:
         assert lerr < tol[0] and ferr < tol[1] and terr < tol[2]
+
+
+# R20 for config 4 in complex64: the input floor in32 (two FP64 marches
+# whose inputs differ by 2^-24) is 7.0e-8, 2.9e-5, 4.6e-3, 3.8e-2, 7.6e-2
+# at steps 100..500, so the largest sampled z with delta_32 <= 1e-3 is step
+# 200 (1.2 m of 3 m).  Field and fluence parity are stated there, at 5x the
+# largest FP32 floor of that step (peer32 6.1e-3 field / 6.7e-3 fluence;
+# step32 1.1e-3 / 1.2e-3), and at step 100 (peer32 4.1e-5 / 9.5e-5).  At
+# the full 500 steps the FP32 march is past the chaotic divergence (every
+# FP32 floor is O(1)): no parity is claimed there; the power of both
+# marches is reported (theta0's imaginary part is a gain at small x, so
+# the power is not monotone) and the FP32 march must stay finite.
+C4_FWD32_TOL = {100: (2.1e-4, 4.8e-4), 200: (3.1e-2, 3.4e-2)}
+
+
+def test_config4_fp32_forward_at_the_r20_horizon():
+    inst, u0, _ = _c4()
+    p = _prop([inst], 32)
+    p.set_field(0, u0)
+    p.set_theta(0, inst.theta)
+    u, done = u0, 0
+    for stop, (tf, tw) in sorted(C4_FWD32_TOL.items()):
+        ref = M.march(u, inst, n_steps=stop - done)
+        u, done = ref.field, stop
+        p.propagate(ref.power.size)
+        got = p.field(0)
+        err = M.rel_l2(got, ref.field)
+        ferr = M.rel_l2(np.abs(got) ** 2, np.abs(ref.field) ** 2)
+        _report(f"c4 fp32 forward step {stop}", field=err, fluence=ferr,
+                field_max=_maxrel(got, ref.field))
+        assert err < tf and ferr < tw
+    ref = M.march(u, inst, n_steps=inst.n_steps - done)
+    p.propagate(inst.n_steps - done)
+    pw, _ = p.diag(0, inst.n_steps - done)
+    perr = float(np.max(np.abs(pw / ref.power - 1)))
+    _report("c4 fp32 forward step 500 (past the R20 horizon)", power=perr,
+            power_oracle=float(ref.power[-1] / ref.power[0]),
+            power_fp32=float(pw[-1] / pw[0]))
+    assert np.all(np.isfinite(pw)) and np.all(np.isfinite(p.field(0)))
 
 
 def test_config4_gradient_matches_finite_differences():
@@ -570,21 +629,23 @@ def test_config2_full_size_against_oracle_samples(precision):
         want = np.array(ref["field_re"][str(m)]) + 1j * np.array(ref["field_im"][str(m)])
         got = u[pts[:, 0], pts[:, 1]]
         err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+        emax = _maxrel(got, want)
         if str(m) in ref["block_fluence"]:
             bf = np.array(ref["block_fluence"][str(m)])
             gb = M.block_mean(np.abs(u) ** 2, inst.n // bf.shape[0])
             berr = float(np.linalg.norm(gb - bf) / np.linalg.norm(bf))
-            _report(f"c2 fp{precision} step {m}", samples=err, block_fluence=berr)
+            _report(f"c2 fp{precision} step {m}", samples=err, samples_max=emax,
+                    block_fluence=berr)
             if precision == 32:
                 assert berr < 5 * d["peer32"]["block_fluence"][k], (m, berr)
             else:
                 assert berr < 10 * d["peer64"]["block_fluence"][k], (m, berr)
         if precision == 64:
             floor = max(d["step64"]["field"][k], d["in64"]["field"][k], d["peer64"]["field"][k])
-            assert err < 10 * floor, (m, err, floor)
+            assert err < 10 * floor and emax < MAX_OVER_L2 * 10 * floor, (m, err, emax, floor)
         elif m <= 1100:
             floor = max(d["peer32"]["field"][k], d["step32"]["field"][k])
-            assert err < 5 * floor, (m, err, floor)
+            assert err < 5 * floor and emax < MAX_OVER_L2 * 5 * floor, (m, err, emax, floor)
     perr = np.abs(np.array(power) / np.array(ref["power"]) - 1)
     kerr = np.abs(np.array(peak) / np.array(ref["peak"]) - 1)
     _report(f"c2 fp{precision} diag", power_max=float(perr.max()), power_end=float(perr[-1]),
@@ -625,9 +686,11 @@ def test_config5_prefix_matches_oracle(c5_oracle, precision):
     p = _prop([inst], precision)
     p.set_field(0, u0)
     p.propagate(10)
-    err = M.rel_l2(p.field(0), ref)
-    _report(f"c5 10 steps fp{precision}", field=err)
-    assert err < C5_TOL[precision]
+    got = p.field(0)
+    err = M.rel_l2(got, ref)
+    emax = _maxrel(got, ref)
+    _report(f"c5 10 steps fp{precision}", field=err, field_max=emax)
+    assert err < C5_TOL[precision] and emax < MAX_OVER_L2 * C5_TOL[precision]
 
 
 def test_config5_first_screens_match_oracle():
