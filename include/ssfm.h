@@ -375,6 +375,19 @@ int ssfm_lens_vjp(ssfm_ctx* ctx, int32_t inst, const ssfm_lens* lens, const void
 int ssfm_hot_areas(ssfm_ctx* ctx, const double* w, int32_t n, double threshold,
                    int32_t periodic, int64_t* count);
 
+/* ssfm_hot_areas for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, e.g. tight serving loops or harnesses that forbid
+ * it) and have no context: the same count, with the labels, overflow flag
+ * and partial counts in a fixed device array inside the library (16 MiB +
+ * 4 KiB per GPU, held until the process ends) instead of a workspace.  w:
+ * n x n FP64 device array [W/m^2], row-major; n <= 2048 (larger grids:
+ * ssfm_hot_areas with a context), else SSFM_EINVAL; stream: hipStream_t or
+ * NULL.  Calls no hipMalloc or hipFree.  All calls on one GPU share that
+ * array: calls that overlap on one GPU (other threads or streams) race and
+ * must be serialised by the caller.  Synchronises stream; *count on the
+ * host.  SSFM_EHIP if the labelling's bounded union loop hit its cap. */
+int ssfm_hot_areas_static(const double* w, int32_t n, double threshold, int32_t periodic,
+                          void* stream, int64_t* count);
 
 /* Spatial moment of a fluence (Eq. (8) family, read as Q(p, m) = sum over
  * the cell-centred grid of w^p (x^2 + y^2)^m dx^2, dx = length / n,

@@ -93,6 +93,8 @@ _SIGS = {
                                         POINTER(c_double)]),
     "ssfm_hot_areas": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_int32,
                                  POINTER(c_int64)]),
+    "ssfm_hot_areas_static": (c_int32, [c_void_p, c_int32, c_double, c_int32, c_void_p,
+                                        POINTER(c_int64)]),
     "ssfm_moment": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_double, c_int32,
                               POINTER(c_double)]),
     "ssfm_set_pass_timing": (c_int32, [c_void_p, c_int32]),

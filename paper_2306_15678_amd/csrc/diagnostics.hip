@@ -16,10 +16,41 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.hpp"
 
+// Device scratch of the allocation-free hot-area count: labels of an n x n
+// grid with n <= kStaticMaxN, the overflow flag and the per-block partial
+// counts.  One copy per GPU, held until the process ends; host code never
+// uses this name as an address (it stands for a host-side shadow): the
+// device address comes from hipGetSymbolAddress in static_scratch().
+static __device__ __align__(256) unsigned char scratch[ssfm::kStaticScratchBytes];
+
 namespace ssfm {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev] == nullptr) {
+    // with device dev current: that device's copy of the array
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
 
 namespace {
 

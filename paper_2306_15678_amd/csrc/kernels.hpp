@@ -166,5 +166,15 @@ hipError_t launch_moment(const double* w, int n, double dx, double p, int m, dou
 hipError_t launch_block_mean(const double* src, int n, int b, double* dst,
                              hipStream_t s);
 
+// Allocation-free hot-area count: a file-scope device array (one per GPU)
+// holds the labels of grids up to kStaticMaxN^2, the overflow flag at
+// kStaticOverflowOff and kStaticParts partial counts at kStaticPartOff.
+constexpr int kStaticMaxN = 2048;
+constexpr int kStaticParts = 256;
+constexpr size_t kStaticOverflowOff = size_t(kStaticMaxN) * kStaticMaxN * sizeof(int);
+constexpr size_t kStaticPartOff = kStaticOverflowOff + 256;
+constexpr size_t kStaticScratchBytes = kStaticPartOff + kStaticParts * sizeof(double);
+// Device address of the current device's copy (looked up once per device).
+hipError_t static_scratch(void** out);
 
 }  // namespace ssfm

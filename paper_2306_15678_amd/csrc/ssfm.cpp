@@ -1984,6 +1984,36 @@ int ssfm_hot_areas(ssfm_ctx* c, const double* w, int32_t n, double threshold, in
   return SSFM_OK;
 }
 
+int ssfm_hot_areas_static(const double* w, int32_t n, double threshold, int32_t periodic,
+                          void* stream, int64_t* count) {
+  g_last_error.clear();
+  if (!w || !count) return fail(SSFM_EINVAL, "w/count is NULL");
+  if (n < 1 || n > kStaticMaxN)
+    return fail(SSFM_EINVAL,
+                "n=%d outside [1, %d], the static scratch's largest grid (larger grids: "
+                "ssfm_hot_areas with a context)", n, kStaticMaxN);
+  if (!std::isfinite(threshold)) return fail(SSFM_EINVAL, "threshold must be finite");
+  void* base = nullptr;
+  HIP_TRY(static_scratch(&base));
+  char* sc = static_cast<char*>(base);
+  int* labels = reinterpret_cast<int*>(sc);
+  int* overflow = reinterpret_cast<int*>(sc + kStaticOverflowOff);
+  double* part = reinterpret_cast<double*>(sc + kStaticPartOff);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_hot_areas(w, n, threshold, periodic ? 1 : 0, labels, overflow, part,
+                           kStaticParts, st));
+  double host[kStaticParts];
+  int ovf = 0;
+  HIP_TRY(hipMemcpyAsync(host, part, sizeof(host), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&ovf, overflow, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (ovf) return fail(SSFM_EHIP, "hot-area labelling: a union exceeded its retry cap");
+  double total = 0.0;
+  for (int k = 0; k < kStaticParts; ++k) total += host[k];
+  *count = int64_t(total);
+  return SSFM_OK;
+}
+
 int ssfm_moment(ssfm_ctx* c, const double* w, int32_t n, double length, double p, int32_t m,
                 double* q) {
   if (int r = check_ctx(c)) return r;

@@ -292,6 +292,20 @@ class Propagator:
         return out
 
 
+def hot_areas_static(w: torch.Tensor, threshold: float, periodic: bool = True,
+                     stream: Optional[torch.cuda.Stream] = None) -> int:
+    """Hot-area count of an n x n float64 fluence on the current device
+    without a context or any device allocation (the library's fixed
+    scratch; n <= 2048), on ``stream`` (default: torch's current one)."""
+    w = w.to(dtype=torch.float64).contiguous()
+    st = stream or torch.cuda.current_stream(w.device)
+    out = ctypes.c_int64()
+    L.call("ssfm_hot_areas_static", ctypes.c_void_p(w.data_ptr()), w.shape[0],
+           float(threshold), 1 if periodic else 0, ctypes.c_void_p(st.cuda_stream),
+           ctypes.byref(out))
+    return out.value
+
+
 def make_lens(l_dif: float, w_l: float, c1: float, c2: float,
               re: Sequence[Sequence[float]] = (), im: Sequence[Sequence[float]] = ()
               ) -> L.LensParams:
