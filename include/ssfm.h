@@ -439,6 +439,18 @@ int ssfm_set_pass_timing(ssfm_ctx* ctx, int32_t every);
 int ssfm_pass_times(ssfm_ctx* ctx, double* ms_row, double* ms_col,
                     int32_t* n_samples);
 
+/* Sampled pass timing of the most recent ssfm_backward (with pass timing on,
+ * ssfm_set_pass_timing(every > 0), the backward runs without its captured
+ * graph; adjoint step s of its first checkpoint segment, the one that runs
+ * without a recompute beside it, with s % every == every / 2 is bracketed
+ * by HIP events on the context's stream).  Mean milliseconds of the adjoint
+ * column pass (reads and writes the cotangent) and of the adjoint row pass
+ * (reads the cotangent and the stored pre-screen field, writes the
+ * cotangent; the adjoint screen fused); synchronises; *n_samples = 0 and
+ * zero times when none were taken. */
+int ssfm_adjoint_pass_times(ssfm_ctx* ctx, double* ms_col, double* ms_row,
+                            int32_t* n_samples);
+
 /* Wait for all work of the context's stream. */
 int ssfm_synchronize(ssfm_ctx* ctx);
 

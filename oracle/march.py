@@ -24,11 +24,31 @@ Screen terms (all functions of I = |V|^2 in W/m^2, x = I / I_a):
 """
 from __future__ import annotations
 
+import contextlib
 import dataclasses
 import math
 from typing import Callable, Dict, List, Optional, Sequence
 
 import numpy as np
+
+# The 2-D transforms the march uses (numpy's, single-threaded).  fft_workers
+# swaps in scipy.fft with a thread count for timing the CPU baseline only:
+# the same transform, the march unchanged.
+_FFT = {"fft2": np.fft.fft2, "ifft2": np.fft.ifft2}
+
+
+@contextlib.contextmanager
+def fft_workers(workers: int):
+    """Run the oracle's 2-D FFTs through scipy.fft with `workers` threads."""
+    import scipy.fft as sf
+    saved = dict(_FFT)
+    _FFT["fft2"] = lambda a: sf.fft2(a, workers=workers)
+    _FFT["ifft2"] = lambda a: sf.ifft2(a, workers=workers)
+    try:
+        yield
+    finally:
+        _FFT.update(saved)
+
 
 KERR, MPA, PLASMA, ANSATZ, TURB = 1, 2, 4, 8, 16
 
@@ -52,12 +72,12 @@ def propagator(n: int, length: float, dz: float, k0: float) -> np.ndarray:
 
 def diffract(u: np.ndarray, prop: np.ndarray) -> np.ndarray:
     """One exact diffraction step: F^-1 [P . F u]."""
-    return np.fft.ifft2(prop * np.fft.fft2(u))
+    return _FFT["ifft2"](prop * _FFT["fft2"](u))
 
 
 def diffract_adjoint(lam: np.ndarray, prop: np.ndarray) -> np.ndarray:
     """Hermitian adjoint of ``diffract``: F^-1 [conj(P) . F lam]."""
-    return np.fft.ifft2(np.conj(prop) * np.fft.fft2(lam))
+    return _FFT["ifft2"](np.conj(prop) * _FFT["fft2"](lam))
 
 
 # ------------------------------------------------------------------ screen

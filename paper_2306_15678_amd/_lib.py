@@ -100,6 +100,8 @@ _SIGS = {
     "ssfm_set_pass_timing": (c_int32, [c_void_p, c_int32]),
     "ssfm_pass_times": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double),
                                   POINTER(c_int32)]),
+    "ssfm_adjoint_pass_times": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double),
+                                          POINTER(c_int32)]),
     "ssfm_synchronize": (c_int32, [c_void_p]),
 }
 

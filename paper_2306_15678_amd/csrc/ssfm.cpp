@@ -167,6 +167,11 @@ struct ssfm_ctx {
   };
   int32_t timing_every = 0;
   std::vector<PassSample> samples, free_samples;
+  // samples of the most recent backward: adjoint steps s of its first
+  // segment (which runs alone, not beside a recompute) with
+  // s % timing_every == timing_every / 2; pass 0 the column pass, 1 the row
+  // pass
+  std::vector<PassSample> adj_samples;
   // second stream (default priority) and events for the overlapped backward
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -192,6 +197,7 @@ struct ssfm_ctx {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     destroy(samples);
     destroy(free_samples);
+    destroy(adj_samples);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (aux) (void)hipStreamDestroy(aux);
@@ -584,19 +590,22 @@ int fwd_step(ssfm_ctx* c, const void* src, void* dst, int64_t pending_step, doub
 
 // One adjoint step: Lam -> Wk (columns) -> Lam (rows + adjoint screen with
 // the pre-screen field `sv` of the screen applied after step pending_step).
+// ts: timing events around the two passes (sampled steps only).
 template <typename R>
-int adj_step(ssfm_ctx* c, const void* sv, int64_t pending_step) {
+int adj_step(ssfm_ctx* c, const void* sv, int64_t pending_step,
+             const ssfm_ctx::PassSample* ts = nullptr) {
+  const size_t ng = c->groups.size();
   PassArgs<R> a = base_args<R>(c);
   a.src = c->field(c->L.Lam);
   a.dst = c->field(c->L.Wk);
-  if (int r = run_pass<R>(c, COL_ADJ, a)) return r;
+  if (int r = run_pass<R>(c, COL_ADJ, a, nullptr, ts ? ts->ev.data() : nullptr)) return r;
   PassArgs<R> b = base_args<R>(c);
   b.src = c->field(c->L.Wk);
   b.dst = c->field(c->L.Lam);
   b.aux = sv;
   b.step = pending_step;
   b.part = c->at<double>(c->L.theta_acc);
-  return run_pass<R>(c, ROW_ADJ, b);
+  return run_pass<R>(c, ROW_ADJ, b, nullptr, ts ? ts->ev.data() + 2 * ng : nullptr);
 }
 
 template <typename R>
@@ -934,10 +943,14 @@ int enqueue_backward(ssfm_ctx* c) {
     }
     const int64_t s0 = k * M;
     const int64_t len = std::min<int64_t>(M, n - s0);
+    const int64_t every = c->timing_every;
     for (int64_t i = len - 1; i >= 0; --i) {
       const int64_t g = s0 + i;
       const int64_t pend = rec_pending(c, step0, step0 + g);
-      if (int r = adj_step<R>(c, sv(k, i), pend)) return r;
+      ssfm_ctx::PassSample ps;
+      const bool sample = every > 0 && k == 0 && g % every == every / 2 && take_sample(c, &ps);
+      if (int r = adj_step<R>(c, sv(k, i), pend, sample ? &ps : nullptr)) return r;
+      if (sample) c->adj_samples.push_back(std::move(ps));
     }
     if (overlap) HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join, 0));
   }
@@ -953,6 +966,8 @@ template <typename R>
 int do_backward(ssfm_ctx* c) {
   if (!c->rec_valid) return fail(SSFM_ESTATE, "backward needs a preceding ssfm_forward_record");
   if (!c->seeded) return fail(SSFM_ESTATE, "backward needs a cotangent (set_cotangent/fluence_loss)");
+  for (auto& e : c->adj_samples) c->free_samples.push_back(std::move(e));
+  c->adj_samples.clear();
   // a beam without a cotangent contributes nothing to the loss: its
   // cotangent and its seed-step theta partials are zero (else the adjoint
   // would march whatever an earlier backward left there)
@@ -965,8 +980,11 @@ int do_backward(ssfm_ctx* c) {
     HIP_TRY(launch_fill_f64(c->at<double>(c->L.seed_theta) + size_t(b) * 8 * c->L.max_n,
                             8 * int64_t(c->inst[b].n), 0.0, c->stream));
   }
-  int r = maybe_graph(c, 2, c->rec_step0, c->rec_steps, 0, 0,
-                      [&] { return enqueue_backward<R>(c); });
+  // sampled timing launches the backward directly (its sampled passes
+  // carry events on their own dispatches)
+  int r = c->timing_every > 0 ? enqueue_backward<R>(c)
+                              : maybe_graph(c, 2, c->rec_step0, c->rec_steps, 0, 0,
+                                            [&] { return enqueue_backward<R>(c); });
   if (r) return r;
   c->grads_valid = true;
   return SSFM_OK;
@@ -2045,38 +2063,48 @@ int ssfm_set_pass_timing(ssfm_ctx* c, int32_t every) {
   return SSFM_OK;
 }
 
-int ssfm_pass_times(ssfm_ctx* c, double* ms_row, double* ms_col, int32_t* n_samples) {
-  if (int r = check_ctx(c)) return r;
-  double tr = 0.0, tc = 0.0;
+namespace {
+// Mean span of pass 0 and pass 1 over samples: for each sample the earliest
+// start to the latest stop over its size groups (group 0 launches first;
+// the others run concurrently).
+int mean_spans(ssfm_ctx* c, const std::vector<ssfm_ctx::PassSample>& samples, double* t0,
+               double* t1, int32_t* count) {
+  double acc[2] = {0.0, 0.0};
   int32_t n = 0;
-  if (!c->samples.empty()) {
+  if (!samples.empty()) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     const size_t ng = c->groups.size();
-    for (const auto& e : c->samples) {
-      // span of each pass: earliest start to latest stop over its size
-      // groups (group 0 launches first; the others run concurrently)
-      double span[2];
+    for (const auto& e : samples) {
       for (int p = 0; p < 2; ++p) {
         const hipEvent_t ref = e.ev[2 * (p * ng)];
         double lo = 0.0, hi = 0.0;
         for (size_t g = 0; g < ng; ++g) {
-          float t0 = 0.f, t1 = 0.f;
-          HIP_TRY(hipEventElapsedTime(&t0, ref, e.ev[2 * (p * ng + g)]));
-          HIP_TRY(hipEventElapsedTime(&t1, ref, e.ev[2 * (p * ng + g) + 1]));
-          lo = std::min(lo, double(t0));
-          hi = std::max(hi, double(t1));
+          float a = 0.f, b = 0.f;
+          HIP_TRY(hipEventElapsedTime(&a, ref, e.ev[2 * (p * ng + g)]));
+          HIP_TRY(hipEventElapsedTime(&b, ref, e.ev[2 * (p * ng + g) + 1]));
+          lo = std::min(lo, double(a));
+          hi = std::max(hi, double(b));
         }
-        span[p] = hi - lo;
+        acc[p] += hi - lo;
       }
-      tr += span[0];
-      tc += span[1];
       ++n;
     }
   }
-  if (ms_row) *ms_row = n ? tr / n : 0.0;
-  if (ms_col) *ms_col = n ? tc / n : 0.0;
-  if (n_samples) *n_samples = n;
+  if (t0) *t0 = n ? acc[0] / n : 0.0;
+  if (t1) *t1 = n ? acc[1] / n : 0.0;
+  if (count) *count = n;
   return SSFM_OK;
+}
+}  // namespace
+
+int ssfm_pass_times(ssfm_ctx* c, double* ms_row, double* ms_col, int32_t* n_samples) {
+  if (int r = check_ctx(c)) return r;
+  return mean_spans(c, c->samples, ms_row, ms_col, n_samples);
+}
+
+int ssfm_adjoint_pass_times(ssfm_ctx* c, double* ms_col, double* ms_row, int32_t* n_samples) {
+  if (int r = check_ctx(c)) return r;
+  return mean_spans(c, c->adj_samples, ms_col, ms_row, n_samples);
 }
 
 int ssfm_synchronize(ssfm_ctx* c) {

@@ -283,6 +283,14 @@ class Propagator:
         L.call("ssfm_pass_times", self.ctx, ctypes.byref(r), ctypes.byref(c), ctypes.byref(n))
         return r.value, c.value, n.value
 
+    def adjoint_pass_times(self):
+        """(ms_col, ms_row, n_samples) of the adjoint passes sampled in the
+        most recent backward (pass timing on)."""
+        c, r, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        L.call("ssfm_adjoint_pass_times", self.ctx, ctypes.byref(c), ctypes.byref(r),
+               ctypes.byref(n))
+        return c.value, r.value, n.value
+
     def block_mean(self, src: torch.Tensor, b: int) -> torch.Tensor:
         n = src.shape[0]
         src = src.contiguous()

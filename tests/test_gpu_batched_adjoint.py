@@ -173,3 +173,27 @@ def test_setting_one_beam_mid_march_keeps_the_others_schedule(precision, tol):
     _report(f"mid-march set_field fp{precision}", beam0=ea, beam1=eb)
     assert ea < tol and eb < tol
     p.close()
+
+
+def test_adjoint_pass_timing_samples_without_changing_gradients(oracle_grads):
+    """With pass timing on, the backward runs without its graph and brackets
+    the sampled adjoint steps of its first segment with events: samples are
+    taken (steps 1 and 3 of segment 0 = steps 0..3 with every = 2), the
+    times are positive, and the gradients are bitwise those of the untimed
+    (graph-captured) backward."""
+    insts = _beams()
+    out = []
+    for every in (0, 2):
+        p = _prop(insts, 32, max_steps=STEPS, ckpt_every=4)
+        p.set_pass_timing(every)
+        _record_backward(p, insts, oracle_grads, range(len(insts)))
+        ms_col, ms_row, n = p.adjoint_pass_times()
+        if every:
+            _report("adjoint pass timing", ms_col=ms_col, ms_row=ms_row, samples=n)
+            assert n == 2 and ms_col > 0 and ms_row > 0
+        else:
+            assert n == 0
+        out.append([(p.grad_field(b), p.grad_theta(b)) for b in range(len(insts))])
+        p.close()
+    for (f0, t0), (f1, t1) in zip(*out):
+        assert np.array_equal(f0, f1) and np.array_equal(t0, t1)
