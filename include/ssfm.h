@@ -409,11 +409,34 @@ int ssfm_set_precise_math(ssfm_ctx* ctx, int32_t enable);
 int ssfm_use_graphs(ssfm_ctx* ctx, int32_t enable);
 
 /* Number of compiled FFT tile variants of the row pass and of the column
- * pass for grid size n (points per thread, lines per workgroup), and the
- * selection of the variants this context uses for that n (autotuner hook;
- * drops the context's captured graphs). */
+ * pass for grid size n (points per thread, lines per workgroup, twiddle
+ * loading, occupancy target), and the selection of the variants this
+ * context uses for that n (autotuner hook; drops the context's captured
+ * graphs).  A variant whose tile does not fit a workgroup's LDS at the
+ * context's precision (wide column tiles in FP64) is not built for it:
+ * ssfm_select_plan then returns SSFM_EUNSUPPORTED and keeps the current
+ * selection. */
 int ssfm_plan_variants(int32_t n, int32_t precision, int32_t* n_row, int32_t* n_col);
 int ssfm_select_plan(ssfm_ctx* ctx, int32_t n, int32_t row_variant, int32_t col_variant);
+
+/* Variants of the adjoint row and column passes for grid size n, chosen
+ * apart from the forward ones (their registers and best tiles differ); -1
+ * follows the forward variant (the default).  A variant must have the lines
+ * per workgroup of the forward variant in use (the work lists are shared),
+ * else SSFM_EINVAL; one not built at the context's precision returns
+ * SSFM_EUNSUPPORTED.  A later ssfm_select_plan whose lines differ resets the
+ * adjoint choice to -1.  Drops the context's captured graphs. */
+int ssfm_select_adjoint_plan(ssfm_ctx* ctx, int32_t n, int32_t row_variant,
+                             int32_t col_variant);
+
+/* Autotuner hook for the adjoint passes: reps launches of the adjoint
+ * column pass and of the adjoint row pass over all instances (with their
+ * selected variants), timed with HIP events on the context's stream; mean
+ * milliseconds per launch.  The passes read the cotangent buffer and the
+ * state and write the work buffer and the theta accumulators (which every
+ * backward clears first): fields, cotangents and gradients are unchanged.
+ * SSFM_ESTATE unless the context was created with max_steps > 0. */
+int ssfm_time_adjoint_passes(ssfm_ctx* ctx, int32_t reps, double* ms_col, double* ms_row);
 
 /* Time each pass kernel of one step in isolation with HIP events on the
  * context's stream: reps launches of the forward row pass and of the

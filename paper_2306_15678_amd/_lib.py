@@ -102,6 +102,9 @@ _SIGS = {
                                   POINTER(c_int32)]),
     "ssfm_adjoint_pass_times": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double),
                                           POINTER(c_int32)]),
+    "ssfm_select_adjoint_plan": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
+    "ssfm_time_adjoint_passes": (c_int32, [c_void_p, c_int32, POINTER(c_double),
+                                           POINTER(c_double)]),
     "ssfm_synchronize": (c_int32, [c_void_p]),
 }
 

@@ -269,8 +269,15 @@ template <int... Rs>
 struct Radices {};
 
 // N points per line, T threads per line, LINES lines per workgroup; column
-// tiles pad their LDS by B slots every A points (see LdsPointMajor).
-template <int N_, int T_, int LINES_, class Rad, int PA_ = 32, int PB_ = 0>
+// tiles pad their LDS by B slots every A points (see LdsPointMajor).  OPT:
+// bit 0 set loads each stage's twiddles just before that stage (fewer live
+// registers) instead of all of them before the first; bit 1 loads the
+// diffraction factors after the forward FFT instead of with the field (and,
+// in the adjoint row pass, the stored field and the screen phases after
+// the inverse FFT); bits 4-7 set the points per batch of the adjoint
+// screen (0: 4); bits 8-11 give the wavefronts per SIMD the compiler must
+// leave room for (0: no target).
+template <int N_, int T_, int LINES_, class Rad, int PA_ = 32, int PB_ = 0, int OPT_ = 0>
 struct Plan {
   static constexpr int N = N_;
   static constexpr int T = T_;
@@ -279,6 +286,10 @@ struct Plan {
   static constexpr int THREADS = T_ * LINES_;
   static constexpr int PA = PA_;
   static constexpr int PB = PB_;
+  static constexpr bool LATE_TW = (OPT_ & 1) != 0;
+  static constexpr bool LATE_PROP = (OPT_ & 2) != 0;
+  static constexpr int ADJ_BATCH = ((OPT_ >> 4) & 15) ? ((OPT_ >> 4) & 15) : 4;
+  static constexpr int WAVES_PER_EU = ((OPT_ >> 8) & 15) ? ((OPT_ >> 8) & 15) : 1;
   using radices = Rad;
   static_assert(N_ % T_ == 0, "T must divide N");
 };
@@ -320,9 +331,10 @@ constexpr int twiddle_count() {
 
 template <class P>
 struct TwCount;
-template <int N, int T, int L, int... Rs, int A, int B>
-struct TwCount<Plan<N, T, L, Radices<Rs...>, A, B>> {
-  static constexpr int value = twiddle_count<N, T, Rs...>();
+template <int N, int T, int L, int... Rs, int A, int B, int O>
+struct TwCount<Plan<N, T, L, Radices<Rs...>, A, B, O>> {
+  // late twiddles are loaded stage by stage: nothing held up front
+  static constexpr int value = (O & 1) ? 0 : twiddle_count<N, T, Rs...>();
 };
 
 template <typename R, int N, int T, int NS, int RAD>
@@ -358,18 +370,24 @@ __device__ __forceinline__ void load_twiddles_impl(cx<R>* w, int t,
 
 template <typename R, class P>
 __device__ __forceinline__ void load_twiddles(cx<R>* w, int t, const cx<R>* __restrict__ tw) {
-  load_twiddles_impl<R, P::N, P::T>(w, t, tw, typename P::radices{});
+  if constexpr (!P::LATE_TW) load_twiddles_impl<R, P::N, P::T>(w, t, tw, typename P::radices{});
 }
 
 // ---------------------------------------------------------- one stage
+// w: this stage's twiddles in registers (preloaded), or, with LATE, loaded
+// here from the table before the stage's LDS reads so that their latency
+// overlaps the exchange.
 template <typename R, int N, int T, int RAD, int NS, int DIR, bool FIRST,
-          bool LAST, class Lds>
+          bool LAST, bool LATE, class Lds>
 __device__ __forceinline__ void fft_stage(cx<R>* v, int t, const Lds& lds,
-                                          const cx<R>* w) {
+                                          const cx<R>* wpre, const cx<R>* __restrict__ tw) {
   constexpr int E = N / T;
   constexpr int NB = E / RAD;
   constexpr int STRIDE = N / RAD;
   static_assert(E % RAD == 0, "radix must divide points per thread");
+  cx<R> wl[(LATE && NS > 1) ? NB * (RAD - 1) : 1];
+  if constexpr (LATE && NS > 1) load_stage_twiddles<R, N, T, NS, RAD>(wl, t, tw);
+  const cx<R>* w = LATE ? wl : wpre;
   cx<R> a[NB][RAD];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -411,30 +429,33 @@ __device__ __forceinline__ void fft_stage(cx<R>* v, int t, const Lds& lds,
   }
 }
 
-template <typename R, int N, int T, int DIR, int NS, bool FIRST, class Lds,
+template <typename R, int N, int T, int DIR, int NS, bool FIRST, bool LATE, class Lds,
           int R0, int... Rest>
 __device__ __forceinline__ void fft_stages(cx<R>* v, int t, const Lds& lds,
-                                           const cx<R>* w) {
+                                           const cx<R>* w, const cx<R>* __restrict__ tw) {
   constexpr bool LAST = sizeof...(Rest) == 0;
-  fft_stage<R, N, T, R0, NS, DIR, FIRST, LAST>(v, t, lds, w);
+  fft_stage<R, N, T, R0, NS, DIR, FIRST, LAST, LATE>(v, t, lds, w, tw);
   if constexpr (!LAST) {
-    constexpr int used = (NS > 1) ? (N / T / R0) * (R0 - 1) : 0;
-    fft_stages<R, N, T, DIR, NS * R0, false, Lds, Rest...>(v, t, lds, w + used);
+    constexpr int used = (!LATE && NS > 1) ? (N / T / R0) * (R0 - 1) : 0;
+    fft_stages<R, N, T, DIR, NS * R0, false, LATE, Lds, Rest...>(v, t, lds, w + used, tw);
   }
 }
 
-template <typename R, int N, int T, int DIR, class Lds, int... Rs>
+template <typename R, int N, int T, int DIR, bool LATE, class Lds, int... Rs>
 __device__ __forceinline__ void fft_line_impl(cx<R>* v, int t, const Lds& lds,
-                                              const cx<R>* w, Radices<Rs...>) {
-  fft_stages<R, N, T, DIR, 1, true, Lds, Rs...>(v, t, lds, w);
+                                              const cx<R>* w, const cx<R>* __restrict__ tw,
+                                              Radices<Rs...>) {
+  fft_stages<R, N, T, DIR, 1, true, LATE, Lds, Rs...>(v, t, lds, w, tw);
 }
 
 // In-register FFT of one line (DIR = -1 forward, +1 inverse, unscaled),
-// with the thread's twiddles preloaded by load_twiddles<R, P>.  On entry and
+// with the thread's twiddles preloaded by load_twiddles<R, P> (w), or, for
+// a late-twiddle plan, read stage by stage from the table tw.  On entry and
 // exit v[e] holds point t + T*e.
 template <typename R, class P, int DIR, class Lds>
-__device__ __forceinline__ void fft_line(cx<R>* v, int t, const Lds& lds, const cx<R>* w) {
-  fft_line_impl<R, P::N, P::T, DIR>(v, t, lds, w, typename P::radices{});
+__device__ __forceinline__ void fft_line(cx<R>* v, int t, const Lds& lds, const cx<R>* w,
+                                         const cx<R>* __restrict__ tw) {
+  fft_line_impl<R, P::N, P::T, DIR, P::LATE_TW>(v, t, lds, w, tw, typename P::radices{});
 }
 
 }  // namespace ssfm

@@ -28,21 +28,22 @@ int plan_count(bool column, int n) {
   return c;
 }
 
+// false when the plan's tile does not fit a workgroup's LDS at this
+// precision (the plan is then not built for it)
 template <class P, bool COLUMN>
-static void fill_info(bool fp64, PlanInfo* o) {
-  const size_t el = fp64 ? 16 : 8;
+static bool fill_info(bool fp64, PlanInfo* o) {
   o->threads = P::THREADS;
   o->lines = P::LINES;
   o->t = P::T;
-  o->lds = COLUMN ? el * LdsPointMajor<float, P::LINES, P::PA, P::PB>::size(P::N)
-                  : el * P::LINES * LdsLineMajor<float, P::N>::LINE;
+  o->lds = fp64 ? plan_lds_bytes<double, P>(COLUMN) : plan_lds_bytes<float, P>(COLUMN);
+  return o->lds <= kMaxLdsBytes;
 }
 
 bool plan_info(bool column, int n, int v, bool fp64, PlanInfo* o) {
 #define SSFM_RINFO(NN, VV, ...) \
-  if (!column && n == NN && v == VV) { fill_info<RowPlanSel<NN, VV>::P, false>(fp64, o); return true; }
+  if (!column && n == NN && v == VV) return fill_info<RowPlanSel<NN, VV>::P, false>(fp64, o);
 #define SSFM_CINFO(NN, VV, ...) \
-  if (column && n == NN && v == VV) { fill_info<ColPlanSel<NN, VV>::P, true>(fp64, o); return true; }
+  if (column && n == NN && v == VV) return fill_info<ColPlanSel<NN, VV>::P, true>(fp64, o);
   SSFM_ROW_PLANS(SSFM_RINFO)
   SSFM_COL_PLANS(SSFM_CINFO)
 #undef SSFM_RINFO

@@ -120,7 +120,8 @@ constexpr int tw_regs() {
 
 // ------------------------------------------------------------ row pass
 template <typename R, class P, int KIND>
-__global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
+__global__ void __launch_bounds__(P::THREADS)
+    __attribute__((amdgpu_waves_per_eu(P::WAVES_PER_EU))) k_row(PassArgs<R> a) {
   constexpr int N = P::N, T = P::T, E = P::E;
   using L = LdsLineMajor<R, N>;
   __shared__ cx<R> lds_mem[P::LINES * L::LINE];
@@ -154,7 +155,7 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
   cx<R> wt[tw_regs<P>()];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = src[toff + uint32_t(T * e)];
-  if constexpr (KIND != ROW_INV && KIND != ROW_FD) {
+  if constexpr (KIND != ROW_INV && KIND != ROW_FD && !P::LATE_PROP) {
 #pragma unroll
     for (int e = 0; e < E; ++e) pr[e] = prop[t + T * e];
   }
@@ -162,24 +163,32 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
   cx<R> sv[KIND == ROW_ADJ ? E : 1];
   R ph[(KIND == ROW_ADJ || KIND == ROW_FWD) ? E : 1];
   const R* plane = nullptr;
-  if constexpr (KIND == ROW_ADJ || KIND == ROW_FWD) {
+  if constexpr (KIND == ROW_ADJ || KIND == ROW_FWD)
     plane = find_plane(a.screens, a.screen_steps, in, a.step);
+  // turbulence phases (forward and adjoint) and the stored pre-screen field
+  // (adjoint) of points [e0, e1), needed by the screen on load (forward) or
+  // by the adjoint screen after the inverse FFT (adjoint; with late loads
+  // it reads them there, chunk by chunk, so they are not held through the
+  // transforms)
+  auto load_screen_inputs = [&](int e0, int e1) {
     if (plane) {
       const R* pw = plane + int64_t(w.line0) * N;
 #pragma unroll
-      for (int e = 0; e < E; ++e) ph[e] = pw[toff + uint32_t(T * e)];
+      for (int e = e0; e < e1; ++e) ph[e] = pw[toff + uint32_t(T * e)];
     } else {
 #pragma unroll
-      for (int e = 0; e < E; ++e) ph[e] = R(0);
+      for (int e = e0; e < e1; ++e) ph[e] = R(0);
     }
-  }
-  if constexpr (KIND == ROW_ADJ) {
-    if (a.step >= 0) {
-      const cx<R>* __restrict__ svp = static_cast<const cx<R>*>(a.aux) + wbase;
+    if constexpr (KIND == ROW_ADJ) {
+      if (a.step >= 0) {
+        const cx<R>* __restrict__ svp = static_cast<const cx<R>*>(a.aux) + wbase;
 #pragma unroll
-      for (int e = 0; e < E; ++e) sv[e] = svp[toff + uint32_t(T * e)];
+        for (int e = e0; e < e1; ++e) sv[e] = svp[toff + uint32_t(T * e)];
+      }
     }
-  }
+  };
+  constexpr bool kLateScreenInputs = (KIND == ROW_ADJ) && P::LATE_PROP;
+  if constexpr ((KIND == ROW_ADJ || KIND == ROW_FWD) && !kLateScreenInputs) load_screen_inputs(0, E);
   (void)row;
 
   if constexpr (KIND == ROW_FD) {
@@ -189,7 +198,7 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
     cx<R> un[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) un[e] = st[toff + uint32_t(T * e)];
-    if (a.flags & FD_SPECTRAL) fft_line<R, P, +1>(v, t, lds, wt);
+    if (a.flags & FD_SPECTRAL) fft_line<R, P, +1>(v, t, lds, wt, tw);
     if (a.flags & FD_FINISH) {
       // U+ = 2 Ubar - U, its power partials; it is the next step's U and
       // its first Ubar
@@ -225,7 +234,7 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
       gi *= R(0.5);
       v[e] = {un[e].re + (gr * v[e].re - gi * v[e].im), un[e].im + (gr * v[e].im + gi * v[e].re)};
     }
-    fft_line<R, P, -1>(v, t, lds, wt);
+    fft_line<R, P, -1>(v, t, lds, wt, tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) dst[toff + uint32_t(T * e)] = v[e];
     return;
@@ -236,21 +245,28 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
   }
 
   if constexpr (KIND == ROW_INV) {
-    fft_line<R, P, +1>(v, t, lds, wt);
+    fft_line<R, P, +1>(v, t, lds, wt, tw);
   } else {
-    fft_line<R, P, -1>(v, t, lds, wt);
+    fft_line<R, P, -1>(v, t, lds, wt, tw);
+    if constexpr (P::LATE_PROP) {
+      // loaded after the forward FFT: not held in registers through it
+#pragma unroll
+      for (int e = 0; e < E; ++e) pr[e] = prop[t + T * e];
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = (KIND == ROW_ADJ) ? cmulc(v[e], pr[e]) : cmul(v[e], pr[e]);
-    fft_line<R, P, +1>(v, t, lds, wt);
+    fft_line<R, P, +1>(v, t, lds, wt, tw);
   }
 
   if constexpr (KIND == ROW_ADJ) {
     if (a.step >= 0) {
       double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      constexpr int AC = (E % 4 == 0) ? 4 : E;  // points per adjoint batch
+      constexpr int AC = (E % P::ADJ_BATCH == 0) ? P::ADJ_BATCH : E;  // points per batch
 #pragma unroll
-      for (int c = 0; c < E; c += AC)
+      for (int c = 0; c < E; c += AC) {
+        if constexpr (kLateScreenInputs) load_screen_inputs(c, c + AC);
         screen_adjoint_n<R, AC>(sc, sv + c, v + c, ph + c, plane != nullptr, g);
+      }
       if (in.terms & T_ANSATZ) {
         block_reduce<8, P::THREADS, false>(g, red);
         if (threadIdx.x == 0) {
@@ -268,7 +284,8 @@ __global__ void __launch_bounds__(P::THREADS) k_row(PassArgs<R> a) {
 
 // --------------------------------------------------------- column pass
 template <typename R, class P, int KIND>
-__global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
+__global__ void __launch_bounds__(P::THREADS)
+    __attribute__((amdgpu_waves_per_eu(P::WAVES_PER_EU))) k_col(PassArgs<R> a) {
   constexpr int N = P::N, T = P::T, E = P::E, W = P::LINES;
   using L = LdsPointMajor<R, W, P::PA, P::PB>;
   __shared__ cx<R> lds_mem[L::size(N)];
@@ -298,16 +315,21 @@ __global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
   cx<R> wt[tw_regs<P>()];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = src[toff + ESTRIDE * e];
-  if constexpr (KIND != COL_INV) {
+  if constexpr (KIND != COL_INV && !P::LATE_PROP) {
 #pragma unroll
     for (int e = 0; e < E; ++e) pr[e] = prop[t + T * e];
   }
   load_twiddles<R, P>(wt, t, tw);
 
   if constexpr (KIND == COL_INV) {
-    fft_line<R, P, +1>(v, t, lds, wt);
+    fft_line<R, P, +1>(v, t, lds, wt, tw);
   } else {
-    fft_line<R, P, -1>(v, t, lds, wt);
+    fft_line<R, P, -1>(v, t, lds, wt, tw);
+    if constexpr (P::LATE_PROP) {
+      // loaded after the forward FFT: not held in registers through it
+#pragma unroll
+      for (int e = 0; e < E; ++e) pr[e] = prop[t + T * e];
+    }
     if constexpr (KIND == COL_FD) {
       // (1 - (i dz/4k0) Lap_h)^-1 = 1 / (1 + i (d[kx] + d[ky])) with the 1/N^2
       // of both inverse DFTs; the table holds d[m] = (dz/4k0)(4/dx^2)
@@ -325,7 +347,7 @@ __global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
       for (int e = 0; e < E; ++e)
         v[e] = (KIND == COL_ADJ) ? cmulc(v[e], pr[e]) : cmul(v[e], pr[e]);
     }
-    fft_line<R, P, +1>(v, t, lds, wt);
+    fft_line<R, P, +1>(v, t, lds, wt, tw);
   }
 
   if constexpr (KIND == COL_INV) {
@@ -376,10 +398,13 @@ __global__ void __launch_bounds__(P::THREADS) k_col(PassArgs<R> a) {
 
 // -------------------------------------------------------------- launch
 // With ev, the launch carries start/stop events on its own dispatch (timing
-// of the kernel alone, no separate marker packets).
+// of the kernel alone, no separate marker packets).  A plan whose LDS tile
+// does not fit a workgroup at this precision is not built for it.
 template <typename R, class P, int KIND>
 hipError_t launch_one(int n_blocks, const PassArgs<R>& a, hipStream_t s, const LaunchEv* ev) {
-  if constexpr (is_col_kind(KIND)) {
+  if constexpr (!plan_fits<R, P>(is_col_kind(KIND))) {
+    return hipErrorInvalidValue;
+  } else if constexpr (is_col_kind(KIND)) {
     if (ev)
       hipExtLaunchKernelGGL((k_col<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s,
                             ev->start, ev->stop, 0, a);

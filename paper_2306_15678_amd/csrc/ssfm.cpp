@@ -107,6 +107,9 @@ struct Layout {
 struct Group {
   int n;
   int row_var = 0, col_var = 0;
+  // variants of the adjoint passes (-1: the forward ones); same lines per
+  // workgroup as the forward variant, so the work lists are shared
+  int row_adj_var = -1, col_adj_var = -1;
   std::vector<int> beams;
   // launch order (XCD-aware), offsets into the work array
   int64_t row_work_off = 0, col_work_off = 0;
@@ -526,7 +529,8 @@ int run_pass(ssfm_ctx* c, int kind, PassArgs<R> a, hipStream_t st = nullptr,
     const Group& g = c->groups[gi];
     a.work = c->at<WorkItem>(c->L.work) + (col ? g.col_work_off : g.row_work_off);
     const int nb = col ? g.col_blocks : g.row_blocks;
-    const int v = col ? g.col_var : g.row_var;
+    const int v = col ? ((kind == COL_ADJ && g.col_adj_var >= 0) ? g.col_adj_var : g.col_var)
+                      : ((kind == ROW_ADJ && g.row_adj_var >= 0) ? g.row_adj_var : g.row_var);
     hipStream_t sg = (fork && gi > 0) ? c->gstream[gi - 1] : st;
     const LaunchEv le = ev ? LaunchEv{ev[2 * gi], ev[2 * gi + 1]} : LaunchEv{nullptr, nullptr};
     HIP_TRY(launch_pass<R>(kind, g.n, v, nb, a, sg, ev ? &le : nullptr));
@@ -1402,6 +1406,47 @@ int do_set_field(ssfm_ctx* c, int b, const void* src, int32_t where) {
   return upload_inst(c, b, b + 1);
 }
 
+// Lines per workgroup of a variant (0 if it does not exist).
+int plan_lines(bool column, int n, int v) {
+  PlanInfo pi{};
+  plan_info(column, n, v, false, &pi);
+  return pi.lines;
+}
+
+// Adjoint-pass variants of size n (-1: follow the forward variants).
+int do_select_adjoint(ssfm_ctx* c, int32_t n, int32_t rv, int32_t cv) {
+  const bool fp64 = c->precision == SSFM_FP64;
+  const int rc = plan_count(false, n), cc = plan_count(true, n);
+  if (rc == 0) return fail(SSFM_EUNSUPPORTED, "grid size %d not supported", n);
+  if (rv < -1 || rv >= rc || cv < -1 || cv >= cc)
+    return fail(SSFM_EINVAL, "variant (%d, %d) out of range [-1, %d) x [-1, %d)", rv, cv, rc, cc);
+  Group* grp = nullptr;
+  for (auto& g : c->groups)
+    if (g.n == n) grp = &g;
+  if (!grp) return fail(SSFM_EINVAL, "no instance with n=%d in this context", n);
+  PlanInfo pi{};
+  if (rv >= 0) {
+    if (!plan_info(false, n, rv, fp64, &pi))
+      return fail(SSFM_EUNSUPPORTED, "row variant %d of n=%d is not built at this precision", rv, n);
+    if (pi.lines != plan_lines(false, n, grp->row_var))
+      return fail(SSFM_EINVAL, "row variant %d has %d lines per workgroup, the forward one %d", rv,
+                  pi.lines, plan_lines(false, n, grp->row_var));
+  }
+  if (cv >= 0) {
+    if (!plan_info(true, n, cv, fp64, &pi))
+      return fail(SSFM_EUNSUPPORTED, "column variant %d of n=%d is not built at this precision",
+                  cv, n);
+    if (pi.lines != plan_lines(true, n, grp->col_var))
+      return fail(SSFM_EINVAL, "column variant %d has %d columns per workgroup, the forward one %d",
+                  cv, pi.lines, plan_lines(true, n, grp->col_var));
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  grp->row_adj_var = rv;
+  grp->col_adj_var = cv;
+  clear_graphs(c);
+  return SSFM_OK;
+}
+
 int do_select(ssfm_ctx* c, int32_t n, int32_t rv, int32_t cv) {
   const int rc = plan_count(false, n), cc = plan_count(true, n);
   if (rc == 0) return fail(SSFM_EUNSUPPORTED, "grid size %d not supported", n);
@@ -1425,6 +1470,19 @@ int do_select(ssfm_ctx* c, int32_t n, int32_t rv, int32_t cv) {
                           c->ckpt_every, &vm, &groups, &work, &wr, &wc, &L2))
     return r;
   if (L2.total != c->L.total) return fail(SSFM_EUNSUPPORTED, "variant changes the workspace layout");
+  // keep each size's adjoint variants while their lines per workgroup still
+  // match the forward ones
+  for (auto& g : groups) {
+    for (const auto& o : c->groups) {
+      if (o.n != g.n) continue;
+      g.row_adj_var = o.row_adj_var;
+      g.col_adj_var = o.col_adj_var;
+    }
+    if (g.row_adj_var >= 0 && plan_lines(false, g.n, g.row_adj_var) != plan_lines(false, g.n, g.row_var))
+      g.row_adj_var = -1;
+    if (g.col_adj_var >= 0 && plan_lines(true, g.n, g.col_adj_var) != plan_lines(true, g.n, g.col_var))
+      g.col_adj_var = -1;
+  }
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->groups = groups;
   c->work = work;
@@ -1856,6 +1914,59 @@ int ssfm_plan_variants(int32_t n, int32_t precision, int32_t* n_row, int32_t* n_
 int ssfm_select_plan(ssfm_ctx* c, int32_t n, int32_t row_variant, int32_t col_variant) {
   if (int r = check_ctx(c)) return r;
   return do_select(c, n, row_variant, col_variant);
+}
+
+int ssfm_select_adjoint_plan(ssfm_ctx* c, int32_t n, int32_t row_variant,
+                             int32_t col_variant) {
+  if (int r = check_ctx(c)) return r;
+  return do_select_adjoint(c, n, row_variant, col_variant);
+}
+
+int ssfm_time_adjoint_passes(ssfm_ctx* c, int32_t reps, double* ms_col, double* ms_row) {
+  if (int r = check_ctx(c)) return r;
+  if (reps < 1) return fail(SSFM_EINVAL, "reps must be >= 1");
+  if (c->max_steps <= 0)
+    return fail(SSFM_ESTATE, "adjoint passes need a context created with max_steps > 0");
+  struct Events {
+    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+    ~Events() {
+      for (auto x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  for (auto& x : ev.e) HIP_TRY(hipEventCreate(&x));
+  // column pass: cotangent -> work buffer; row pass: work buffer in place,
+  // the state standing in for the stored pre-screen field, at a step with
+  // no turbulence screen (its ansatz partials go to the accumulators every
+  // backward clears first).  Fields, cotangent and gradients are unchanged.
+  auto body = [&]<typename R>(R*) -> int {
+    PassArgs<R> a = base_args<R>(c);
+    a.src = c->field(c->L.Lam);
+    a.dst = c->field(c->L.Wk);
+    PassArgs<R> b = base_args<R>(c);
+    b.src = c->field(c->L.Wk);
+    b.dst = c->field(c->L.Wk);
+    b.aux = c->field(c->L.S);
+    b.step = int64_t(1) << 60;
+    b.part = c->at<double>(c->L.theta_acc);
+    HIP_TRY(hipEventRecord(ev.e[0], c->stream));
+    for (int i = 0; i < reps; ++i)
+      if (int q = run_pass<R>(c, COL_ADJ, a)) return q;
+    HIP_TRY(hipEventRecord(ev.e[1], c->stream));
+    for (int i = 0; i < reps; ++i)
+      if (int q = run_pass<R>(c, ROW_ADJ, b)) return q;
+    HIP_TRY(hipEventRecord(ev.e[2], c->stream));
+    return SSFM_OK;
+  };
+  int r = (c->precision == SSFM_FP64) ? body((double*)nullptr) : body((float*)nullptr);
+  if (r) return r;
+  HIP_TRY(hipEventSynchronize(ev.e[2]));
+  float t1 = 0, t2 = 0;
+  HIP_TRY(hipEventElapsedTime(&t1, ev.e[0], ev.e[1]));
+  HIP_TRY(hipEventElapsedTime(&t2, ev.e[1], ev.e[2]));
+  if (ms_col) *ms_col = double(t1) / reps;
+  if (ms_row) *ms_row = double(t2) / reps;
+  return SSFM_OK;
 }
 
 int ssfm_time_passes(ssfm_ctx* c, int32_t reps, double* ms_row, double* ms_col,

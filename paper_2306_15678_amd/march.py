@@ -73,6 +73,7 @@ class Propagator:
         arr = (L.InstanceDesc * self.n_inst)(*self.descs)
         self._arr = arr
         self.precision = precision
+        self.max_steps = int(max_steps)
         nbytes = ctypes.c_size_t()
         L.call("ssfm_workspace_bytes", arr, self.n_inst, precision, max_steps,
                ckpt_every, ctypes.byref(nbytes))
@@ -200,6 +201,17 @@ class Propagator:
 
     def select_plan(self, n: int, row_variant: int, col_variant: int) -> None:
         L.call("ssfm_select_plan", self.ctx, n, row_variant, col_variant)
+
+    def select_adjoint_plan(self, n: int, row_variant: int, col_variant: int) -> None:
+        """Variants of the adjoint passes for grid size n (-1: follow the
+        forward ones)."""
+        L.call("ssfm_select_adjoint_plan", self.ctx, n, row_variant, col_variant)
+
+    def time_adjoint_passes(self, reps: int = 20):
+        """(ms_col, ms_row) per launch of the adjoint column and row pass."""
+        c, r = ctypes.c_double(), ctypes.c_double()
+        L.call("ssfm_time_adjoint_passes", self.ctx, reps, ctypes.byref(c), ctypes.byref(r))
+        return c.value, r.value
 
     def time_passes(self, reps: int = 20):
         """(ms_row, ms_col, bytes_row, bytes_col) per launch of one pass."""

@@ -197,3 +197,31 @@ def test_adjoint_pass_timing_samples_without_changing_gradients(oracle_grads):
         p.close()
     for (f0, t0), (f1, t1) in zip(*out):
         assert np.array_equal(f0, f1) and np.array_equal(t0, t1)
+
+
+def test_adjoint_variants_chosen_apart_from_the_forward_ones(oracle_grads):
+    """Every adjoint row/column variant the library accepts for the 1024^2
+    beam's forward tiling gives the oracle's gradient (FP64); a variant with
+    other lines per workgroup is refused."""
+    from paper_2306_15678_amd._lib import EINVAL, EUNSUPPORTED
+    from paper_2306_15678_amd.march import plan_variants
+    inst = _beams()[0]
+    assert inst.n == 1024
+    u0, tgt, (loss, g_u0, g_th) = oracle_grads[0]
+    p = _prop([inst], 64, max_steps=STEPS, ckpt_every=3)
+    n_row, n_col = plan_variants(inst.n, 64)
+    tried = 0
+    for rv, cv in [(v, -1) for v in range(n_row)] + [(-1, v) for v in range(n_col)]:
+        try:
+            p.select_adjoint_plan(inst.n, rv, cv)
+        except SsfmError as e:
+            assert e.status in (EINVAL, EUNSUPPORTED)
+            continue
+        tried += 1
+        _record_backward(p, [inst], [oracle_grads[0]], [0])
+        ferr = M.rel_l2(p.grad_field(0), g_u0)
+        terr = float(np.max(np.abs(p.grad_theta(0) - g_th)) / np.max(np.abs(g_th)))
+        _report(f"adjoint variant row={rv} col={cv}", g_u0=ferr, g_theta=terr)
+        assert ferr < 1e-10 and terr < 1e-10, (rv, cv)
+    assert tried >= 3
+    p.close()
