@@ -398,6 +398,31 @@ int ssfm_hot_areas_static(const double* w, int32_t n, double threshold, int32_t 
 int ssfm_moment(ssfm_ctx* ctx, const double* w, int32_t n, double length, double p,
                 int32_t m, double* q);
 
+/* Measure vector P of a solution, for the genetic search's population
+ * fitness (Math and Equations, GA paragraph: P characterises the solution of
+ * a gene and is compared with the dense-grid solution's P0 by the Euclidean
+ * metric; Eq. (8) moments).  Of an n x n FP64 fluence w [W/m^2] in device
+ * memory on a window of side length [m]:
+ *   P = (Q(1,0), Q(1,1), Q(2,0), Q(2,1), max w, N_ha(w >= w_p))
+ * with Q(p, m) as in ssfm_moment (energy [W], its second moment [W m^2], the
+ * Eq. (8) m = 1 moment Q(2,1) and Q(2,0)), the peak [W/m^2] and the hot-area
+ * count of ssfm_hot_areas (periodic != 0: regions continue across the
+ * window edge).  FP64 partial sums in a fixed order; p: host double[6].
+ * n at most the context's largest grid (labels in its staging area).
+ * Synchronises. */
+#define SSFM_MEASURE_LEN 6
+int ssfm_measure_vector(ssfm_ctx* ctx, const double* w, int32_t n, double length, double w_p,
+                        int32_t periodic, double* p);
+
+/* Distance of instance inst's current fluence from a reference measure
+ * vector p0 (host double[6], e.g. ssfm_measure_vector of a dense-grid
+ * fluence): d = sqrt(sum_k ((P_k - P0_k) / s_k)^2), s_k = |P0_k| (1 where
+ * P0_k = 0), the Euclidean metric in relative units so that quantities of
+ * different units weigh alike.  Writes d and, if p is not NULL, P (host
+ * double[6]).  Uses the staging area; synchronises. */
+int ssfm_measure_distance(ssfm_ctx* ctx, int32_t inst, double w_p, int32_t periodic,
+                          const double* p0, double* d, double* p);
+
 /* FP32 screens evaluate sin/cos with the hardware v_sin/v_cos instructions
  * after an exact-to-rounding reduction to [-1/2, 1/2] revolutions (0,
  * default) or with the device math library's sincosf (1).  No effect on

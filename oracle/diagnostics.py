@@ -95,3 +95,30 @@ def moment(w: np.ndarray, length: float, p: float, m: int) -> float:
     n = w.shape[0]
     dx = length / n
     return float(np.sum(w.astype(np.float64) ** p * grid_r2(n, length) ** m) * dx * dx)
+
+
+# ------------------------------------------------------- measure vector
+# The GA's fitness (Math and Equations, GA paragraph): a vector P that
+# characterises a solution, compared with the dense-grid solution's P0 by
+# the Euclidean metric.  P is read here as the fluence's integral
+# quantities that the text names: its energy and the Eq. (8) spatial
+# moments (the printed m = 1 moment, w^2 r^2, and the usual energy moments),
+# its peak (the on-axis intensity the text monitors) and the hot-area count.
+MEASURE_NAMES = ("energy Q(1,0)", "Q(1,1)", "Q(2,0)", "Q(2,1)", "peak", "hot areas")
+
+
+def measure_vector(w: np.ndarray, length: float, w_p: float, periodic: bool = True) -> np.ndarray:
+    """P = (Q(1,0), Q(1,1), Q(2,0), Q(2,1), max w, N_ha(w >= w_p))."""
+    return np.array([moment(w, length, 1.0, 0), moment(w, length, 1.0, 1),
+                     moment(w, length, 2.0, 0), moment(w, length, 2.0, 1),
+                     float(np.max(w)), float(hot_area_count(w, w_p, periodic))])
+
+
+def measure_distance(p: np.ndarray, p0: np.ndarray) -> float:
+    """Euclidean distance of P from P0 in component-wise relative units:
+    sqrt(sum_k ((P_k - P0_k) / s_k)^2), s_k = |P0_k| (1 where P0_k = 0), so
+    that quantities of different units and sizes weigh alike."""
+    p = np.asarray(p, dtype=np.float64)
+    p0 = np.asarray(p0, dtype=np.float64)
+    s = np.where(p0 != 0.0, np.abs(p0), 1.0)
+    return float(np.sqrt(np.sum(((p - p0) / s) ** 2)))

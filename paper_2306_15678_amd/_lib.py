@@ -38,6 +38,7 @@ class SsfmError(RuntimeError):
 
 
 SPECTRUM_KOLMOGOROV, SPECTRUM_STEP = 0, 1
+MEASURE_LEN = 6
 LIE, STRANG, FD = 0, 1, 2
 
 
@@ -95,6 +96,10 @@ _SIGS = {
                                  POINTER(c_int64)]),
     "ssfm_hot_areas_static": (c_int32, [c_void_p, c_int32, c_double, c_int32, c_void_p,
                                         POINTER(c_int64)]),
+    "ssfm_measure_vector": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_double, c_int32,
+                                      POINTER(c_double)]),
+    "ssfm_measure_distance": (c_int32, [c_void_p, c_int32, c_double, c_int32, POINTER(c_double),
+                                        POINTER(c_double), POINTER(c_double)]),
     "ssfm_moment": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_double, c_int32,
                               POINTER(c_double)]),
     "ssfm_set_pass_timing": (c_int32, [c_void_p, c_int32]),

@@ -89,6 +89,27 @@ __device__ __forceinline__ void unite(int* lab, int a, int b, int* overflow) {
   *overflow = 1;
 }
 
+// Deterministic reduction of NV doubles over a 256-thread block (sum or
+// max); valid in thread 0.  red: shared [4][NV].
+template <int NV, int THREADS, bool MAX>
+__device__ __forceinline__ void block_reduce_diag(double (&v)[NV], double* red) {
+  for (int off = 32; off >= 1; off >>= 1)
+    for (int k = 0; k < NV; ++k) {
+      const double o = __shfl_xor(v[k], off, 64);
+      v[k] = MAX ? fmax(v[k], o) : v[k] + o;
+    }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NV; ++k) {
+      double t = red[k];
+      for (int q = 1; q < THREADS / 64; ++q) t = MAX ? fmax(t, red[q * NV + k]) : t + red[q * NV + k];
+      v[k] = t;
+    }
+}
+
 __global__ void k_set_i32(int* p, int v) {
   if (blockIdx.x == 0 && threadIdx.x == 0) p[0] = v;
 }
@@ -167,7 +188,41 @@ __global__ void __launch_bounds__(256) k_moment(const double* __restrict__ w, in
   if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// Per-block FP64 partials of the measure vector's sums over an n x n
+// fluence: [sum w, sum w r^2, sum w^2, sum w^2 r^2, max w] (grid-stride,
+// then a fixed tree per block).
+__global__ void __launch_bounds__(256) k_measure(const double* __restrict__ w, int n, double dx,
+                                                 double* part) {
+  __shared__ double red[4 * 5];
+  const int64_t n2 = int64_t(n) * n;
+  double s[4] = {0.0, 0.0, 0.0, 0.0}, mx[1] = {0.0};
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n2;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int y = int(i / n), x = int(i - int64_t(y) * n);
+    const double xc = (x + 0.5 - n / 2.0) * dx, yc = (y + 0.5 - n / 2.0) * dx;
+    const double r2 = xc * xc + yc * yc;
+    const double wi = w[i], w2 = wi * wi;
+    s[0] += wi;
+    s[1] += wi * r2;
+    s[2] += w2;
+    s[3] += w2 * r2;
+    mx[0] = fmax(mx[0], wi);
+  }
+  block_reduce_diag<4, 256, false>(s, red);
+  block_reduce_diag<1, 256, true>(mx, red + 16);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 4; ++k) part[5 * blockIdx.x + k] = s[k];
+    part[5 * blockIdx.x + 4] = mx[0];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_measure(const double* w, int n, double dx, double* part, int n_part,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_measure, dim3(n_part), dim3(256), 0, s, w, n, dx, part);
+  return hipGetLastError();
+}
 
 hipError_t launch_hot_areas(const double* w, int n, double threshold, int periodic, int* labels,
                             int* overflow, double* part, int n_part, hipStream_t s) {

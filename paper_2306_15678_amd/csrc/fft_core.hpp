@@ -276,7 +276,7 @@ struct Radices {};
 // in the adjoint row pass, the stored field and the screen phases after
 // the inverse FFT); bits 4-7 set the points per batch of the adjoint
 // screen (0: 4); bits 8-11 give the wavefronts per SIMD the compiler must
-// leave room for (0: no target).
+// leave room for in the complex64 kernels (0: no target).
 template <int N_, int T_, int LINES_, class Rad, int PA_ = 32, int PB_ = 0, int OPT_ = 0>
 struct Plan {
   static constexpr int N = N_;

@@ -162,6 +162,10 @@ hipError_t launch_hot_areas(const double* w, int n, double threshold, int period
                             int* overflow, double* part, int n_part, hipStream_t s);
 hipError_t launch_moment(const double* w, int n, double dx, double p, int m, double* part,
                          int n_part, hipStream_t s);
+// Measure-vector partials: n_part blocks x [sum w, sum w r^2, sum w^2,
+// sum w^2 r^2, max w].
+hipError_t launch_measure(const double* w, int n, double dx, double* part, int n_part,
+                          hipStream_t s);
 
 hipError_t launch_block_mean(const double* src, int n, int b, double* dst,
                              hipStream_t s);

@@ -121,7 +121,7 @@ constexpr int tw_regs() {
 // ------------------------------------------------------------ row pass
 template <typename R, class P, int KIND>
 __global__ void __launch_bounds__(P::THREADS)
-    __attribute__((amdgpu_waves_per_eu(P::WAVES_PER_EU))) k_row(PassArgs<R> a) {
+    __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? P::WAVES_PER_EU : 1))) k_row(PassArgs<R> a) {
   constexpr int N = P::N, T = P::T, E = P::E;
   using L = LdsLineMajor<R, N>;
   __shared__ cx<R> lds_mem[P::LINES * L::LINE];
@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(P::THREADS)
 // --------------------------------------------------------- column pass
 template <typename R, class P, int KIND>
 __global__ void __launch_bounds__(P::THREADS)
-    __attribute__((amdgpu_waves_per_eu(P::WAVES_PER_EU))) k_col(PassArgs<R> a) {
+    __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? P::WAVES_PER_EU : 1))) k_col(PassArgs<R> a) {
   constexpr int N = P::N, T = P::T, E = P::E, W = P::LINES;
   using L = LdsPointMajor<R, W, P::PA, P::PB>;
   __shared__ cx<R> lds_mem[L::size(N)];

@@ -414,7 +414,9 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
   l.seed_loss = take(sizeof(double) * max_n);
   l.seed_theta = take(sizeof(double) * 8 * max_n * n_inst);
   l.scal = take(sizeof(double) * 16);
-  l.sumsq_part = take(sizeof(double) * 256);
+  // 256 partials of a sum of squares, moment or hot-area count, then 256 x 5
+  // measure-vector partials
+  l.sumsq_part = take(sizeof(double) * 256 * 6);
   l.lens_inst = take(sizeof(InstDev) * n_inst);
   l.half_inst = take(sizeof(InstDev) * n_inst);
   l.back_inst = take(sizeof(InstDev) * n_inst);
@@ -2140,6 +2142,68 @@ int ssfm_hot_areas_static(const double* w, int32_t n, double threshold, int32_t 
   double total = 0.0;
   for (int k = 0; k < kStaticParts; ++k) total += host[k];
   *count = int64_t(total);
+  return SSFM_OK;
+}
+
+namespace {
+// The measure vector of an n x n device fluence w (see ssfm_measure_vector);
+// the hot-area labels use the staging area's first half.
+int measure(ssfm_ctx* c, const double* w, int32_t n, double length, double w_p,
+            int32_t periodic, double* p) {
+  constexpr int kParts = 256;
+  const double dx = length / n;
+  double* part = c->at<double>(c->L.sumsq_part) + kParts;
+  HIP_TRY(launch_measure(w, n, dx, part, kParts, c->stream));
+  std::vector<double> host(5 * kParts);
+  HIP_TRY(hipMemcpyAsync(host.data(), part, sizeof(double) * host.size(), hipMemcpyDeviceToHost,
+                         c->stream));
+  int64_t count = 0;
+  if (int r = ssfm_hot_areas(c, w, n, w_p, periodic, &count)) return r;  // synchronises
+  double acc[4] = {0.0, 0.0, 0.0, 0.0}, mx = 0.0;
+  for (int b = 0; b < kParts; ++b) {
+    for (int k = 0; k < 4; ++k) acc[k] += host[5 * b + k];
+    mx = std::max(mx, host[5 * b + 4]);
+  }
+  p[0] = acc[0] * dx * dx;  // Q(1, 0)
+  p[1] = acc[1] * dx * dx;  // Q(1, 1)
+  p[2] = acc[2] * dx * dx;  // Q(2, 0)
+  p[3] = acc[3] * dx * dx;  // Q(2, 1)
+  p[4] = mx;
+  p[5] = double(count);
+  return SSFM_OK;
+}
+}  // namespace
+
+int ssfm_measure_vector(ssfm_ctx* c, const double* w, int32_t n, double length, double w_p,
+                        int32_t periodic, double* p) {
+  if (int r = check_ctx(c)) return r;
+  if (!w || !p) return fail(SSFM_EINVAL, "w/p is NULL");
+  if (n < 1 || n > c->L.max_n || !(length > 0.0) || !std::isfinite(w_p))
+    return fail(SSFM_EINVAL, "need 1 <= n <= %d, length > 0, finite w_p", c->L.max_n);
+  return measure(c, w, n, length, w_p, periodic, p);
+}
+
+int ssfm_measure_distance(ssfm_ctx* c, int32_t inst, double w_p, int32_t periodic,
+                          const double* p0, double* d, double* p) {
+  if (int r = check_inst(c, inst)) return r;
+  if (!p0 || !d) return fail(SSFM_EINVAL, "p0/d is NULL");
+  if (!std::isfinite(w_p)) return fail(SSFM_EINVAL, "w_p must be finite");
+  const ssfm_instance_desc& desc = c->desc[inst];
+  const int n = desc.n;
+  // the fluence into the staging area's second half (the labels use the first)
+  double* w = c->at<double>(c->L.stage) + size_t(c->L.max_n) * c->L.max_n;
+  if (int r = SSFM_DISPATCH(c, read_out, c, inst, w, SSFM_DEVICE, true)) return r;
+  double pv[SSFM_MEASURE_LEN];
+  if (int r = measure(c, w, n, desc.length, w_p, periodic, pv)) return r;
+  double acc = 0.0;
+  for (int k = 0; k < SSFM_MEASURE_LEN; ++k) {
+    const double s = (p0[k] != 0.0) ? std::fabs(p0[k]) : 1.0;
+    const double q = (pv[k] - p0[k]) / s;
+    acc += q * q;
+  }
+  *d = std::sqrt(acc);
+  if (p)
+    for (int k = 0; k < SSFM_MEASURE_LEN; ++k) p[k] = pv[k];
   return SSFM_OK;
 }
 

@@ -276,6 +276,27 @@ class Propagator:
                float(threshold), 1 if periodic else 0, ctypes.byref(out))
         return out.value
 
+    def measure_vector(self, w: torch.Tensor, length: float, w_p: float,
+                       periodic: bool = True) -> np.ndarray:
+        """P = (Q(1,0), Q(1,1), Q(2,0), Q(2,1), max w, N_ha(w >= w_p)) of an
+        n x n float64 fluence on this device (the GA's measure vector)."""
+        w = w.to(device=self.device, dtype=torch.float64).contiguous()
+        out = (ctypes.c_double * L.MEASURE_LEN)()
+        L.call("ssfm_measure_vector", self.ctx, ctypes.c_void_p(w.data_ptr()), w.shape[0],
+               float(length), float(w_p), 1 if periodic else 0, out)
+        return np.array(list(out))
+
+    def measure_distance(self, i: int, p0: Sequence[float], w_p: float,
+                         periodic: bool = True) -> Tuple[float, np.ndarray]:
+        """(d, P): the relative Euclidean distance of instance i's current
+        fluence's measure vector P from p0, and P."""
+        ref = (ctypes.c_double * L.MEASURE_LEN)(*[float(v) for v in p0])
+        d = ctypes.c_double()
+        out = (ctypes.c_double * L.MEASURE_LEN)()
+        L.call("ssfm_measure_distance", self.ctx, i, float(w_p), 1 if periodic else 0, ref,
+               ctypes.byref(d), out)
+        return d.value, np.array(list(out))
+
     def moment(self, w: torch.Tensor, length: float, p: float, m: int) -> float:
         """Q(p, m) = sum w^p (x^2 + y^2)^m dx^2 of an n x n float64 fluence."""
         w = w.to(device=self.device, dtype=torch.float64).contiguous()

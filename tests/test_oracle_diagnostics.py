@@ -87,3 +87,39 @@ def test_moments_of_a_gaussian():
     assert D.moment(w, length, 1, 1) == pytest.approx(p * w0 ** 2 / 2, rel=1e-12)
     assert D.moment(w, length, 2, 1) == pytest.approx(math.pi * i0 ** 2 * w0 ** 4 / 16, rel=1e-12)
     assert D.moment(w, length, 0, 0) == pytest.approx(length ** 2, rel=1e-14)
+
+
+def test_measure_vector_of_a_gaussian():
+    """Closed forms of the fluence w = I0 exp(-2 r^2 / w0^2) on a window
+    wide enough to hold it (int_0^inf r^3 exp(-a r^2) dr = 1 / (2 a^2)):
+    energy pi w0^2 I0 / 2, Q(1,1) = pi w0^4 I0 / 4, Q(2,0) = pi w0^2 I0^2 / 4,
+    Q(2,1) = pi w0^4 I0^2 / 16, peak I0 (the grid
+    is cell-centred, so the peak sample sits half a cell off axis: I0
+    exp(-dx^2 / w0^2)), one hot area above half the peak."""
+    n, length, w0, i0 = 256, 8e-3, 1e-3, 3e16
+    r2 = D.grid_r2(n, length)
+    w = i0 * np.exp(-2 * r2 / w0 ** 2)
+    p = D.measure_vector(w, length, 0.5 * i0)
+    dx = length / n
+    want = [np.pi * w0 ** 2 * i0 / 2, np.pi * w0 ** 4 * i0 / 4, np.pi * w0 ** 2 * i0 ** 2 / 4,
+            np.pi * w0 ** 4 * i0 ** 2 / 16, i0 * np.exp(-dx ** 2 / w0 ** 2), 1.0]
+    assert np.allclose(p, want, rtol=1e-10, atol=0)
+    assert D.MEASURE_NAMES[0].startswith("energy") and len(D.MEASURE_NAMES) == len(p)
+
+
+def test_measure_distance_by_hand():
+    """Relative Euclidean distance: equal vectors 0; one component doubled
+    1; two components each 10 % off sqrt(0.02); a zero reference component
+    counts absolutely; scaling P and P0 together leaves d."""
+    p0 = np.array([2.0, 4.0, 8.0, 16.0, 1.0, 3.0])
+    assert D.measure_distance(p0, p0) == 0.0
+    p = p0.copy()
+    p[2] *= 2
+    assert D.measure_distance(p, p0) == pytest.approx(1.0, rel=1e-15)
+    p = p0.copy()
+    p[0] *= 1.1
+    p[5] *= 0.9
+    assert D.measure_distance(p, p0) == pytest.approx(np.sqrt(0.02), rel=1e-14)
+    z = np.array([1.0, 0.0])
+    assert D.measure_distance(np.array([1.0, 0.5]), z) == pytest.approx(0.5, rel=1e-15)
+    assert D.measure_distance(7 * p, 7 * p0) == pytest.approx(D.measure_distance(p, p0), rel=1e-14)
