@@ -89,7 +89,7 @@ def run_headline(args):
     import torch
 
     import workloads as W
-    from paper_2306_15678_amd.march import Propagator, checkpoint_interval
+    from paper_2306_15678_amd.march import Propagator, checkpoint_plan
     from paper_2306_15678_amd.tune import tune
 
     dev = torch.device("cuda", 0)
@@ -102,13 +102,20 @@ def run_headline(args):
     out = {}
 
     def make(precision):
-        m = args.ckpt_every or checkpoint_interval(_desc_list([inst]), precision, z_steps)
+        # checkpoints every M steps, the last K segments kept whole: the
+        # layout that fits three quarters of the free HBM and recomputes the
+        # fewest steps (or plain checkpointing every --ckpt-every steps)
+        if args.ckpt_every:
+            m, k = args.ckpt_every, 0
+            rec = _ckpt_plan(z_steps, m)[1]
+        else:
+            m, k, rec = checkpoint_plan(_desc_list([inst]), precision, z_steps)
         p = Propagator(_desc_list([inst]), precision=precision, max_steps=z_steps,
-                       ckpt_every=m, device=dev)
+                       ckpt_every=m, stored_segments=k, device=dev)
         tuned = tune(p, reps=10, use_cache=False)[n]
         p.gen_screens()
         p.set_theta(0, inst.theta)
-        return p, m, tuned
+        return p, {"ckpt_every": m, "stored_segments": k, "recomputed_steps": rec}, tuned
 
     def fwd_adj(p):
         def go():
@@ -118,11 +125,12 @@ def run_headline(args):
             p.backward()
         return go
 
-    p, m, tuned = make(32)
-    _say(f"headline fp32: 4096^2 x {z_steps} steps, checkpoint every {m}, "
-         f"workspace {p.ws_bytes / 2**30:.1f} GiB")
+    p, ck, tuned = make(32)
+    _say(f"headline fp32: 4096^2 x {z_steps} steps, checkpoint every {ck['ckpt_every']}, "
+         f"last {ck['stored_segments']} segments kept, {ck['recomputed_steps']} steps "
+         f"recomputed, workspace {p.ws_bytes / 2**30:.1f} GiB")
     t = _timed(fwd_adj(p), args.steps, args.warmup, p.synchronize)
-    out["fp32"] = {"s_per_step": t, "value": gp_steps / t, "ckpt_every": m,
+    out["fp32"] = {"s_per_step": t, "value": gp_steps / t, **ck,
                    "workspace_GiB": p.ws_bytes / 2 ** 30, "tune": tuned}
     _say(f"headline fp32: {t:.3f} s per step, {gp_steps / t:.3e} {UNIT}")
     # the same step sampled (untimed): pass kernels bracketed by events
@@ -147,11 +155,12 @@ def run_headline(args):
     del p
     torch.cuda.empty_cache()
     if not args.no_fp64:
-        q, m64, tuned64 = make(64)
-        _say(f"headline fp64: checkpoint every {m64}")
+        q, ck64, tuned64 = make(64)
+        _say(f"headline fp64: checkpoint every {ck64['ckpt_every']}, last "
+             f"{ck64['stored_segments']} segments kept")
         t64 = _timed(fwd_adj(q), 1, 1, q.synchronize)
-        out["fp64"] = {"s_per_step": t64, "value": gp_steps / t64, "ckpt_every": m64,
-                       "tune": tuned64}
+        out["fp64"] = {"s_per_step": t64, "value": gp_steps / t64, **ck64,
+                       "workspace_GiB": q.ws_bytes / 2 ** 30, "tune": tuned64}
         q.close()
         del q
         torch.cuda.empty_cache()
@@ -165,7 +174,7 @@ def roofline(head, copy_peak):
     inst = W.config5()[0]
     n2, z = float(inst.n) ** 2, inst.n_steps
     ps = head["passes"]
-    _, recomputed = _ckpt_plan(z, head["fp32"]["ckpt_every"])
+    recomputed = head["fp32"]["recomputed_steps"]
     launches = {"row_fwd": z + recomputed, "col_fwd": z + recomputed, "col_adj": z,
                 "row_adj": z}
     total = {k: ps[k] * launches[k] for k in launches}
@@ -227,13 +236,14 @@ def run_c2_fwd_adj(args):
     import torch
 
     import workloads as W
-    from paper_2306_15678_amd.march import Propagator, checkpoint_interval
+    from paper_2306_15678_amd.march import Propagator, checkpoint_plan
     from paper_2306_15678_amd.tune import tune
     dev = torch.device("cuda", 0)
     inst = W.config2()[0]
     z = inst.n_steps
-    m = checkpoint_interval(_desc_list([inst]), 32, z)
-    p = Propagator(_desc_list([inst]), precision=32, max_steps=z, ckpt_every=m, device=dev)
+    m, k, _ = checkpoint_plan(_desc_list([inst]), 32, z)
+    p = Propagator(_desc_list([inst]), precision=32, max_steps=z, ckpt_every=m,
+                   stored_segments=k, device=dev)
     tune(p, reps=10, use_cache=False)
     u0_d = torch.from_numpy(W.initial_field(inst)).to(dev)
     tgt_d = torch.from_numpy(W.synthetic_target(inst, 2)).to(dev)
@@ -254,6 +264,7 @@ def run_c2_fwd_adj(args):
     return {"workload": "multifilament beam, 1024x1024 complex64, Kerr+MPA+plasma, "
                         f"2000 z steps, forward+adjoint, checkpoint every {m}",
             "value": gp / t, "unit": UNIT, "ms_per_step": t * 1e3, "ckpt_every": m,
+            "stored_segments": k,
             "parity": par, "diagnostics": diag}
 
 
@@ -264,14 +275,14 @@ def run_batched(args):
     import torch
 
     import workloads as W
-    from paper_2306_15678_amd.march import Propagator, checkpoint_interval
+    from paper_2306_15678_amd.march import Propagator, checkpoint_plan
     from paper_2306_15678_amd.tune import tune
     insts = W.config3()
     z = insts[0].n_steps
     gp = float(sum(i.n * i.n for i in insts)) * z
-    m = checkpoint_interval(_desc_list(insts), 32, z)
+    m, k, _ = checkpoint_plan(_desc_list(insts), 32, z)
     p = Propagator(_desc_list(insts), precision=32, max_steps=z, ckpt_every=m,
-                   device=torch.device("cuda", 0))
+                   stored_segments=k, device=torch.device("cuda", 0))
     tune(p, reps=10, use_cache=False)
     p.gen_screens()
     fields = [torch.from_numpy(W.initial_field(i)).to("cuda") for i in insts]
@@ -301,8 +312,9 @@ def run_batched(args):
     return ({"workload": work + ", forward", "value": gp / tf, "unit": UNIT,
              "ms_per_march": tf * 1e3},
             {"workload": work + f", forward+adjoint (fluence loss on every beam), "
-                                f"checkpoint every {m}",
-             "value": gp / ta, "unit": UNIT, "ms_per_step": ta * 1e3, "ckpt_every": m})
+                                f"checkpoint every {m}, last {k} segments kept",
+             "value": gp / ta, "unit": UNIT, "ms_per_step": ta * 1e3, "ckpt_every": m,
+             "stored_segments": k})
 
 
 FD_ITERS = 4
@@ -552,9 +564,13 @@ def main():
     copy_peak = measured_copy_peak()
     t32 = head["fp32"]["s_per_step"]
     m = head["fp32"]["ckpt_every"]
-    survey_bytes = 112.0 + 8.0 / m if m < inst.n_steps else 80.0
-    design_bytes = 104.0 - 32.0 / m if m < inst.n_steps else 72.0
-    march_gbps = head["fp32"]["value"] * survey_bytes / 1e9
+    k = head["fp32"]["stored_segments"]
+    rec = head["fp32"]["recomputed_steps"]
+    # whole-march algorithmic bytes per grid point and z step (complex64):
+    # forward 32, adjoint 40 (its row pass reads the stored V), and 32 per
+    # recomputed step; recording writes nothing beyond the march's own output
+    design_bytes = 72.0 + 32.0 * rec / inst.n_steps
+    march_gbps = head["fp32"]["value"] * design_bytes / 1e9
     line = {
         "metric": METRIC,
         "value": head["fp32"]["value"],
@@ -571,20 +587,20 @@ def main():
         "config": {
             "workload": "large-aperture beam, 4096x4096 complex64 (FP64 reductions), "
                         "Kerr+MPA+plasma+ansatz, 50 Kolmogorov screens over 1 km, 5000 z steps, "
-                        f"forward+adjoint, checkpoint every {m} steps",
+                        f"forward+adjoint, checkpoint every {m} steps, last {k} segments "
+                        f"kept whole ({rec} steps recomputed)",
             "grid": inst.n, "z_steps": inst.n_steps, "ckpt_every": m,
+            "stored_segments": k, "recomputed_steps": rec,
             "workspace_GiB": round(head["fp32"]["workspace_GiB"], 2),
             "beam": "w0=2.5 cm, 1000 P_cr, 5% seeded noise, window 12 cm, dz=20 cm",
         },
         "roofline": roofline(head, copy_peak),
         "march_hbm": {
-            "bytes_per_gp_step_survey": survey_bytes,
-            "bytes_per_gp_step_this_design": design_bytes,
+            "bytes_per_gp_step": design_bytes,
             "achieved_GBps": march_gbps,
             "frac": march_gbps / HBM_PEAK_GBS,
-            "frac_this_design_bytes": head["fp32"]["value"] * design_bytes / 1e9 / HBM_PEAK_GBS,
-            "note": "whole-march algorithmic bytes (forward with checkpoints, recompute, adjoint) "
-                    "x grid-point.steps/s over the 8 TB/s spec",
+            "note": "whole-march algorithmic bytes (forward 32, adjoint 40, 32 per recomputed "
+                    "step, per grid point and z step) x grid-point.steps/s over the 8 TB/s spec",
         },
         "passes_ms": head["passes"],
         "forward_only": {"value": head["fwd"]["value"],
@@ -595,6 +611,7 @@ def main():
     if "fp64" in head:
         line["fp64"] = {"value": head["fp64"]["value"], "ms_per_step": head["fp64"]["s_per_step"] * 1e3,
                         "ckpt_every": head["fp64"]["ckpt_every"],
+                        "stored_segments": head["fp64"]["stored_segments"],
                         "speedup_fp32_over_fp64": head["fp64"]["s_per_step"] / t32}
     if not args.no_extra:
         _say("1024^2 forward+adjoint")

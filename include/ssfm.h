@@ -109,19 +109,39 @@ const char* ssfm_last_error(void);
  *                  (0 if ssfm_forward_record() will not be used)
  *   ckpt_every   : M, steps per adjoint checkpoint segment (M >= 1; M >=
  *                  max_steps stores every step and needs no recompute)
- * Writes the byte count to *bytes.  Pure host computation. */
+ *   stored_segments : K >= 0, the last K segments of a recorded march are
+ *                  kept whole (every pre-screen field) by the forward
+ *                  itself, so the backward recomputes only the others; each
+ *                  costs M - 1 fields of workspace
+ * Writes the byte count to *bytes.  Pure host computation.  SSFM_EINVAL
+ * for a bad argument, SSFM_EUNSUPPORTED for an unsupported grid size. */
 int ssfm_workspace_bytes(const ssfm_instance_desc* desc, int32_t n_inst,
                          int32_t precision, int64_t max_steps,
-                         int32_t ckpt_every, size_t* bytes);
+                         int32_t ckpt_every, int32_t stored_segments,
+                         size_t* bytes);
+
+/* Checkpointing of a recorded march of n_steps that fits budget_bytes of
+ * workspace (the memory side of the adjoint: the trajectory the backward
+ * needs, Math and Equations, kept or recomputed).  Every pre-screen field
+ * when that fits (M = n_steps, K = 0); else the (M, K) of
+ * ssfm_workspace_bytes that fits and minimises the steps the backward
+ * recomputes plus one per segment.  Writes M to *ckpt_every, K to
+ * *stored_segments and, if recomputed is not NULL, the steps the backward
+ * recomputes.  Pure host computation.  SSFM_EWORKSPACE if no layout fits. */
+int ssfm_checkpoint_plan(const ssfm_instance_desc* desc, int32_t n_inst,
+                         int32_t precision, int64_t n_steps,
+                         size_t budget_bytes, int32_t* ckpt_every,
+                         int32_t* stored_segments, int64_t* recomputed);
 
 /* Create a context over a caller-owned device workspace of ws_bytes bytes
- * (256-byte aligned, at least ssfm_workspace_bytes()).  Builds the
- * propagator and twiddle tables (FP64 on the host, rounded once) and the
- * work lists; fields start at zero.  stream: hipStream_t or NULL. */
+ * (256-byte aligned, at least ssfm_workspace_bytes() of the same
+ * arguments).  Builds the propagator and twiddle tables (FP64 on the host,
+ * rounded once) and the work lists; fields start at zero.  stream:
+ * hipStream_t or NULL. */
 int ssfm_create(const ssfm_instance_desc* desc, int32_t n_inst,
                 int32_t precision, int64_t max_steps, int32_t ckpt_every,
-                void* workspace, size_t ws_bytes, void* stream,
-                ssfm_ctx** out);
+                int32_t stored_segments, void* workspace, size_t ws_bytes,
+                void* stream, ssfm_ctx** out);
 
 /* Release the context's host objects (not the workspace).  Synchronises. */
 int ssfm_destroy(ssfm_ctx* ctx);
@@ -259,8 +279,9 @@ int ssfm_get_diag(ssfm_ctx* ctx, int32_t inst, double* power, double* peak,
  * max_steps) from the current fields, keeping what its adjoint needs for
  * fitting the screen parameters to a discrepancy (Math and Equations: the
  * effective screen's parameters minimise the residual against the dense
- * solution): the field at the start of every segment of M steps, or every
- * pre-screen field when M >= n_steps.  Drops earlier cotangents.
+ * solution): the field at the start of every segment of M steps and every
+ * pre-screen field of the last K (stored_segments) segments; all of them
+ * when M >= n_steps.  Drops earlier cotangents.
  * SSFM_EINVAL if n_steps exceeds max_steps or is < 1. */
 int ssfm_forward_record(ssfm_ctx* ctx, int64_t n_steps);
 
@@ -293,9 +314,9 @@ int ssfm_fluence_mismatch(ssfm_ctx* ctx, int32_t inst, const void* target,
 
 /* Exact discrete adjoint of the recorded march (the Eq. (1), (3), (9)
  * split steps in reverse) back to its first step, recomputing each segment
- * from its checkpoint when M < n_steps; gives dL/dU_0 and dL/dtheta for
- * fitting the screen parameters by gradients (Math and Equations fits them
- * with a genetic algorithm).  Instances without a cotangent since the
+ * the record did not keep whole from its checkpoint; gives dL/dU_0 and
+ * dL/dtheta for fitting the screen parameters by gradients (Math and
+ * Equations fits them with a genetic algorithm).  Instances without a cotangent since the
  * record contribute nothing to L: their gradients are zero.  SSFM_ESTATE
  * without a record or without any cotangent. */
 int ssfm_backward(ssfm_ctx* ctx);

@@ -57,9 +57,12 @@ _SIGS = {
     "ssfm_strerror": (c_char_p, [c_int32]),
     "ssfm_last_error": (c_char_p, []),
     "ssfm_workspace_bytes": (c_int32, [POINTER(InstanceDesc), c_int32, c_int32, c_int64,
-                                       c_int32, POINTER(c_size_t)]),
+                                       c_int32, c_int32, POINTER(c_size_t)]),
+    "ssfm_checkpoint_plan": (c_int32, [POINTER(InstanceDesc), c_int32, c_int32, c_int64,
+                                       c_size_t, POINTER(c_int32), POINTER(c_int32),
+                                       POINTER(c_int64)]),
     "ssfm_create": (c_int32, [POINTER(InstanceDesc), c_int32, c_int32, c_int64, c_int32,
-                              c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
+                              c_int32, c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
     "ssfm_destroy": (c_int32, [c_void_p]),
     "ssfm_set_field": (c_int32, [c_void_p, c_int32, c_void_p, c_int32]),
     "ssfm_set_theta": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),

@@ -101,6 +101,9 @@ struct Layout {
   int64_t n_work_rows, n_work_cols;  // launch entries (with padding)
   int64_t n_widx_rows, n_widx_cols;  // real work items
   int64_t n_ckpt, n_stack, diag_cap, screen_elems, n_steps_total;
+  // regions of n_stack segment slots: recompute banks (0, 1 or 2) and
+  // segments kept whole by the forward record
+  int64_t n_banks, n_kept;
   int max_n;
 };
 
@@ -150,6 +153,7 @@ struct ssfm_ctx {
   hipStream_t stream = nullptr;
   int64_t max_steps = 0;
   int32_t ckpt_every = 1;
+  int32_t stored_segments = 0;  // last segments of a record kept whole
   // march state
   int64_t step = 0;        // steps taken since the last set_field
   bool pending = false;    // state holds V with its screen still to apply
@@ -285,7 +289,8 @@ int64_t max_items(bool column, int n, bool fp64) {
 }
 
 int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t max_steps,
-                int32_t ckpt_every, const VariantMap* variants, std::vector<Group>* groups_out,
+                int32_t ckpt_every, int32_t stored_segments, const VariantMap* variants,
+                std::vector<Group>* groups_out,
                 std::vector<WorkItem>* work_out, std::vector<int32_t>* wb_row,
                 std::vector<int32_t>* wb_col, Layout* L) {
   const size_t el = precision == SSFM_FP64 ? 16 : 8;
@@ -379,6 +384,13 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
     const int64_t seg = std::min<int64_t>(m, max_steps);
     l.n_ckpt = (max_steps + seg - 1) / seg;
     l.n_stack = seg - 1;
+    if (l.n_ckpt == 1) {
+      l.n_banks = 0;  // a single segment is always kept whole
+      l.n_kept = 1;
+    } else {
+      l.n_kept = std::min<int64_t>(stored_segments, l.n_ckpt);
+      l.n_banks = std::min<int64_t>(2, l.n_ckpt - l.n_kept);
+    }
   }
   l.diag_cap = std::max<int64_t>(max_steps, 4096);
   size_t off = 0;
@@ -402,7 +414,7 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
   l.Wk2 = take(l.n_ckpt > 1 ? el * fe : 0);
   l.Lam = take(max_steps > 0 ? el * fe : 0);
   l.ckpt = take(el * fe * l.n_ckpt);
-  l.stack = take(el * fe * l.n_stack * (l.n_ckpt > 1 ? 2 : 1));
+  l.stack = take(el * fe * l.n_stack * (l.n_banks + l.n_kept));
   l.screens = take(rel * se);
   l.stage = take(16 * size_t(max_n) * max_n);
   // power partials of column work items (split-step) or row work items
@@ -847,12 +859,40 @@ int64_t rec_pending(const ssfm_ctx* c, int64_t step0, int64_t step) {
   return (step == step0) ? -1 : step - 1;
 }
 
+// Segments of a record of n steps.  Segment k covers s_{kM} .. s_{kM+M-1}:
+// s_{kM} is checkpoint k, the others sit in segment slots (a region of
+// n_stack fields).  Segments k >= first_kept are written whole by the
+// forward record, each in a region of its own after the recompute banks;
+// the backward recomputes the others from their checkpoints, alternating
+// between banks 0 and 1.  A single-segment record is kept whole in region 0.
+struct Segments {
+  int64_t M, n_seg, first_kept, banks;
+  int64_t region(int64_t k) const { return k >= first_kept ? banks + (k - first_kept) : k % 2; }
+  bool recomputed(int64_t k) const { return k < first_kept; }
+};
+
+Segments rec_segments(const ssfm_ctx* c, int64_t n) {
+  Segments g;
+  g.M = std::min<int64_t>(std::max<int32_t>(c->ckpt_every, 1), n);
+  g.n_seg = (n + g.M - 1) / g.M;
+  if (g.n_seg == 1) {
+    g.first_kept = 0;
+    g.banks = 0;
+  } else {
+    // never more kept segments than the layout has regions for (a record
+    // shorter than max_steps has no more segments than the layout)
+    g.first_kept = g.n_seg - std::min<int64_t>(c->L.n_kept, g.n_seg);
+    g.banks = c->L.n_banks;
+  }
+  return g;
+}
+
 // Location of s_i during a record of n steps (i in [0, n]).
-void* rec_slot(ssfm_ctx* c, int64_t i, int64_t n) {
-  const int64_t M = std::min<int64_t>(std::max<int32_t>(c->ckpt_every, 1), n);
+void* rec_slot(ssfm_ctx* c, const Segments& g, int64_t i, int64_t n) {
   if (i == n) return c->field(c->L.S);
-  if (i % M == 0) return c->field(c->L.ckpt, i / M);
-  if (n <= M) return c->field(c->L.stack, i - 1);  // single segment: all stored
+  if (i % g.M == 0) return c->field(c->L.ckpt, i / g.M);
+  const int64_t k = i / g.M;
+  if (!g.recomputed(k)) return c->field(c->L.stack, g.region(k) * c->L.n_stack + i % g.M - 1);
   return c->field(c->L.S);
 }
 
@@ -865,11 +905,12 @@ int enqueue_record(ssfm_ctx* c, int64_t n, int64_t step0, int64_t i0, int64_t i1
     HIP_TRY(launch_copy<R>(c->field(c->L.S), c->field(c->L.ckpt, 0), c->L.field_elems,
                            c->stream));
   int64_t chunk_start = step0 + i0;
+  const Segments g = rec_segments(c, n);
   for (int64_t i = i0; i < i1; ++i) {
     const int slot = int((i - i0) % kDiagChunk);
     double* part = c->at<double>(c->L.diag_part) + size_t(slot) * 2 * c->L.n_widx_cols;
     const int64_t pend = rec_pending(c, step0, step0 + i);
-    if (int r = fwd_step<R>(c, rec_slot(c, i, n), rec_slot(c, i + 1, n), pend, part, nullptr,
+    if (int r = fwd_step<R>(c, rec_slot(c, g, i, n), rec_slot(c, g, i + 1, n), pend, part, nullptr,
                             nullptr, ts))
       return r;
     if (slot == kDiagChunk - 1 || i == i1 - 1) {
@@ -902,20 +943,19 @@ int do_record(ssfm_ctx* c, int64_t n) {
   return SSFM_OK;
 }
 
-// Backward over the recorded march, segment by segment from the last.  With
-// more than one segment, segment k-1 is recomputed from its checkpoint on
-// the auxiliary stream (into the other bank of segment slots, with its own
+// Backward over the recorded march, segment by segment from the last.  A
+// segment the forward did not keep whole is recomputed from its checkpoint:
+// segment k-1 on the auxiliary stream (into the other bank, with its own
 // work buffer) while the adjoint of segment k runs on the main stream; the
 // two chains join before the adjoint of segment k-1.
 template <typename R>
 int enqueue_backward(ssfm_ctx* c) {
   const int64_t n = c->rec_steps, step0 = c->rec_step0;
-  const int64_t M = std::min<int64_t>(std::max<int32_t>(c->ckpt_every, 1), n);
-  const int64_t n_seg = (n + M - 1) / M;
-  const bool stored = n <= M;
+  const Segments g = rec_segments(c, n);
+  const int64_t M = g.M, n_seg = g.n_seg;
   const int64_t bank = c->L.n_stack;
-  auto slot = [&](int64_t k, int64_t i) -> void* {  // slot i of segment k's bank
-    return c->field(c->L.stack, (stored ? 0 : (k % 2) * bank) + i);
+  auto slot = [&](int64_t k, int64_t i) -> void* {  // slot i of segment k's region
+    return c->field(c->L.stack, g.region(k) * bank + i);
   };
   auto sv = [&](int64_t k, int64_t i) -> void* {  // s_{kM+i}
     if (i == 0) return c->field(c->L.ckpt, k);
@@ -936,11 +976,11 @@ int enqueue_backward(ssfm_ctx* c) {
   // adjoint starts from L(dz/2) of it (the adjoint of the read-out)
   if (c->strang)
     if (int r = half_step_lam<R>(c, true)) return r;
-  if (!stored) {
+  if (g.recomputed(n_seg - 1)) {
     if (int r = recompute(n_seg - 1, c->field(c->L.Wk), c->stream)) return r;
   }
   for (int64_t k = n_seg - 1; k >= 0; --k) {
-    const bool overlap = !stored && k >= 1;
+    const bool overlap = k >= 1 && g.recomputed(k - 1);
     if (overlap) {
       HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
       HIP_TRY(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
@@ -1469,7 +1509,7 @@ int do_select(ssfm_ctx* c, int32_t n, int32_t rv, int32_t cv) {
   std::vector<WorkItem> work;
   std::vector<int32_t> wr, wc;
   if (int r = plan_layout(c->desc.data(), int(c->desc.size()), c->precision, c->max_steps,
-                          c->ckpt_every, &vm, &groups, &work, &wr, &wc, &L2))
+                          c->ckpt_every, c->stored_segments, &vm, &groups, &work, &wr, &wc, &L2))
     return r;
   if (L2.total != c->L.total) return fail(SSFM_EUNSUPPORTED, "variant changes the workspace layout");
   // keep each size's adjoint variants while their lines per workgroup still
@@ -1525,27 +1565,111 @@ const char* ssfm_strerror(int s) {
 const char* ssfm_last_error(void) { return g_last_error.c_str(); }
 
 int ssfm_workspace_bytes(const ssfm_instance_desc* desc, int32_t n_inst, int32_t precision,
-                         int64_t max_steps, int32_t ckpt_every, size_t* bytes) {
+                         int64_t max_steps, int32_t ckpt_every, int32_t stored_segments,
+                         size_t* bytes) {
   g_last_error.clear();
   if (!bytes) return fail(SSFM_EINVAL, "bytes is NULL");
   if (int r = validate_desc(desc, n_inst, precision)) return r;
-  if (max_steps < 0 || ckpt_every < 1) return fail(SSFM_EINVAL, "need max_steps >= 0, ckpt_every >= 1");
+  if (max_steps < 0 || ckpt_every < 1 || stored_segments < 0)
+    return fail(SSFM_EINVAL, "need max_steps >= 0, ckpt_every >= 1, stored_segments >= 0");
   Layout L;
-  if (int r = plan_layout(desc, n_inst, precision, max_steps, ckpt_every, nullptr, nullptr,
-                          nullptr, nullptr, nullptr, &L))
+  if (int r = plan_layout(desc, n_inst, precision, max_steps, ckpt_every, stored_segments,
+                          nullptr, nullptr, nullptr, nullptr, nullptr, &L))
     return r;
   *bytes = L.total;
   return SSFM_OK;
 }
 
+int ssfm_checkpoint_plan(const ssfm_instance_desc* desc, int32_t n_inst, int32_t precision,
+                         int64_t n_steps, size_t budget_bytes, int32_t* ckpt_every,
+                         int32_t* stored_segments, int64_t* recomputed) {
+  g_last_error.clear();
+  if (!ckpt_every || !stored_segments) return fail(SSFM_EINVAL, "output pointer is NULL");
+  if (int r = validate_desc(desc, n_inst, precision)) return r;
+  if (n_steps < 1 || n_steps > INT32_MAX) return fail(SSFM_EINVAL, "need 1 <= n_steps < 2^31");
+  Layout L;
+  auto bytes_of = [&](int64_t m, int64_t k, size_t* out) {
+    int r = plan_layout(desc, n_inst, precision, n_steps, int32_t(m), int32_t(k), nullptr,
+                        nullptr, nullptr, nullptr, nullptr, &L);
+    *out = L.total;
+    return r;
+  };
+  size_t b = 0;
+  // every pre-screen field kept: no recompute
+  if (int r = bytes_of(n_steps, 0, &b)) return r;
+  if (b <= budget_bytes) {
+    *ckpt_every = int32_t(n_steps);
+    *stored_segments = 0;
+    if (recomputed) *recomputed = 0;
+    return SSFM_OK;
+  }
+  if (n_steps < 3) return fail(SSFM_EWORKSPACE, "%zu bytes needed, budget %zu", b, budget_bytes);
+  // With M < n_steps the layout is affine in its field slots (every field
+  // array is a whole number of alignment units): bytes = A + F * slots,
+  // slots = checkpoints + (M - 1) * (banks + kept segments).
+  auto slots_of = [&](int64_t m, int64_t k) {
+    const int64_t seg = (n_steps + m - 1) / m;
+    const int64_t kept = std::min(k, seg);
+    return seg + (m - 1) * (std::min<int64_t>(2, seg - kept) + kept);
+  };
+  size_t b2 = 0;
+  if (int r = bytes_of(2, 0, &b2)) return r;
+  const double F = double(L.field_elems) * (precision == SSFM_FP64 ? 16.0 : 8.0);
+  const double A = double(b2) - F * double(slots_of(2, 0));
+  const double cap = (double(budget_bytes) - A) / F;  // field slots that fit
+  // Cost of (M, K): steps recomputed by the backward, plus one per segment
+  // for its fork, join and checkpoint boundary; the cheapest that fits.
+  int64_t best_m = -1, best_k = 0, best_rec = 0;
+  double best_cost = 0.0;
+  for (int64_t m = 2; m < n_steps; ++m) {
+    const int64_t seg = (n_steps + m - 1) / m;
+    if (double(slots_of(m, 0)) > cap) continue;
+    // kept segments that fit (slots rise with K; K = seg - 1 costs what
+    // K = seg costs, so it is never the choice)
+    int64_t k = 0;
+    if (double(slots_of(m, seg)) <= cap) {
+      k = seg;
+    } else {
+      const double room = (cap - double(seg)) / double(m - 1) - 2.0;
+      k = std::max<int64_t>(0, std::min<int64_t>(seg - 2, int64_t(std::floor(room))));
+      while (k > 0 && double(slots_of(m, k)) > cap) --k;
+    }
+    const int64_t rec = (k == 0) ? n_steps - seg : (seg - std::min(k, seg)) * (m - 1);
+    const double cost = double(rec) + double(seg);
+    if (best_m < 0 || cost < best_cost) {
+      best_m = m;
+      best_k = k;
+      best_rec = rec;
+      best_cost = cost;
+    }
+  }
+  if (best_m < 0) {
+    // the smallest layout: M near sqrt(n_steps / 2), nothing kept
+    size_t need = 0;
+    bytes_of(std::max<int64_t>(2, int64_t(std::sqrt(0.5 * double(n_steps)))), 0, &need);
+    return fail(SSFM_EWORKSPACE, "no checkpoint layout fits %zu bytes (at least %zu needed)",
+                budget_bytes, need);
+  }
+  // the affine model is exact; confirm with the layout itself
+  if (int r = bytes_of(best_m, best_k, &b)) return r;
+  if (b > budget_bytes)
+    return fail(SSFM_EWORKSPACE, "checkpoint layout of %zu bytes exceeds budget %zu", b,
+                budget_bytes);
+  *ckpt_every = int32_t(best_m);
+  *stored_segments = int32_t(best_k);
+  if (recomputed) *recomputed = best_rec;
+  return SSFM_OK;
+}
+
 int ssfm_create(const ssfm_instance_desc* desc, int32_t n_inst, int32_t precision,
-                int64_t max_steps, int32_t ckpt_every, void* workspace, size_t ws_bytes,
-                void* stream, ssfm_ctx** out) {
+                int64_t max_steps, int32_t ckpt_every, int32_t stored_segments,
+                void* workspace, size_t ws_bytes, void* stream, ssfm_ctx** out) {
   g_last_error.clear();
   if (!out) return fail(SSFM_EINVAL, "out is NULL");
   *out = nullptr;
   if (int r = validate_desc(desc, n_inst, precision)) return r;
-  if (max_steps < 0 || ckpt_every < 1) return fail(SSFM_EINVAL, "need max_steps >= 0, ckpt_every >= 1");
+  if (max_steps < 0 || ckpt_every < 1 || stored_segments < 0)
+    return fail(SSFM_EINVAL, "need max_steps >= 0, ckpt_every >= 1, stored_segments >= 0");
   std::unique_ptr<ssfm_ctx> c(new ssfm_ctx);
   c->precision = precision;
   c->el = precision == SSFM_FP64 ? 16 : 8;
@@ -1553,8 +1677,10 @@ int ssfm_create(const ssfm_instance_desc* desc, int32_t n_inst, int32_t precisio
   c->seeded_beam.assign(n_inst, 0);
   c->max_steps = max_steps;
   c->ckpt_every = ckpt_every;
+  c->stored_segments = stored_segments;
   c->stream = static_cast<hipStream_t>(stream);
-  if (int r = plan_layout(desc, n_inst, precision, max_steps, ckpt_every, nullptr, &c->groups,
+  if (int r = plan_layout(desc, n_inst, precision, max_steps, ckpt_every, stored_segments,
+                          nullptr, &c->groups,
                           &c->work, &c->wbegin_row, &c->wbegin_col, &c->L))
     return r;
   if (!workspace) return fail(SSFM_EWORKSPACE, "workspace is NULL");

@@ -63,7 +63,7 @@ class Propagator:
     def __init__(self, descs: Sequence[L.InstanceDesc], precision: int = 32,
                  max_steps: int = 0, ckpt_every: int = 1,
                  device: Optional[torch.device] = None,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, stored_segments: int = 0):
         L.lib()
         if not torch.cuda.is_available():
             raise RuntimeError("Propagator needs a GPU (HIP device); none is visible")
@@ -76,7 +76,7 @@ class Propagator:
         self.max_steps = int(max_steps)
         nbytes = ctypes.c_size_t()
         L.call("ssfm_workspace_bytes", arr, self.n_inst, precision, max_steps,
-               ckpt_every, ctypes.byref(nbytes))
+               ckpt_every, stored_segments, ctypes.byref(nbytes))
         self.ws_bytes = nbytes.value
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8,
                                      device=self.device)
@@ -85,7 +85,7 @@ class Propagator:
         self.stream = stream or torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
         L.call("ssfm_create", arr, self.n_inst, precision, max_steps, ckpt_every,
-               ctypes.c_void_p(self._ws_ptr), self.ws_bytes,
+               stored_segments, ctypes.c_void_p(self._ws_ptr), self.ws_bytes,
                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
         self.ctx = ctx
 
@@ -403,13 +403,29 @@ def hot_area_trace(prop: "Propagator", i: int, n_steps: int, every: int,
 
 
 def workspace_bytes(descs: Sequence[L.InstanceDesc], precision: int, max_steps: int,
-                    ckpt_every: int) -> int:
+                    ckpt_every: int, stored_segments: int = 0) -> int:
     """Device workspace a context with these arguments needs."""
     arr = (L.InstanceDesc * len(descs))(*descs)
     nbytes = ctypes.c_size_t()
     L.call("ssfm_workspace_bytes", arr, len(descs), precision, max_steps, ckpt_every,
-           ctypes.byref(nbytes))
+           stored_segments, ctypes.byref(nbytes))
     return nbytes.value
+
+
+def checkpoint_plan(descs: Sequence[L.InstanceDesc], precision: int, n_steps: int,
+                    budget_bytes: Optional[int] = None) -> Tuple[int, int, int]:
+    """(M, K, recomputed steps) for a recorded march of n_steps whose
+    workspace fits the budget (default: three quarters of the free device
+    memory): every pre-screen field kept when that fits, else checkpoints
+    every M steps with the last K segments kept whole, chosen to recompute
+    the fewest steps (ssfm_checkpoint_plan)."""
+    if budget_bytes is None:
+        budget_bytes = torch.cuda.mem_get_info()[0] * 3 // 4
+    arr = (L.InstanceDesc * len(descs))(*descs)
+    m, k, rec = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    L.call("ssfm_checkpoint_plan", arr, len(descs), precision, n_steps, int(budget_bytes),
+           ctypes.byref(m), ctypes.byref(k), ctypes.byref(rec))
+    return m.value, k.value, rec.value
 
 
 def checkpoint_interval(descs: Sequence[L.InstanceDesc], precision: int, n_steps: int,

@@ -79,10 +79,12 @@ def _record_backward(p, insts, data, seeded):
     return losses
 
 
-@pytest.mark.parametrize("precision,ckpt", [(64, 3), (64, 100), (32, 3)])
-def test_batched_gradients_match_oracle_and_each_beam_alone(oracle_grads, precision, ckpt):
+@pytest.mark.parametrize("precision,ckpt,kept", [(64, 3, 0), (64, 100, 0), (32, 3, 0),
+                                                  (64, 3, 1), (32, 3, 2)])
+def test_batched_gradients_match_oracle_and_each_beam_alone(oracle_grads, precision, ckpt,
+                                                            kept):
     insts = _beams()
-    p = _prop(insts, precision, max_steps=STEPS, ckpt_every=ckpt)
+    p = _prop(insts, precision, max_steps=STEPS, ckpt_every=ckpt, stored_segments=kept)
     losses = _record_backward(p, insts, oracle_grads, range(len(insts)))
     tol = 1e-10 if precision == 64 else 1e-4
     for b, inst in enumerate(insts):
@@ -91,15 +93,49 @@ def test_batched_gradients_match_oracle_and_each_beam_alone(oracle_grads, precis
         lerr = abs(losses[b] / loss - 1)
         ferr = M.rel_l2(gu, g_u0)
         terr = float(np.max(np.abs(gt - g_th)) / np.max(np.abs(g_th)))
-        _report(f"batched grad fp{precision} M={ckpt} beam {b} n={inst.n}",
+        _report(f"batched grad fp{precision} M={ckpt} K={kept} beam {b} n={inst.n}",
                 loss=lerr, g_u0=ferr, g_theta=terr)
         assert lerr < tol and ferr < tol and terr < tol, b
-        q = _prop([inst], precision, max_steps=STEPS, ckpt_every=ckpt)
+        q = _prop([inst], precision, max_steps=STEPS, ckpt_every=ckpt, stored_segments=kept)
         _record_backward(q, [inst], [oracle_grads[b]], [0])
         assert np.array_equal(gu, q.grad_field(0)), b
         assert np.array_equal(gt, q.grad_theta(0)), b
         q.close()
     p.close()
+
+
+def test_kept_segments_give_the_checkpointed_gradients_bitwise(oracle_grads):
+    """Segments kept whole by the record hold exactly the fields the
+    backward would recompute: with M = 3 (segments of 3, 3 and 2 steps)
+    keeping 1, 2 or all 3 of them (two banks and one kept region; one bank
+    and two; none and three), and for a 5-step record in the same context
+    (two segments, both kept when K >= 2), the gradients equal those of
+    plain checkpointing bit for bit."""
+    insts = _beams()[:2]
+    data = oracle_grads[:2]
+
+    def grads(kept, steps):
+        p = _prop(insts, 32, max_steps=STEPS, ckpt_every=3, stored_segments=kept)
+        p.gen_screens()
+        for b, inst in enumerate(insts):
+            p.set_field(b, data[b][0])
+            p.set_theta(b, inst.theta)
+        p.forward_record(steps)
+        for b in range(len(insts)):
+            p.fluence_loss(b, data[b][1])
+        p.backward()
+        out = [(p.grad_field(b), p.grad_theta(b)) for b in range(len(insts))]
+        p.close()
+        return out
+
+    for steps in (STEPS, 5):
+        ref = grads(0, steps)
+        for kept in (1, 2, 3, 7):
+            got = grads(kept, steps)
+            for b in range(len(insts)):
+                assert np.array_equal(got[b][0], ref[b][0]), (steps, kept, b)
+                assert np.array_equal(got[b][1], ref[b][1]), (steps, kept, b)
+        _report(f"kept segments, {steps}-step record", beams=len(insts))
 
 
 def test_unseeded_beam_gets_zero_gradient(oracle_grads):

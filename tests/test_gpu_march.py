@@ -315,22 +315,25 @@ def test_every_tile_variant_matches_oracle(n):
     """Each compiled row and column variant (points per thread, lines per
     workgroup, radix plan, late twiddles, occupancy target) computes the same
     march: FP64 kernels against the oracle to rounding, 3 steps with every
-    screen term.  A variant whose tile does not fit a workgroup in FP64 (not
-    built for it) is checked in FP32 against the oracle to the FP32
-    tolerance of the all-terms march (2e-5)."""
+    screen term and two turbulence screens (z_s/dz = 0.55, 1.65: after steps 0 and
+    1).  A variant whose tile does not fit a workgroup in FP64 (not built for
+    it) is checked in FP32 against the oracle to the FP32 tolerance of the
+    all-terms march (2e-5)."""
     from paper_2306_15678_amd._lib import EUNSUPPORTED, SsfmError
     from paper_2306_15678_amd.march import plan_variants
-    terms = W.KPM | W.TERM_ANSATZ
+    terms = W.KPM | W.TERM_ANSATZ | W.TERM_TURB
     theta = tuple(np.array(W.THETA0) + W.random_theta(n + 1, 0.2))
-    inst = _strong(n, terms, theta=theta, n_steps=3)
+    inst = _strong(n, terms, theta=theta, n_steps=3, cn2=3e-13, screen_dz=0.011, n_screens=2)
+    assert list(inst.screen_steps()) == [0, 1]
     u0 = W.initial_field(inst)
-    ref = M.march(u0, inst)
+    ref = M.march(u0, inst, screens=T.instance_screens(inst))
     n_row, n_col = plan_variants(n, 64)
     combos = [(r, 0) for r in range(n_row)] + [(0, c) for c in range(1, n_col)]
     props = {}
     for precision in (64, 32):
         props[precision] = _prop([inst], precision)
         props[precision].set_theta(0, theta)
+        props[precision].gen_screens()
     for r, c in combos:
         for precision, tol in ((64, 1e-11), (32, 2e-5)):
             p = props[precision]
