@@ -91,9 +91,12 @@ class Propagator:
 
     # ------------------------------------------------------------ lifecycle
     def close(self) -> None:
+        """Destroy the context and release its workspace (also while other
+        references to this object remain)."""
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             L.lib().ssfm_destroy(self.ctx)
             self.ctx = None
+        self.workspace = None
 
     def __del__(self):
         try:
