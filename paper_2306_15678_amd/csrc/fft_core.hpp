@@ -276,7 +276,9 @@ struct Radices {};
 // in the adjoint row pass, the stored field and the screen phases after
 // the inverse FFT); bits 4-7 set the points per batch of the adjoint
 // screen (0: 4); bits 8-11 give the wavefronts per SIMD the compiler must
-// leave room for in the complex64 kernels (0: no target).
+// leave room for in the complex64 kernels (0: no target); bit 12 makes the
+// forward and adjoint row passes persistent and pipelined (complex64 only:
+// each workgroup loads its next row while it transforms the current one).
 template <int N_, int T_, int LINES_, class Rad, int PA_ = 32, int PB_ = 0, int OPT_ = 0>
 struct Plan {
   static constexpr int N = N_;
@@ -290,6 +292,7 @@ struct Plan {
   static constexpr bool LATE_PROP = (OPT_ & 2) != 0;
   static constexpr int ADJ_BATCH = ((OPT_ >> 4) & 15) ? ((OPT_ >> 4) & 15) : 4;
   static constexpr int WAVES_PER_EU = ((OPT_ >> 8) & 15) ? ((OPT_ >> 8) & 15) : 1;
+  static constexpr bool PIPE = (OPT_ & 0x1000) != 0;
   using radices = Rad;
   static_assert(N_ % T_ == 0, "T must divide N");
 };
@@ -456,6 +459,112 @@ template <typename R, class P, int DIR, class Lds>
 __device__ __forceinline__ void fft_line(cx<R>* v, int t, const Lds& lds, const cx<R>* w,
                                          const cx<R>* __restrict__ tw) {
   fft_line_impl<R, P::N, P::T, DIR, P::LATE_TW>(v, t, lds, w, tw, typename P::radices{});
+}
+
+// ------------------------------------------- twiddles staged in LDS
+// Persistent kernels copy the twiddles of every stage with span NS > 1 into
+// LDS once, in the order the stage reads them: entry (r - 1) NS + k of the
+// stage's block holds tw[r k N/(NS R)] for butterflies with j mod NS = k.
+// Stage blocks follow each other; the block of span NS starts at NS - R0
+// and they hold N - R0 entries together.  The lanes of a wave read
+// consecutive k (or one broadcast value), so the reads are free of bank
+// conflicts, and the values are those of the table.
+template <int N, int R0, int... Rest>
+constexpr int lds_tw_entries(Radices<R0, Rest...>) {
+  return N - R0;
+}
+
+template <typename R, int N, int NS, int RAD, int... Rest>
+__device__ __forceinline__ cx<R> lds_tw_value(int idx, const cx<R>* __restrict__ tw) {
+  // idx counts from the start of this stage's block
+  if (NS > 1 && idx < (RAD - 1) * NS) {
+    const int r = idx / NS + 1, k = idx - (r - 1) * NS;
+    return tw[r * k * (N / (NS * RAD))];
+  }
+  if constexpr (sizeof...(Rest) > 0) {
+    return lds_tw_value<R, N, NS * RAD, Rest...>(NS > 1 ? idx - (RAD - 1) * NS : idx, tw);
+  } else {
+    return tw[0];
+  }
+}
+
+template <typename R, int N, int THREADS, int... Rs>
+__device__ __forceinline__ void fill_lds_twiddles(cx<R>* twl, int t, const cx<R>* __restrict__ tw,
+                                                  Radices<Rs...> rad) {
+  constexpr int M = lds_tw_entries<N>(rad);
+  for (int i = t; i < M; i += THREADS) twl[i] = lds_tw_value<R, N, 1, Rs...>(i, tw);
+}
+
+template <typename R, int N, int T, int RAD, int NS, int R0, int DIR, bool FIRST, bool LAST,
+          class Lds>
+__device__ __forceinline__ void fft_stage_ltw(cx<R>* v, int t, const Lds& lds,
+                                              const cx<R>* twl) {
+  constexpr int E = N / T;
+  constexpr int NB = E / RAD;
+  constexpr int STRIDE = N / RAD;
+  static_assert(E % RAD == 0, "radix must divide points per thread");
+  const cx<R>* ws = twl + (NS - R0);
+  cx<R> a[NB][RAD];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) {
+      if constexpr (FIRST) {
+        a[b][r] = v[b + r * NB];
+      } else {
+        a[b][r] = lds.get(t + T * b + r * STRIDE);
+      }
+    }
+  }
+  if constexpr (!FIRST) {
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = t + T * b;
+    const int k = j % NS;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        const cx<R> ww = ws[(r - 1) * NS + k];
+        a[b][r] = (DIR > 0) ? cmulc(a[b][r], ww) : cmul(a[b][r], ww);
+      }
+    }
+    dft<RAD, DIR>(a[b]);
+    if constexpr (!LAST) {
+      const int base = (j / NS) * NS * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) lds.put(base + r * NS, a[b][r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[b + r * NB] = a[b][r];
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+  }
+}
+
+template <typename R, int N, int T, int DIR, int NS, int R0, bool FIRST, class Lds, int RA,
+          int... Rest>
+__device__ __forceinline__ void fft_stages_ltw(cx<R>* v, int t, const Lds& lds,
+                                               const cx<R>* twl) {
+  constexpr bool LAST = sizeof...(Rest) == 0;
+  fft_stage_ltw<R, N, T, RA, NS, R0, DIR, FIRST, LAST>(v, t, lds, twl);
+  if constexpr (!LAST) fft_stages_ltw<R, N, T, DIR, NS * RA, R0, false, Lds, Rest...>(v, t, lds, twl);
+}
+
+template <typename R, int N, int T, int DIR, class Lds, int R0, int... Rest>
+__device__ __forceinline__ void fft_line_ltw_impl(cx<R>* v, int t, const Lds& lds,
+                                                  const cx<R>* twl, Radices<R0, Rest...>) {
+  fft_stages_ltw<R, N, T, DIR, 1, R0, true, Lds, R0, Rest...>(v, t, lds, twl);
+}
+
+// fft_line with the twiddles read from the LDS copy made by
+// fill_lds_twiddles; same values and operation order as fft_line.
+template <typename R, class P, int DIR, class Lds>
+__device__ __forceinline__ void fft_line_ltw(cx<R>* v, int t, const Lds& lds, const cx<R>* twl) {
+  fft_line_ltw_impl<R, P::N, P::T, DIR>(v, t, lds, twl, typename P::radices{});
 }
 
 }  // namespace ssfm

@@ -28,15 +28,15 @@ int plan_count(bool column, int n) {
   return c;
 }
 
-// false when the plan's tile does not fit a workgroup's LDS at this
-// precision (the plan is then not built for it)
+// false when the plan is not built at this precision (its tile does not
+// fit a workgroup's LDS, or a pipelined plan at complex128)
 template <class P, bool COLUMN>
 static bool fill_info(bool fp64, PlanInfo* o) {
   o->threads = P::THREADS;
   o->lines = P::LINES;
   o->t = P::T;
   o->lds = fp64 ? plan_lds_bytes<double, P>(COLUMN) : plan_lds_bytes<float, P>(COLUMN);
-  return o->lds <= kMaxLdsBytes;
+  return fp64 ? plan_fits<double, P>(COLUMN) : plan_fits<float, P>(COLUMN);
 }
 
 bool plan_info(bool column, int n, int v, bool fp64, PlanInfo* o) {

@@ -59,6 +59,9 @@ struct PassArgs {
   int32_t pair;               // COL_INV: screen pair index
   int32_t flags;              // COL_FWD: bit 0 = power partials without the screen's A^2;
                               // ROW_FD: FD_* bits
+  int32_t n_work;             // entries of the work list (persistent passes; set at launch)
+  int32_t precise;            // library sine/cosine in the screens: the pipelined row
+                              // passes (which carry none) are replaced by k_row
 };
 
 struct PlanInfo {

@@ -21,6 +21,8 @@
 // 8 B read + 8 B written per point per pass (complex64).
 #pragma once
 
+#include <algorithm>
+
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -66,6 +68,45 @@ __device__ __forceinline__ const R* find_plane(const R* screens, const int64_t* 
       hi = mid;
   }
   if (st[lo] != step) return nullptr;
+  return screens + in.screen_off + int64_t(lo) * in.n * in.n;
+}
+
+// Uniform reads of the tables no kernel writes (work list, beam table,
+// screen step lists) through the constant address space: scalar loads,
+// counted apart from the vector loads, so waiting for them never waits for
+// the field loads in flight.
+template <typename T>
+using const_as4 = const __attribute__((address_space(4))) T;
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole dwords");
+  T out;
+  const_as4<uint32_t>* src =
+      reinterpret_cast<const_as4<uint32_t>*>(reinterpret_cast<uintptr_t>(p));
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+  for (int i = 0; i < int(sizeof(T) / 4); ++i) dst[i] = src[i];
+  return out;
+}
+
+// find_plane with the step list read through scalar loads.
+template <typename R>
+__device__ __forceinline__ const R* find_plane_uniform(const R* screens, const int64_t* steps,
+                                                       const InstDev& in, int64_t step) {
+  if (step < 0 || !(in.terms & T_TURB) || in.n_screens <= 0 || screens == nullptr)
+    return nullptr;
+  step -= in.step_base;
+  const int64_t* st = steps + in.steps_off;
+  int lo = 0, hi = in.n_screens - 1;
+  if (step < load_uniform(st + lo) || step > load_uniform(st + hi)) return nullptr;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (load_uniform(st + mid) < step)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  if (load_uniform(st + lo) != step) return nullptr;
   return screens + in.screen_off + int64_t(lo) * in.n * in.n;
 }
 
@@ -282,6 +323,164 @@ __global__ void __launch_bounds__(P::THREADS)
   for (int e = 0; e < E; ++e) dst[toff + uint32_t(T * e)] = v[e];
 }
 
+// ------------------------------------------------- pipelined row pass
+// Forward and adjoint row passes of a pipelined plan.  The grid holds as
+// many workgroups as are resident at once (a multiple of 8, so that every
+// item a workgroup takes runs on its own XCD); workgroup g takes items g,
+// g + gridDim.x, ... of the work list.  While it transforms one row, the
+// field loads of its next row are in flight, so the memory latency of a
+// row overlaps the arithmetic of the previous one.  The twiddles are copied
+// into LDS once per workgroup (stage by stage in the order they are read)
+// and the propagator is held in registers, reloaded only when the beam
+// changes.  The next row's loads are issued on every iteration (after the
+// last row, every lane reads that row's first point): loads issued on one
+// path only would make the compiler wait for every load in flight before
+// the transform.  The forward pass loads a row's turbulence phases when
+// its iteration starts, ahead of the next row's field; the adjoint pass
+// loads the stored pre-screen field and the phases after its inverse
+// transform, when they are needed.  These kernels carry no library sine and
+// cosine: with precise math on, the passes run k_row.  Per row the
+// arithmetic and its order are those of k_row with the same radices and
+// threads (screens run over batches of points, point by point in the same
+// order); the two kernels agree to rounding (the compiler may fuse a
+// multiply and an add in one and not the other).
+template <typename R, class P, int KIND>
+__global__ void __launch_bounds__(P::THREADS)
+    __attribute__((amdgpu_waves_per_eu(P::WAVES_PER_EU))) k_row_pipe(PassArgs<R> a) {
+  static_assert(KIND == ROW_FWD || KIND == ROW_ADJ, "pipelined row pass: forward or adjoint");
+  static_assert(P::LINES == 1, "one row per item");
+  constexpr int N = P::N, T = P::T, E = P::E;
+  constexpr bool ADJ = KIND == ROW_ADJ;
+  constexpr int SB = (E % 4 == 0) ? 4 : E;  // forward screen batch
+  using L = LdsLineMajor<R, N>;
+  __shared__ cx<R> lds_mem[L::LINE];
+  __shared__ cx<R> twl[lds_tw_entries<N>(typename P::radices{})];
+  __shared__ double red[((P::THREADS + 63) / 64) * 8];
+  const L lds{lds_mem};
+  const int t0 = threadIdx.x;
+  const int nb = a.n_work, G = gridDim.x;
+  auto next_item = [&](int i) {
+    while (i < nb && load_uniform(a.work + i).inst < 0) i += G;
+    return i;
+  };
+  int it = next_item(int(blockIdx.x));
+  if (it >= nb) return;
+
+  const cx<R>* tables = static_cast<const cx<R>*>(a.tables);
+  const cx<R>* __restrict__ src = static_cast<const cx<R>*>(a.src);
+  const cx<R>* __restrict__ aux = static_cast<const cx<R>*>(a.aux);
+  cx<R>* __restrict__ dst = static_cast<cx<R>*>(a.dst);
+
+  WorkItem w = load_uniform(a.work + it);
+  int64_t base = load_uniform(&a.inst[w.inst].off) + int64_t(w.line0) * N;
+  cx<R> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = src[base + uint32_t(t0 + T * e)];
+  int64_t prop_off = load_uniform(&a.inst[w.inst].prop_off);
+  int64_t tw_off = load_uniform(&a.inst[w.inst].tw_off);
+  cx<R> pr[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) pr[e] = tables[prop_off + t0 + T * e];
+  fill_lds_twiddles<R, N, P::THREADS>(twl, t0, tables + tw_off, typename P::radices{});
+
+  for (;;) {
+    // the thread index laundered per iteration: addresses derived from it
+    // are recomputed in the loop instead of held in registers across it
+    int t = t0;
+    asm volatile("" : "+v"(t));
+    const InstDev in = load_uniform(a.inst + w.inst);
+    ScreenConst<R> sc = screen_const<R>(in);
+    sc.terms &= ~unsigned(T_PRECISE);
+    const R* plane = find_plane_uniform(a.screens, a.screen_steps, in, a.step);
+    // this row's turbulence phases and (adjoint) stored pre-screen field,
+    // ahead of the next row's field
+    R ph[E];
+    if (plane) {
+      const R* pw = plane + int64_t(w.line0) * N;
+#pragma unroll
+      for (int e = 0; e < E; ++e) ph[e] = pw[uint32_t(t + T * e)];
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) ph[e] = R(0);
+    }
+    cx<R> sv[ADJ ? E : 1];
+    if constexpr (ADJ) {
+      if (a.step >= 0) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) sv[e] = aux[base + uint32_t(t + T * e)];
+      }
+    }
+    // the next row's field
+    const int nit = next_item(it + G);
+    const bool more = nit < nb;
+    const WorkItem wn = more ? load_uniform(a.work + nit) : w;
+    const int64_t base_n =
+        more ? load_uniform(&a.inst[wn.inst].off) + int64_t(wn.line0) * N : base;
+    const uint32_t live = more ? 0xffffffffu : 0u;
+    cx<R> vn[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) vn[e] = src[base_n + (uint32_t(t + T * e) & live)];
+
+    if constexpr (!ADJ) {
+      if (a.step >= 0) {
+#pragma unroll
+        for (int c = 0; c < E; c += SB) screen_apply_n<R, SB>(sc, v + c, ph + c);
+      }
+    }
+    // every wave has read the previous row out of LDS (and the twiddles
+    // are in place)
+    __syncthreads();
+    fft_line_ltw<R, P, -1>(v, t, lds, twl);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = ADJ ? cmulc(v[e], pr[e]) : cmul(v[e], pr[e]);
+    fft_line_ltw<R, P, +1>(v, t, lds, twl);
+    if constexpr (ADJ) {
+      if (a.step >= 0) {
+        double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        constexpr int AC = (E % P::ADJ_BATCH == 0) ? P::ADJ_BATCH : E;
+#pragma unroll
+        for (int c = 0; c < E; c += AC) {
+          screen_adjoint_n<R, AC, true>(sc, sv + c, v + c, ph + c, plane != nullptr, g);
+          // one batch at a time: the scheduler does not interleave batches
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (in.terms & T_ANSATZ) {
+          // the scratch's address from a laundered zero, so its per-wave
+          // slot addresses are not held in registers across the loop
+          int z = 0;
+          asm volatile("" : "+v"(z));
+          block_reduce<8, P::THREADS, false>(g, red + z);
+          if (threadIdx.x == 0) {
+            double* acc = a.part + int64_t(w.widx) * 8;
+#pragma unroll
+            for (int p = 0; p < 8; ++p) acc[p] += g[p];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[base + uint32_t(t + T * e)] = v[e];
+    if (!more) break;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = vn[e];
+    w = wn;
+    base = base_n;
+    it = nit;
+    const int64_t po = load_uniform(&a.inst[w.inst].prop_off);
+    if (po != prop_off) {
+      prop_off = po;
+#pragma unroll
+      for (int e = 0; e < E; ++e) pr[e] = tables[prop_off + t + T * e];
+    }
+    const int64_t to = load_uniform(&a.inst[w.inst].tw_off);
+    if (to != tw_off) {
+      tw_off = to;
+      __syncthreads();
+      fill_lds_twiddles<R, N, P::THREADS>(twl, t, tables + tw_off, typename P::radices{});
+    }
+  }
+}
+
 // --------------------------------------------------------- column pass
 template <typename R, class P, int KIND>
 __global__ void __launch_bounds__(P::THREADS)
@@ -400,10 +599,49 @@ __global__ void __launch_bounds__(P::THREADS)
 // With ev, the launch carries start/stop events on its own dispatch (timing
 // of the kernel alone, no separate marker packets).  A plan whose LDS tile
 // does not fit a workgroup at this precision is not built for it.
+// Workgroups of a persistent launch: as many as are resident at once (the
+// runtime's occupancy for the kernel times the compute units), rounded down
+// to a multiple of 8, and no more than the items.
+inline int resident_grid(int per_cu, int items) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 1;
+  const int g = std::max(8, per_cu * cus / 8 * 8);
+  return std::min(g, items);
+}
+
 template <typename R, class P, int KIND>
 hipError_t launch_one(int n_blocks, const PassArgs<R>& a, hipStream_t s, const LaunchEv* ev) {
   if constexpr (!plan_fits<R, P>(is_col_kind(KIND))) {
     return hipErrorInvalidValue;
+  } else if constexpr (P::PIPE && (KIND == ROW_FWD || KIND == ROW_ADJ)) {
+    if (a.precise) {
+      if (ev)
+        hipExtLaunchKernelGGL((k_row<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s,
+                              ev->start, ev->stop, 0, a);
+      else
+        hipLaunchKernelGGL((k_row<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s, a);
+      return hipGetLastError();
+    }
+    static const int per_cu = [] {
+      int b = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &b, reinterpret_cast<const void*>(k_row_pipe<R, P, KIND>), P::THREADS, 0) !=
+              hipSuccess ||
+          b < 1)
+        b = 1;
+      return b;
+    }();
+    PassArgs<R> b = a;
+    b.n_work = n_blocks;
+    const int grid = resident_grid(per_cu, n_blocks);
+    if (ev)
+      hipExtLaunchKernelGGL((k_row_pipe<R, P, KIND>), dim3(grid), dim3(P::THREADS), 0, s,
+                            ev->start, ev->stop, 0, b);
+    else
+      hipLaunchKernelGGL((k_row_pipe<R, P, KIND>), dim3(grid), dim3(P::THREADS), 0, s, b);
   } else if constexpr (is_col_kind(KIND)) {
     if (ev)
       hipExtLaunchKernelGGL((k_col<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s,

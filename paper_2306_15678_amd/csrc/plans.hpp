@@ -2,7 +2,8 @@
 //
 // Rows: X(N, variant, T, LINES, OPT, radices...); columns: X(N, variant,
 // T, W, A, B, OPT, radices...).  OPT: 1 = late twiddles, plus 0x100 times the
-// wavefronts per SIMD the compiler must leave room for (see Plan).  T
+// wavefronts per SIMD the compiler must leave room for, 0x1000 = persistent
+// pipelined forward and adjoint row passes (complex64; see Plan).  T
 // threads per line, LINES lines per workgroup (rows:
 // LINES consecutive rows; columns: W adjacent columns, read as
 // W * sizeof(complex) contiguous bytes per row), radix plan in stage order.
@@ -37,12 +38,15 @@ namespace ssfm {
   X(1024, 6, 32, 2, 0, 32, 32)            \
   X(2048, 0, 128, 2, 0, 16, 16, 8)        \
   X(2048, 1, 256, 1, 0, 8, 8, 8, 4)       \
+  X(2048, 2, 256, 1, 0x1000, 8, 8, 8, 4)  \
   X(4096, 0, 256, 1, 0, 16, 16, 16)       \
   X(4096, 1, 512, 1, 0, 8, 8, 8, 8)       \
   X(4096, 2, 256, 1, 0x201, 16, 16, 16)   \
   X(4096, 3, 256, 1, 0x203, 16, 16, 16)   \
   X(4096, 4, 256, 1, 0x323, 16, 16, 16)   \
-  X(4096, 5, 256, 1, 0x303, 16, 16, 16)
+  X(4096, 5, 256, 1, 0x303, 16, 16, 16)   \
+  X(4096, 6, 512, 1, 0x1000, 8, 8, 8, 8)  \
+  X(4096, 7, 512, 1, 0x1010, 8, 8, 8, 8)
 
 #define SSFM_COL_PLANS(X)              \
   X(128, 0, 8, 32, 1, 0, 0, 16, 8) \
@@ -77,9 +81,11 @@ constexpr size_t plan_lds_bytes(bool column) {
                              : size_t(P::LINES) * LdsLineMajor<R, P::N>::LINE;
   return tile * sizeof(cx<R>) + sizeof(double) * 8 * ((P::THREADS + 63) / 64);
 }
+// Pipelined (persistent) plans are built for complex64 rows only.
 template <typename R, class P>
 constexpr bool plan_fits(bool column) {
-  return plan_lds_bytes<R, P>(column) <= kMaxLdsBytes;
+  return plan_lds_bytes<R, P>(column) <= kMaxLdsBytes &&
+         !(P::PIPE && (column || sizeof(R) != 4 || P::LINES != 1));
 }
 
 template <int N, int V>

@@ -353,7 +353,9 @@ __device__ __forceinline__ void screen_apply_n(const ScreenConst<R>& s, cx<R>* u
 // cotangents of the screened values and is overwritten with those of V;
 // the ansatz gradient terms are added to gth[8] point by point in order.
 // has_plane: a turbulence plane phi_t is applied at this step.
-template <typename R, int C>
+// SERIAL: a scheduling barrier after each point's gradient terms, so the
+// FP64 products of later points are not computed ahead and held.
+template <typename R, int C, bool SERIAL = false>
 __device__ __forceinline__ void screen_adjoint_n(const ScreenConst<R>& s, const cx<R>* v,
                                                  cx<R>* lam, const R* phi_t, bool has_plane,
                                                  double* gth) {
@@ -455,6 +457,7 @@ __device__ __forceinline__ void screen_adjoint_n(const ScreenConst<R>& s, const 
       }
     }
     lam[e] = t1 + t2;
+    if constexpr (SERIAL) __builtin_amdgcn_sched_barrier(0);
   }
 }
 

@@ -517,6 +517,8 @@ PassArgs<R> base_args(ssfm_ctx* c) {
   a.screens = c->at<R>(c->L.screens);
   a.screen_steps = c->at<int64_t>(c->L.steps);
   a.step = -1;
+  for (const auto& in : c->inst)
+    if (in.terms & (1u << 8)) a.precise = 1;
   return a;
 }
 
@@ -2021,6 +2023,8 @@ int ssfm_set_precise_math(ssfm_ctx* c, int32_t enable) {
   HIP_TRY(hipMemcpyAsync(c->ws + c->L.inst, c->inst.data(), sizeof(InstDev) * c->inst.size(),
                          hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  // captured steps hold the kernels chosen for the previous setting
+  clear_graphs(c);
   return SSFM_OK;
 }
 

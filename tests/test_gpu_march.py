@@ -351,6 +351,123 @@ def test_every_tile_variant_matches_oracle(n):
                 break
 
 
+# ------------------------------------------- adjoint row-pass variants
+# Every row variant of the large grids (the persistent pipelined ones
+# included: complex64 only) as the forward and the adjoint row pass of a
+# recorded march with every screen term, the ansatz and two turbulence
+# screens (after steps 0 and 1), 3 steps, fluence loss, backward.
+def _adjoint_variant_case(n):
+    terms = W.KPM | W.TERM_ANSATZ | W.TERM_TURB
+    theta = tuple(np.array(W.THETA0) + W.random_theta(n + 3, 0.2))
+    inst = _strong(n, terms, theta=theta, n_steps=3, cn2=3e-13, screen_dz=0.011, n_screens=2)
+    assert list(inst.screen_steps()) == [0, 1]
+    return inst, W.initial_field(inst), W.synthetic_target(inst, 5)
+
+
+def _fwd_adj(p, inst, u0, target):
+    p.set_field(0, u0)
+    p.set_theta(0, inst.theta)
+    p.forward_record(inst.n_steps)
+    loss = p.fluence_loss(0, target)
+    p.backward()
+    return loss, p.grad_field(0), p.grad_theta(0)
+
+
+@pytest.fixture(scope="module")
+def adj2048_oracle():
+    inst, u0, target = _adjoint_variant_case(2048)
+    screens = T.instance_screens(inst)
+    return (inst, u0, target), M.gradient(u0, inst, screens=screens,
+                                          cotangent=lambda u: M.fluence_loss(u, target))
+
+
+def test_every_row_variant_adjoint_2048_matches_oracle(adj2048_oracle):
+    """FP32 forward + adjoint with each row variant used for both row passes
+    (column variant 0), against the FP64 oracle gradient: loss, gradient of
+    U0 and of theta to the FP32 gradient tolerance (1e-4, as for the 256^2
+    gradient case), the field gradient also pointwise."""
+    from paper_2306_15678_amd.march import plan_variants
+    (inst, u0, target), (loss_o, g_u0, g_th) = adj2048_oracle
+    n_row, _ = plan_variants(2048, 32)
+    p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=2)
+    p.gen_screens()
+    for r in range(n_row):
+        p.select_plan(2048, r, 0)
+        p.select_adjoint_plan(2048, r, -1)
+        loss, gg, gt = _fwd_adj(p, inst, u0, target)
+        lerr = abs(loss / loss_o - 1)
+        ferr = M.rel_l2(gg, g_u0)
+        fmax = _maxrel(gg, g_u0)
+        terr = float(np.max(np.abs(gt - g_th)) / np.max(np.abs(g_th)))
+        _report(f"adjoint row variant n=2048 r={r}", loss=lerr, g_u0=ferr, g_u0_max=fmax,
+                g_theta=terr)
+        assert lerr < 1e-4 and ferr < 1e-4 and terr < 1e-4, r
+        assert fmax < MAX_OVER_L2 * 1e-4, r
+
+
+def test_every_row_variant_adjoint_4096_agrees():
+    """At 4096^2 (FP64 oracle too slow for every variant): each row variant's
+    FP32 forward + adjoint against row variant 0's, to a few FP32 roundings
+    of the 3-step march (the radix plans round differently); the pipelined
+    variants also against the plain kernel of the same radices and threads
+    (same arithmetic per point; the compiler may fuse a multiply and an add
+    differently in the two kernels, so they agree to rounding, not bitwise)."""
+    from paper_2306_15678_amd.march import plan_variants
+    inst, u0, target = _adjoint_variant_case(4096)
+    n_row, _ = plan_variants(4096, 32)
+    p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=2)
+    p.gen_screens()
+    res = {}
+    for r in range(n_row):
+        p.select_plan(4096, r, 0)
+        p.select_adjoint_plan(4096, r, -1)
+        res[r] = _fwd_adj(p, inst, u0, target)
+    l0, g0, t0 = res[0]
+    for r in range(1, n_row):
+        loss, gg, gt = res[r]
+        lerr = abs(loss / l0 - 1)
+        ferr = M.rel_l2(gg, g0)
+        terr = float(np.max(np.abs(gt - t0)) / np.max(np.abs(t0)))
+        _report(f"adjoint row variant n=4096 r={r} vs r=0", loss=lerr, g_u0=ferr, g_theta=terr)
+        assert lerr < 1e-5 and ferr < 1e-5 and terr < 1e-5, r
+    # pipelined (6, 7) against the plain kernel with 512 threads and radices
+    # 8, 8, 8, 8 (1)
+    for r in (6, 7):
+        loss, gg, gt = res[r]
+        ferr = M.rel_l2(gg, res[1][1])
+        terr = float(np.max(np.abs(gt - res[1][2])) / np.max(np.abs(res[1][2])))
+        _report(f"pipelined row variant {r} vs plain 1", g_u0=ferr, g_theta=terr,
+                bitwise=bool(np.array_equal(gg, res[1][1])))
+        assert ferr < 1e-5 and terr < 1e-5, r
+
+
+def test_pipelined_rows_batch_equals_each_beam_alone():
+    """Two 2048^2 beams with different z steps (so different propagators) in
+    one context: a persistent row workgroup takes rows of both beams in turn
+    and reloads the propagator when the beam changes.  Forward + adjoint of
+    each beam equals that beam in a context of its own, bitwise."""
+    base, u0, target = _adjoint_variant_case(2048)
+    other = dataclasses.replace(base, dz=0.007, seed=base.seed + 1)
+    u1 = W.initial_field(other)
+    pair = _prop([base, other], 32, max_steps=3, ckpt_every=2)
+    pair.gen_screens()
+    pair.select_plan(2048, 2, 0)
+    for b, (inst, u) in enumerate(((base, u0), (other, u1))):
+        pair.set_field(b, u)
+        pair.set_theta(b, inst.theta)
+    pair.forward_record(3)
+    pair.fluence_loss(0, target)
+    pair.fluence_loss(1, target)
+    pair.backward()
+    for b, (inst, u) in enumerate(((base, u0), (other, u1))):
+        one = _prop([inst], 32, max_steps=3, ckpt_every=2)
+        one.gen_screens()
+        one.select_plan(2048, 2, 0)
+        _fwd_adj(one, inst, u, target)
+        assert np.array_equal(pair.grad_field(b), one.grad_field(0)), b
+        assert np.array_equal(pair.grad_theta(b), one.grad_theta(0)), b
+
+
 # ---------------------------------------------------------- config 3
 # 64 uneven beams (n in {256, 512, 768, 1024}) with 20 Kolmogorov screens
 # each, marched together in one context.  Checked on one beam of each size
