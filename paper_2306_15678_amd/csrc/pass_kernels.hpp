@@ -595,6 +595,136 @@ __global__ void __launch_bounds__(P::THREADS)
   }
 }
 
+// ---------------------------------------------- pipelined column pass
+// Forward and adjoint column passes of a pipelined plan, organised like
+// k_row_pipe: a resident grid, workgroup g taking column tiles g,
+// g + gridDim.x, ... (a multiple of 8: an XCD's workgroups hold adjacent
+// tiles at any time, so the rows of neighbouring tiles meet in its L2),
+// the next tile's field loads in flight while the current tile is
+// transformed, the twiddles in LDS and the propagator in registers.
+template <typename R, class P, int KIND>
+__global__ void __launch_bounds__(P::THREADS)
+    __attribute__((amdgpu_waves_per_eu(P::WAVES_PER_EU))) k_col_pipe(PassArgs<R> a) {
+  static_assert(KIND == COL_FWD || KIND == COL_ADJ, "pipelined column pass: forward or adjoint");
+  constexpr int N = P::N, T = P::T, E = P::E, W = P::LINES;
+  constexpr bool ADJ = KIND == COL_ADJ;
+  constexpr int SB = (E % 4 == 0) ? 4 : E;  // power-partial batch
+  constexpr uint32_t ESTRIDE = uint32_t(T) * N;
+  using L = LdsPointMajor<R, W, P::PA, P::PB>;
+  __shared__ cx<R> lds_mem[L::size(N)];
+  __shared__ cx<R> twl[lds_tw_entries<N>(typename P::radices{})];
+  __shared__ double red[((P::THREADS + 63) / 64) * 2];
+  const int nb = a.n_work, G = gridDim.x;
+  auto next_item = [&](int i) {
+    while (i < nb && load_uniform(a.work + i).inst < 0) i += G;
+    return i;
+  };
+  int it = next_item(int(blockIdx.x));
+  if (it >= nb) return;
+
+  const cx<R>* tables = static_cast<const cx<R>*>(a.tables);
+  const cx<R>* __restrict__ src = static_cast<const cx<R>*>(a.src);
+  cx<R>* __restrict__ dst = static_cast<cx<R>*>(a.dst);
+  const int c0 = threadIdx.x % W, t0 = threadIdx.x / W;
+  const uint32_t toff0 = uint32_t(t0) * N + uint32_t(c0);
+
+  WorkItem w = load_uniform(a.work + it);
+  int64_t base = load_uniform(&a.inst[w.inst].off) + w.line0;
+  cx<R> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = src[base + toff0 + ESTRIDE * e];
+  int64_t prop_off = load_uniform(&a.inst[w.inst].prop_off);
+  int64_t tw_off = load_uniform(&a.inst[w.inst].tw_off);
+  cx<R> pr[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) pr[e] = tables[prop_off + t0 + T * e];
+  fill_lds_twiddles<R, N, P::THREADS>(twl, int(threadIdx.x), tables + tw_off,
+                                      typename P::radices{});
+
+  for (;;) {
+    // thread coordinates laundered per iteration (addresses recomputed in
+    // the loop instead of held across it)
+    int c = c0, t = t0;
+    asm volatile("" : "+v"(c), "+v"(t));
+    const uint32_t toff = uint32_t(t) * N + uint32_t(c);
+    const L lds{lds_mem + c};
+    // the next tile's field
+    const int nit = next_item(it + G);
+    const bool more = nit < nb;
+    const WorkItem wn = more ? load_uniform(a.work + nit) : w;
+    const int64_t base_n = more ? load_uniform(&a.inst[wn.inst].off) + wn.line0 : base;
+    const uint32_t live = more ? 0xffffffffu : 0u;
+    cx<R> vn[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) vn[e] = src[base_n + ((toff + ESTRIDE * e) & live)];
+
+    // every wave has read the previous tile out of LDS (and the twiddles
+    // are in place)
+    __syncthreads();
+    fft_line_ltw<R, P, -1>(v, t, lds, twl);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = ADJ ? cmulc(v[e], pr[e]) : cmul(v[e], pr[e]);
+    fft_line_ltw<R, P, +1>(v, t, lds, twl);
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[base + toff + ESTRIDE * e] = v[e];
+
+    if constexpr (!ADJ) {
+      if (a.part != nullptr) {
+        const InstDev in = load_uniform(a.inst + w.inst);
+        ScreenConst<R> sc = screen_const<R>(in);
+        double s[1] = {0.0}, m[1] = {0.0};
+#pragma unroll
+        for (int b = 0; b < E; b += SB) {
+          R x[SB], a2[SB];
+#pragma unroll
+          for (int e = 0; e < SB; ++e) x[e] = v[b + e].re * v[b + e].re + v[b + e].im * v[b + e].im;
+          if (a.flags & 1) {
+#pragma unroll
+            for (int e = 0; e < SB; ++e) a2[e] = R(1);
+          } else {
+            screen_amp2_n<R, SB>(sc, x, a2);
+          }
+#pragma unroll
+          for (int e = 0; e < SB; ++e) {
+            const double xa = double(x[e]) * double(a2[e]);
+            s[0] += xa;
+            m[0] = fmax(m[0], xa);
+          }
+        }
+        int z = 0;
+        asm volatile("" : "+v"(z));
+        double* rp = red + z;
+        block_reduce<1, P::THREADS, false>(s, rp);
+        __syncthreads();
+        block_reduce<1, P::THREADS, true>(m, rp + ((P::THREADS + 63) / 64));
+        if (threadIdx.x == 0) {
+          a.part[int64_t(w.widx) * 2 + 0] = s[0];
+          a.part[int64_t(w.widx) * 2 + 1] = m[0];
+        }
+      }
+    }
+    if (!more) break;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = vn[e];
+    w = wn;
+    base = base_n;
+    it = nit;
+    const int64_t po = load_uniform(&a.inst[w.inst].prop_off);
+    if (po != prop_off) {
+      prop_off = po;
+#pragma unroll
+      for (int e = 0; e < E; ++e) pr[e] = tables[prop_off + t + T * e];
+    }
+    const int64_t to = load_uniform(&a.inst[w.inst].tw_off);
+    if (to != tw_off) {
+      tw_off = to;
+      __syncthreads();
+      fill_lds_twiddles<R, N, P::THREADS>(twl, int(threadIdx.x), tables + tw_off,
+                                          typename P::radices{});
+    }
+  }
+}
+
 // -------------------------------------------------------------- launch
 // With ev, the launch carries start/stop events on its own dispatch (timing
 // of the kernel alone, no separate marker packets).  A plan whose LDS tile
@@ -642,6 +772,24 @@ hipError_t launch_one(int n_blocks, const PassArgs<R>& a, hipStream_t s, const L
                             ev->start, ev->stop, 0, b);
     else
       hipLaunchKernelGGL((k_row_pipe<R, P, KIND>), dim3(grid), dim3(P::THREADS), 0, s, b);
+  } else if constexpr (P::PIPE && (KIND == COL_FWD || KIND == COL_ADJ)) {
+    static const int per_cu = [] {
+      int b = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &b, reinterpret_cast<const void*>(k_col_pipe<R, P, KIND>), P::THREADS, 0) !=
+              hipSuccess ||
+          b < 1)
+        b = 1;
+      return b;
+    }();
+    PassArgs<R> b = a;
+    b.n_work = n_blocks;
+    const int grid = resident_grid(per_cu, n_blocks);
+    if (ev)
+      hipExtLaunchKernelGGL((k_col_pipe<R, P, KIND>), dim3(grid), dim3(P::THREADS), 0, s,
+                            ev->start, ev->stop, 0, b);
+    else
+      hipLaunchKernelGGL((k_col_pipe<R, P, KIND>), dim3(grid), dim3(P::THREADS), 0, s, b);
   } else if constexpr (is_col_kind(KIND)) {
     if (ev)
       hipExtLaunchKernelGGL((k_col<R, P, KIND>), dim3(n_blocks), dim3(P::THREADS), 0, s,

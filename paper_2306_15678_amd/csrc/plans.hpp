@@ -65,27 +65,33 @@ namespace ssfm {
   X(1024, 5, 32, 8, 4, 1, 0, 32, 32) \
   X(2048, 0, 128, 2, 16, 2, 0, 16, 16, 8) \
   X(2048, 1, 256, 2, 16, 2, 0, 8, 8, 8, 4) \
+  X(2048, 2, 256, 2, 16, 2, 0x1000, 8, 8, 8, 4) \
   X(4096, 0, 256, 2, 16, 2, 0, 16, 16, 16) \
   X(4096, 1, 512, 2, 16, 2, 0, 8, 8, 8, 8) \
   X(4096, 2, 256, 2, 16, 2, 0x203, 16, 16, 16) \
   X(4096, 3, 256, 4, 16, 2, 0x403, 16, 16, 16) \
   X(4096, 4, 128, 2, 16, 2, 0x203, 16, 16, 16) \
-  X(4096, 5, 128, 4, 16, 2, 0x203, 16, 16, 16)
+  X(4096, 5, 128, 4, 16, 2, 0x203, 16, 16, 16) \
+  X(4096, 6, 512, 2, 16, 2, 0x1000, 8, 8, 8, 8) \
+  X(4096, 7, 256, 2, 16, 2, 0x1000, 16, 16, 16)
 
 // LDS of a pass workgroup (line tiles, plus the FP64 reduction scratch)
 // against the 160 KiB a gfx950 workgroup may allocate.
 constexpr size_t kMaxLdsBytes = 160 * 1024;
+// (pipelined plans also hold the twiddles of every stage, N - R0 entries)
 template <typename R, class P>
 constexpr size_t plan_lds_bytes(bool column) {
   const size_t tile = column ? size_t(LdsPointMajor<R, P::LINES, P::PA, P::PB>::size(P::N))
                              : size_t(P::LINES) * LdsLineMajor<R, P::N>::LINE;
-  return tile * sizeof(cx<R>) + sizeof(double) * 8 * ((P::THREADS + 63) / 64);
+  const size_t tw = P::PIPE ? size_t(lds_tw_entries<P::N>(typename P::radices{})) : 0;
+  return (tile + tw) * sizeof(cx<R>) + sizeof(double) * 8 * ((P::THREADS + 63) / 64);
 }
-// Pipelined (persistent) plans are built for complex64 rows only.
+// Pipelined (persistent) plans are built for complex64 only, rows with one
+// row per workgroup.
 template <typename R, class P>
 constexpr bool plan_fits(bool column) {
   return plan_lds_bytes<R, P>(column) <= kMaxLdsBytes &&
-         !(P::PIPE && (column || sizeof(R) != 4 || P::LINES != 1));
+         !(P::PIPE && (sizeof(R) != 4 || (!column && P::LINES != 1)));
 }
 
 template <int N, int V>

@@ -381,77 +381,81 @@ def adj2048_oracle():
                                           cotangent=lambda u: M.fluence_loss(u, target))
 
 
-def test_every_row_variant_adjoint_2048_matches_oracle(adj2048_oracle):
+def test_every_variant_adjoint_2048_matches_oracle(adj2048_oracle):
     """FP32 forward + adjoint with each row variant used for both row passes
-    (column variant 0), against the FP64 oracle gradient: loss, gradient of
-    U0 and of theta to the FP32 gradient tolerance (1e-4, as for the 256^2
+    (column variant 0), then each column variant for both column passes (row
+    variant 0), against the FP64 oracle gradient: loss, gradient of U0 and
+    of theta to the FP32 gradient tolerance (1e-4, as for the 256^2
     gradient case), the field gradient also pointwise."""
     from paper_2306_15678_amd.march import plan_variants
     (inst, u0, target), (loss_o, g_u0, g_th) = adj2048_oracle
-    n_row, _ = plan_variants(2048, 32)
+    n_row, n_col = plan_variants(2048, 32)
     p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=2)
     p.gen_screens()
-    for r in range(n_row):
-        p.select_plan(2048, r, 0)
-        p.select_adjoint_plan(2048, r, -1)
+    combos = [(r, 0) for r in range(n_row)] + [(0, c) for c in range(1, n_col)]
+    for r, c in combos:
+        p.select_plan(2048, r, c)
+        p.select_adjoint_plan(2048, -1, -1)
         loss, gg, gt = _fwd_adj(p, inst, u0, target)
         lerr = abs(loss / loss_o - 1)
         ferr = M.rel_l2(gg, g_u0)
         fmax = _maxrel(gg, g_u0)
         terr = float(np.max(np.abs(gt - g_th)) / np.max(np.abs(g_th)))
-        _report(f"adjoint row variant n=2048 r={r}", loss=lerr, g_u0=ferr, g_u0_max=fmax,
-                g_theta=terr)
-        assert lerr < 1e-4 and ferr < 1e-4 and terr < 1e-4, r
-        assert fmax < MAX_OVER_L2 * 1e-4, r
+        _report(f"adjoint variants n=2048 row={r} col={c}", loss=lerr, g_u0=ferr,
+                g_u0_max=fmax, g_theta=terr)
+        assert lerr < 1e-4 and ferr < 1e-4 and terr < 1e-4, (r, c)
+        assert fmax < MAX_OVER_L2 * 1e-4, (r, c)
 
 
-def test_every_row_variant_adjoint_4096_agrees():
+def test_every_variant_adjoint_4096_agrees():
     """At 4096^2 (FP64 oracle too slow for every variant): each row variant's
-    FP32 forward + adjoint against row variant 0's, to a few FP32 roundings
-    of the 3-step march (the radix plans round differently); the pipelined
-    variants also against the plain kernel of the same radices and threads
-    (same arithmetic per point; the compiler may fuse a multiply and an add
-    differently in the two kernels, so they agree to rounding, not bitwise)."""
+    and each column variant's FP32 forward + adjoint against variants
+    (0, 0), to a few FP32 roundings of the 3-step march (the radix plans
+    round differently); the pipelined variants also against the plain kernel
+    of the same radices and threads (same arithmetic per point; the compiler
+    may fuse a multiply and an add differently in the two kernels, so they
+    agree to rounding, not bitwise)."""
     from paper_2306_15678_amd.march import plan_variants
     inst, u0, target = _adjoint_variant_case(4096)
-    n_row, _ = plan_variants(4096, 32)
+    n_row, n_col = plan_variants(4096, 32)
     p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=2)
     p.gen_screens()
     res = {}
-    for r in range(n_row):
-        p.select_plan(4096, r, 0)
-        p.select_adjoint_plan(4096, r, -1)
-        res[r] = _fwd_adj(p, inst, u0, target)
-    l0, g0, t0 = res[0]
-    for r in range(1, n_row):
-        loss, gg, gt = res[r]
+    combos = [(r, 0) for r in range(n_row)] + [(0, c) for c in range(1, n_col)]
+    for r, c in combos:
+        p.select_plan(4096, r, c)
+        p.select_adjoint_plan(4096, -1, -1)
+        res[(r, c)] = _fwd_adj(p, inst, u0, target)
+    l0, g0, t0 = res[(0, 0)]
+    for key in combos[1:]:
+        loss, gg, gt = res[key]
         lerr = abs(loss / l0 - 1)
         ferr = M.rel_l2(gg, g0)
         terr = float(np.max(np.abs(gt - t0)) / np.max(np.abs(t0)))
-        _report(f"adjoint row variant n=4096 r={r} vs r=0", loss=lerr, g_u0=ferr, g_theta=terr)
-        assert lerr < 1e-5 and ferr < 1e-5 and terr < 1e-5, r
-    # pipelined (6, 7) against the plain kernel with 512 threads and radices
-    # 8, 8, 8, 8 (1)
-    for r in (6, 7):
-        loss, gg, gt = res[r]
-        ferr = M.rel_l2(gg, res[1][1])
-        terr = float(np.max(np.abs(gt - res[1][2])) / np.max(np.abs(res[1][2])))
-        _report(f"pipelined row variant {r} vs plain 1", g_u0=ferr, g_theta=terr,
-                bitwise=bool(np.array_equal(gg, res[1][1])))
-        assert ferr < 1e-5 and terr < 1e-5, r
+        _report(f"adjoint variants n=4096 {key} vs (0, 0)", loss=lerr, g_u0=ferr, g_theta=terr)
+        assert lerr < 1e-5 and ferr < 1e-5 and terr < 1e-5, key
+    # pipelined against the plain kernels of the same radices and threads:
+    # rows 6, 7 against row 1; column 6 against column 1, column 7 against 0
+    for key, ref in (((6, 0), (1, 0)), ((7, 0), (1, 0)), ((0, 6), (0, 1)), ((0, 7), (0, 0))):
+        loss, gg, gt = res[key]
+        ferr = M.rel_l2(gg, res[ref][1])
+        terr = float(np.max(np.abs(gt - res[ref][2])) / np.max(np.abs(res[ref][2])))
+        _report(f"pipelined variants {key} vs plain {ref}", g_u0=ferr, g_theta=terr,
+                bitwise=bool(np.array_equal(gg, res[ref][1])))
+        assert ferr < 1e-5 and terr < 1e-5, key
 
 
 def test_pipelined_rows_batch_equals_each_beam_alone():
     """Two 2048^2 beams with different z steps (so different propagators) in
-    one context: a persistent row workgroup takes rows of both beams in turn
-    and reloads the propagator when the beam changes.  Forward + adjoint of
+    one context: a persistent row or column workgroup takes lines of both
+    beams in turn and reloads the propagator when the beam changes.  Forward + adjoint of
     each beam equals that beam in a context of its own, bitwise."""
     base, u0, target = _adjoint_variant_case(2048)
     other = dataclasses.replace(base, dz=0.007, seed=base.seed + 1)
     u1 = W.initial_field(other)
     pair = _prop([base, other], 32, max_steps=3, ckpt_every=2)
     pair.gen_screens()
-    pair.select_plan(2048, 2, 0)
+    pair.select_plan(2048, 2, 2)
     for b, (inst, u) in enumerate(((base, u0), (other, u1))):
         pair.set_field(b, u)
         pair.set_theta(b, inst.theta)
@@ -462,7 +466,7 @@ def test_pipelined_rows_batch_equals_each_beam_alone():
     for b, (inst, u) in enumerate(((base, u0), (other, u1))):
         one = _prop([inst], 32, max_steps=3, ckpt_every=2)
         one.gen_screens()
-        one.select_plan(2048, 2, 0)
+        one.select_plan(2048, 2, 2)
         _fwd_adj(one, inst, u, target)
         assert np.array_equal(pair.grad_field(b), one.grad_field(0)), b
         assert np.array_equal(pair.grad_theta(b), one.grad_theta(0)), b
