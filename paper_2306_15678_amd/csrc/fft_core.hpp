@@ -278,7 +278,9 @@ struct Radices {};
 // screen (0: 4); bits 8-11 give the wavefronts per SIMD the compiler must
 // leave room for in the complex64 kernels (0: no target); bit 12 makes the
 // forward and adjoint row passes persistent and pipelined (complex64 only:
-// each workgroup loads its next row while it transforms the current one).
+// each workgroup loads its next row while it transforms the current one);
+// bit 13 recomputes each stage's LDS and twiddle addresses within the stage
+// (fewer registers held through the transform, a few more instructions).
 template <int N_, int T_, int LINES_, class Rad, int PA_ = 32, int PB_ = 0, int OPT_ = 0>
 struct Plan {
   static constexpr int N = N_;
@@ -293,6 +295,7 @@ struct Plan {
   static constexpr int ADJ_BATCH = ((OPT_ >> 4) & 15) ? ((OPT_ >> 4) & 15) : 4;
   static constexpr int WAVES_PER_EU = ((OPT_ >> 8) & 15) ? ((OPT_ >> 8) & 15) : 1;
   static constexpr bool PIPE = (OPT_ & 0x1000) != 0;
+  static constexpr bool LAUNDER = (OPT_ & 0x2000) != 0;
   using radices = Rad;
   static_assert(N_ % T_ == 0, "T must divide N");
 };
@@ -381,9 +384,13 @@ __device__ __forceinline__ void load_twiddles(cx<R>* w, int t, const cx<R>* __re
 // here from the table before the stage's LDS reads so that their latency
 // overlaps the exchange.
 template <typename R, int N, int T, int RAD, int NS, int DIR, bool FIRST,
-          bool LAST, bool LATE, class Lds>
+          bool LAST, bool LATE, class Lds, bool LAUNDER = false>
 __device__ __forceinline__ void fft_stage(cx<R>* v, int t, const Lds& lds,
                                           const cx<R>* wpre, const cx<R>* __restrict__ tw) {
+  // LAUNDER: the thread index made opaque per stage, so the stage's LDS
+  // and twiddle addresses are computed where they are used instead of
+  // held in registers from the kernel's start
+  if constexpr (LAUNDER) asm volatile("" : "+v"(t));
   constexpr int E = N / T;
   constexpr int NB = E / RAD;
   constexpr int STRIDE = N / RAD;
@@ -432,23 +439,24 @@ __device__ __forceinline__ void fft_stage(cx<R>* v, int t, const Lds& lds,
   }
 }
 
-template <typename R, int N, int T, int DIR, int NS, bool FIRST, bool LATE, class Lds,
-          int R0, int... Rest>
+template <typename R, int N, int T, int DIR, int NS, bool FIRST, bool LATE, bool LAUNDER,
+          class Lds, int R0, int... Rest>
 __device__ __forceinline__ void fft_stages(cx<R>* v, int t, const Lds& lds,
                                            const cx<R>* w, const cx<R>* __restrict__ tw) {
   constexpr bool LAST = sizeof...(Rest) == 0;
-  fft_stage<R, N, T, R0, NS, DIR, FIRST, LAST, LATE>(v, t, lds, w, tw);
+  fft_stage<R, N, T, R0, NS, DIR, FIRST, LAST, LATE, Lds, LAUNDER>(v, t, lds, w, tw);
   if constexpr (!LAST) {
     constexpr int used = (!LATE && NS > 1) ? (N / T / R0) * (R0 - 1) : 0;
-    fft_stages<R, N, T, DIR, NS * R0, false, LATE, Lds, Rest...>(v, t, lds, w + used, tw);
+    fft_stages<R, N, T, DIR, NS * R0, false, LATE, LAUNDER, Lds, Rest...>(v, t, lds, w + used,
+                                                                         tw);
   }
 }
 
-template <typename R, int N, int T, int DIR, bool LATE, class Lds, int... Rs>
+template <typename R, int N, int T, int DIR, bool LATE, bool LAUNDER, class Lds, int... Rs>
 __device__ __forceinline__ void fft_line_impl(cx<R>* v, int t, const Lds& lds,
                                               const cx<R>* w, const cx<R>* __restrict__ tw,
                                               Radices<Rs...>) {
-  fft_stages<R, N, T, DIR, 1, true, LATE, Lds, Rs...>(v, t, lds, w, tw);
+  fft_stages<R, N, T, DIR, 1, true, LATE, LAUNDER, Lds, Rs...>(v, t, lds, w, tw);
 }
 
 // In-register FFT of one line (DIR = -1 forward, +1 inverse, unscaled),
@@ -458,7 +466,8 @@ __device__ __forceinline__ void fft_line_impl(cx<R>* v, int t, const Lds& lds,
 template <typename R, class P, int DIR, class Lds>
 __device__ __forceinline__ void fft_line(cx<R>* v, int t, const Lds& lds, const cx<R>* w,
                                          const cx<R>* __restrict__ tw) {
-  fft_line_impl<R, P::N, P::T, DIR, P::LATE_TW>(v, t, lds, w, tw, typename P::radices{});
+  fft_line_impl<R, P::N, P::T, DIR, P::LATE_TW, P::LAUNDER>(v, t, lds, w, tw,
+                                                             typename P::radices{});
 }
 
 // ------------------------------------------- twiddles staged in LDS

@@ -1,9 +1,10 @@
 // plans.hpp -- compiled FFT tile variants of the row and column passes.
 //
 // Rows: X(N, variant, T, LINES, OPT, radices...); columns: X(N, variant,
-// T, W, A, B, OPT, radices...).  OPT: 1 = late twiddles, plus 0x100 times the
-// wavefronts per SIMD the compiler must leave room for, 0x1000 = persistent
-// pipelined forward and adjoint row passes (complex64; see Plan).  T
+// T, W, A, B, OPT, radices...).  OPT: 1 = late twiddles, 2 = late
+// propagator, plus 0x100 times the wavefronts per SIMD the compiler must
+// leave room for, 0x1000 = persistent pipelined passes (complex64),
+// 0x2000 = per-stage address computation (see Plan).  T
 // threads per line, LINES lines per workgroup (rows:
 // LINES consecutive rows; columns: W adjacent columns, read as
 // W * sizeof(complex) contiguous bytes per row), radix plan in stage order.
@@ -63,9 +64,11 @@ namespace ssfm {
   X(1024, 3, 256, 2, 16, 6, 0, 4, 4, 4, 4, 4) \
   X(1024, 4, 64, 8, 4, 2, 0, 16, 8, 8) \
   X(1024, 5, 32, 8, 4, 1, 0, 32, 32) \
+  X(1024, 6, 64, 16, 4, 4, 0x2403, 16, 8, 8) \
   X(2048, 0, 128, 2, 16, 2, 0, 16, 16, 8) \
   X(2048, 1, 256, 2, 16, 2, 0, 8, 8, 8, 4) \
   X(2048, 2, 256, 2, 16, 2, 0x1000, 8, 8, 8, 4) \
+  X(2048, 3, 128, 8, 4, 2, 0x2403, 16, 16, 8) \
   X(4096, 0, 256, 2, 16, 2, 0, 16, 16, 16) \
   X(4096, 1, 512, 2, 16, 2, 0, 8, 8, 8, 8) \
   X(4096, 2, 256, 2, 16, 2, 0x203, 16, 16, 16) \
@@ -73,7 +76,9 @@ namespace ssfm {
   X(4096, 4, 128, 2, 16, 2, 0x203, 16, 16, 16) \
   X(4096, 5, 128, 4, 16, 2, 0x203, 16, 16, 16) \
   X(4096, 6, 512, 2, 16, 2, 0x1000, 8, 8, 8, 8) \
-  X(4096, 7, 256, 2, 16, 2, 0x1000, 16, 16, 16)
+  X(4096, 7, 256, 2, 16, 2, 0x1000, 16, 16, 16) \
+  X(4096, 8, 256, 4, 8, 2, 0x2403, 16, 16, 16) \
+  X(4096, 9, 256, 4, 16, 2, 0x2403, 16, 16, 16)
 
 // LDS of a pass workgroup (line tiles, plus the FP64 reduction scratch)
 // against the 160 KiB a gfx950 workgroup may allocate.

@@ -61,6 +61,8 @@ def kernel_kind(name: str):
     base = name.split("<")[0].split("::")[-1].strip()
     if base == "k_copy":
         return "copy"
+    if base in ("k_row_pipe", "k_col_pipe"):  # persistent forms of the same passes
+        base = base[:-len("_pipe")]
     if base in ("k_row", "k_col"):
         tail = name.rsplit(",", 1)[-1]
         digits = "".join(ch for ch in tail if ch.isdigit())

@@ -373,35 +373,36 @@ def _fwd_adj(p, inst, u0, target):
     return loss, p.grad_field(0), p.grad_theta(0)
 
 
-@pytest.fixture(scope="module")
-def adj2048_oracle():
-    inst, u0, target = _adjoint_variant_case(2048)
+@pytest.fixture(scope="module", params=[1024, 2048])
+def adj_oracle(request):
+    inst, u0, target = _adjoint_variant_case(request.param)
     screens = T.instance_screens(inst)
     return (inst, u0, target), M.gradient(u0, inst, screens=screens,
                                           cotangent=lambda u: M.fluence_loss(u, target))
 
 
-def test_every_variant_adjoint_2048_matches_oracle(adj2048_oracle):
+def test_every_variant_adjoint_matches_oracle(adj_oracle):
     """FP32 forward + adjoint with each row variant used for both row passes
     (column variant 0), then each column variant for both column passes (row
     variant 0), against the FP64 oracle gradient: loss, gradient of U0 and
     of theta to the FP32 gradient tolerance (1e-4, as for the 256^2
     gradient case), the field gradient also pointwise."""
     from paper_2306_15678_amd.march import plan_variants
-    (inst, u0, target), (loss_o, g_u0, g_th) = adj2048_oracle
-    n_row, n_col = plan_variants(2048, 32)
+    (inst, u0, target), (loss_o, g_u0, g_th) = adj_oracle
+    n = inst.n
+    n_row, n_col = plan_variants(n, 32)
     p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=2)
     p.gen_screens()
     combos = [(r, 0) for r in range(n_row)] + [(0, c) for c in range(1, n_col)]
     for r, c in combos:
-        p.select_plan(2048, r, c)
-        p.select_adjoint_plan(2048, -1, -1)
+        p.select_plan(n, r, c)
+        p.select_adjoint_plan(n, -1, -1)
         loss, gg, gt = _fwd_adj(p, inst, u0, target)
         lerr = abs(loss / loss_o - 1)
         ferr = M.rel_l2(gg, g_u0)
         fmax = _maxrel(gg, g_u0)
         terr = float(np.max(np.abs(gt - g_th)) / np.max(np.abs(g_th)))
-        _report(f"adjoint variants n=2048 row={r} col={c}", loss=lerr, g_u0=ferr,
+        _report(f"adjoint variants n={n} row={r} col={c}", loss=lerr, g_u0=ferr,
                 g_u0_max=fmax, g_theta=terr)
         assert lerr < 1e-4 and ferr < 1e-4 and terr < 1e-4, (r, c)
         assert fmax < MAX_OVER_L2 * 1e-4, (r, c)
