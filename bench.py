@@ -51,6 +51,9 @@ SAMPLE_EVERY = 8
 # the length of the short forward+adjoint compared within the horizon
 SNAP_STEPS = (5, 10, 20, 50, 100, 150, 200, 300, 500, 1000, 2000, 5000)
 SHORT_STEPS = 100
+# device memory left outside the headline march's workspace (torch's own
+# allocations, the runtime, the timing events)
+WORKSPACE_RESERVE = 20 * 2 ** 30
 # algorithmic HBM bytes per grid point of one launch (complex64): a pass
 # reads and writes the field; the adjoint row pass also reads the stored
 # pre-screen field
@@ -107,13 +110,15 @@ def run_headline(args):
 
     def make(precision):
         # checkpoints every M steps, the last K segments kept whole: the
-        # layout that fits three quarters of the free HBM and recomputes the
-        # fewest steps (or plain checkpointing every --ckpt-every steps)
+        # layout that fits the free HBM less WORKSPACE_RESERVE and
+        # recomputes the fewest steps (or plain checkpointing every
+        # --ckpt-every steps)
         if args.ckpt_every:
             m, k = args.ckpt_every, 0
             rec = _ckpt_plan(z_steps, m)[1]
         else:
-            m, k, rec = checkpoint_plan(_desc_list([inst]), precision, z_steps)
+            budget = torch.cuda.mem_get_info()[0] - WORKSPACE_RESERVE
+            m, k, rec = checkpoint_plan(_desc_list([inst]), precision, z_steps, budget)
         p = Propagator(_desc_list([inst]), precision=precision, max_steps=z_steps,
                        ckpt_every=m, stored_segments=k, device=dev)
         tuned = tune(p, reps=10, use_cache=False)[n]

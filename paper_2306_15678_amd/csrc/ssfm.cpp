@@ -92,7 +92,7 @@ int validate_desc(const ssfm_instance_desc* d, int32_t n_inst, int32_t precision
 // Device-side layout of everything a context keeps in the workspace.
 struct Layout {
   size_t inst, steps, work, wbegin_row, wbegin_col, tables;
-  size_t S, Wk, Wk2, Lam, ckpt, stack, screens, stage, diag_part, diag, theta_acc,
+  size_t S, Wk, Lam, ckpt, stack, screens, stage, diag_part, diag, theta_acc,
       theta_out, seed_loss, seed_theta, scal, sumsq_part, lens_inst, half_inst, back_inst,
       fd_inst, subh, subh_beams;
   size_t total;
@@ -408,10 +408,9 @@ int plan_layout(const ssfm_instance_desc* d, int n_inst, int precision, int64_t 
   l.tables = take(el * te);
   l.S = take(el * fe);
   l.Wk = take(el * fe);
-  // with more than one segment, the recompute of the next segment runs
-  // beside the adjoint of the current one: a second work buffer and a
-  // second bank of segment slots
-  l.Wk2 = take(l.n_ckpt > 1 ? el * fe : 0);
+  // (with more than one segment the recompute of the next segment runs
+  // beside the adjoint of the current one, in its own bank of segment
+  // slots; both work in place)
   l.Lam = take(max_steps > 0 ? el * fe : 0);
   l.ckpt = take(el * fe * l.n_ckpt);
   l.stack = take(el * fe * l.n_stack * (l.n_banks + l.n_kept));
@@ -592,7 +591,10 @@ template <typename R>
 int fwd_step(ssfm_ctx* c, const void* src, void* dst, int64_t pending_step, double* part,
              void* work = nullptr, hipStream_t st = nullptr,
              const ssfm_ctx::PassSample* ts = nullptr) {
-  if (!work) work = c->field(c->L.Wk);
+  // both passes transform whole lines, each read and written by one
+  // workgroup, so the row pass can write straight into dst and the column
+  // pass finish there in place: two field streams per step instead of three
+  if (!work) work = dst;
   if (!st) st = c->stream;
   PassArgs<R> a = base_args<R>(c);
   a.src = src;
@@ -615,12 +617,13 @@ template <typename R>
 int adj_step(ssfm_ctx* c, const void* sv, int64_t pending_step,
              const ssfm_ctx::PassSample* ts = nullptr) {
   const size_t ng = c->groups.size();
+  // both passes in place on the cotangent (whole lines per workgroup)
   PassArgs<R> a = base_args<R>(c);
   a.src = c->field(c->L.Lam);
-  a.dst = c->field(c->L.Wk);
+  a.dst = c->field(c->L.Lam);
   if (int r = run_pass<R>(c, COL_ADJ, a, nullptr, ts ? ts->ev.data() : nullptr)) return r;
   PassArgs<R> b = base_args<R>(c);
-  b.src = c->field(c->L.Wk);
+  b.src = c->field(c->L.Lam);
   b.dst = c->field(c->L.Lam);
   b.aux = sv;
   b.step = pending_step;
@@ -963,13 +966,13 @@ int enqueue_backward(ssfm_ctx* c) {
     if (i == 0) return c->field(c->L.ckpt, k);
     return slot(k, i - 1);
   };
-  auto recompute = [&](int64_t k, void* work, hipStream_t st) -> int {
+  auto recompute = [&](int64_t k, hipStream_t st) -> int {
     const int64_t s0 = k * M;
     const int64_t len = std::min<int64_t>(M, n - s0);
     for (int64_t i = 0; i + 1 < len; ++i) {
       const int64_t g = s0 + i;
       const int64_t pend = rec_pending(c, step0, step0 + g);
-      if (int r = fwd_step<R>(c, sv(k, i), slot(k, i), pend, nullptr, work, st)) return r;
+      if (int r = fwd_step<R>(c, sv(k, i), slot(k, i), pend, nullptr, nullptr, st)) return r;
     }
     return SSFM_OK;
   };
@@ -979,14 +982,14 @@ int enqueue_backward(ssfm_ctx* c) {
   if (c->strang)
     if (int r = half_step_lam<R>(c, true)) return r;
   if (g.recomputed(n_seg - 1)) {
-    if (int r = recompute(n_seg - 1, c->field(c->L.Wk), c->stream)) return r;
+    if (int r = recompute(n_seg - 1, c->stream)) return r;
   }
   for (int64_t k = n_seg - 1; k >= 0; --k) {
     const bool overlap = k >= 1 && g.recomputed(k - 1);
     if (overlap) {
       HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
       HIP_TRY(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-      if (int r = recompute(k - 1, c->field(c->L.Wk2), c->aux)) return r;
+      if (int r = recompute(k - 1, c->aux)) return r;
       HIP_TRY(hipEventRecord(c->ev_join, c->aux));
     }
     const int64_t s0 = k * M;
