@@ -280,7 +280,10 @@ struct Radices {};
 // forward and adjoint row passes persistent and pipelined (complex64 only:
 // each workgroup loads its next row while it transforms the current one);
 // bit 13 recomputes each stage's LDS and twiddle addresses within the stage
-// (fewer registers held through the transform, a few more instructions).
+// (fewer registers held through the transform, a few more instructions);
+// bit 14 gives a pipelined column pass its twiddles from a quarter table
+// in LDS and loads its propagator after the forward transform (for tiles
+// that leave no LDS room for the stage tables).
 template <int N_, int T_, int LINES_, class Rad, int PA_ = 32, int PB_ = 0, int OPT_ = 0>
 struct Plan {
   static constexpr int N = N_;
@@ -296,6 +299,7 @@ struct Plan {
   static constexpr int WAVES_PER_EU = ((OPT_ >> 8) & 15) ? ((OPT_ >> 8) & 15) : 1;
   static constexpr bool PIPE = (OPT_ & 0x1000) != 0;
   static constexpr bool LAUNDER = (OPT_ & 0x2000) != 0;
+  static constexpr bool QTW = (OPT_ & 0x4000) != 0;
   using radices = Rad;
   static_assert(N_ % T_ == 0, "T must divide N");
 };
@@ -574,6 +578,94 @@ __device__ __forceinline__ void fft_line_ltw_impl(cx<R>* v, int t, const Lds& ld
 template <typename R, class P, int DIR, class Lds>
 __device__ __forceinline__ void fft_line_ltw(cx<R>* v, int t, const Lds& lds, const cx<R>* twl) {
   fft_line_ltw_impl<R, P::N, P::T, DIR>(v, t, lds, twl, typename P::radices{});
+}
+
+// ----------------------------------- twiddles from a quarter table in LDS
+// tw[m] = exp(-2 pi i m / N) for m < N/4 in LDS; the rest follow from
+// exp(-2 pi i (m + q N/4) / N) = (-i)^q exp(-2 pi i m / N), a swap and sign
+// changes.  For tiles that fill the LDS (N/4 entries instead of N - R0).
+template <typename R, int N>
+__device__ __forceinline__ cx<R> qtw(const cx<R>* twq, int m) {
+  const cx<R> a = twq[m & (N / 4 - 1)];
+  const int q = (m / (N / 4)) & 3;
+  const cx<R> b = (q & 1) ? cx<R>{a.im, -a.re} : a;
+  return (q & 2) ? cx<R>{-b.re, -b.im} : b;
+}
+
+template <typename R, int N, int THREADS>
+__device__ __forceinline__ void fill_qtw(cx<R>* twq, int t, const cx<R>* __restrict__ tw) {
+  for (int i = t; i < N / 4; i += THREADS) twq[i] = tw[i];
+}
+
+template <typename R, int N, int T, int RAD, int NS, int DIR, bool FIRST, bool LAST, class Lds>
+__device__ __forceinline__ void fft_stage_qtw(cx<R>* v, int t, const Lds& lds,
+                                              const cx<R>* twq) {
+  // the thread index made opaque per stage (addresses computed in the stage)
+  asm volatile("" : "+v"(t));
+  constexpr int E = N / T;
+  constexpr int NB = E / RAD;
+  constexpr int STRIDE = N / RAD;
+  constexpr int TWS = N / (NS * RAD);
+  static_assert(E % RAD == 0, "radix must divide points per thread");
+  cx<R> a[NB][RAD];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) {
+      if constexpr (FIRST) {
+        a[b][r] = v[b + r * NB];
+      } else {
+        a[b][r] = lds.get(t + T * b + r * STRIDE);
+      }
+    }
+  }
+  if constexpr (!FIRST) {
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = t + T * b;
+    const int k = j % NS;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        const cx<R> ww = qtw<R, N>(twq, r * k * TWS);
+        a[b][r] = (DIR > 0) ? cmulc(a[b][r], ww) : cmul(a[b][r], ww);
+      }
+    }
+    dft<RAD, DIR>(a[b]);
+    if constexpr (!LAST) {
+      const int base = (j / NS) * NS * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) lds.put(base + r * NS, a[b][r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[b + r * NB] = a[b][r];
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+  }
+}
+
+template <typename R, int N, int T, int DIR, int NS, bool FIRST, class Lds, int RA, int... Rest>
+__device__ __forceinline__ void fft_stages_qtw(cx<R>* v, int t, const Lds& lds,
+                                               const cx<R>* twq) {
+  constexpr bool LAST = sizeof...(Rest) == 0;
+  fft_stage_qtw<R, N, T, RA, NS, DIR, FIRST, LAST>(v, t, lds, twq);
+  if constexpr (!LAST) fft_stages_qtw<R, N, T, DIR, NS * RA, false, Lds, Rest...>(v, t, lds, twq);
+}
+
+template <typename R, int N, int T, int DIR, class Lds, int... Rs>
+__device__ __forceinline__ void fft_line_qtw_impl(cx<R>* v, int t, const Lds& lds,
+                                                  const cx<R>* twq, Radices<Rs...>) {
+  fft_stages_qtw<R, N, T, DIR, 1, true, Lds, Rs...>(v, t, lds, twq);
+}
+
+// fft_line with the twiddles read from the quarter table made by fill_qtw.
+template <typename R, class P, int DIR, class Lds>
+__device__ __forceinline__ void fft_line_qtw(cx<R>* v, int t, const Lds& lds, const cx<R>* twq) {
+  fft_line_qtw_impl<R, P::N, P::T, DIR>(v, t, lds, twq, typename P::radices{});
 }
 
 }  // namespace ssfm

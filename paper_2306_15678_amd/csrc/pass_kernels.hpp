@@ -601,18 +601,21 @@ __global__ void __launch_bounds__(P::THREADS)
 // g + gridDim.x, ... (a multiple of 8: an XCD's workgroups hold adjacent
 // tiles at any time, so the rows of neighbouring tiles meet in its L2),
 // the next tile's field loads in flight while the current tile is
-// transformed, the twiddles in LDS and the propagator in registers.
+// transformed.  Twiddles come from LDS: the stage tables, or (QTW plans,
+// whose tile fills the LDS) a quarter table; the propagator is held in
+// registers, or (QTW) loaded after the forward transform.
 template <typename R, class P, int KIND>
 __global__ void __launch_bounds__(P::THREADS)
     __attribute__((amdgpu_waves_per_eu(P::WAVES_PER_EU))) k_col_pipe(PassArgs<R> a) {
   static_assert(KIND == COL_FWD || KIND == COL_ADJ, "pipelined column pass: forward or adjoint");
   constexpr int N = P::N, T = P::T, E = P::E, W = P::LINES;
   constexpr bool ADJ = KIND == COL_ADJ;
+  constexpr bool QTW = P::QTW;
   constexpr int SB = (E % 4 == 0) ? 4 : E;  // power-partial batch
   constexpr uint32_t ESTRIDE = uint32_t(T) * N;
   using L = LdsPointMajor<R, W, P::PA, P::PB>;
   __shared__ cx<R> lds_mem[L::size(N)];
-  __shared__ cx<R> twl[lds_tw_entries<N>(typename P::radices{})];
+  __shared__ cx<R> twl[QTW ? N / 4 : lds_tw_entries<N>(typename P::radices{})];
   __shared__ double red[((P::THREADS + 63) / 64) * 2];
   const int nb = a.n_work, G = gridDim.x;
   auto next_item = [&](int i) {
@@ -627,6 +630,13 @@ __global__ void __launch_bounds__(P::THREADS)
   cx<R>* __restrict__ dst = static_cast<cx<R>*>(a.dst);
   const int c0 = threadIdx.x % W, t0 = threadIdx.x / W;
   const uint32_t toff0 = uint32_t(t0) * N + uint32_t(c0);
+  auto fill_twiddles = [&](int64_t off) {
+    if constexpr (QTW)
+      fill_qtw<R, N, P::THREADS>(twl, int(threadIdx.x), tables + off);
+    else
+      fill_lds_twiddles<R, N, P::THREADS>(twl, int(threadIdx.x), tables + off,
+                                          typename P::radices{});
+  };
 
   WorkItem w = load_uniform(a.work + it);
   int64_t base = load_uniform(&a.inst[w.inst].off) + w.line0;
@@ -636,10 +646,11 @@ __global__ void __launch_bounds__(P::THREADS)
   int64_t prop_off = load_uniform(&a.inst[w.inst].prop_off);
   int64_t tw_off = load_uniform(&a.inst[w.inst].tw_off);
   cx<R> pr[E];
+  if constexpr (!QTW) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) pr[e] = tables[prop_off + t0 + T * e];
-  fill_lds_twiddles<R, N, P::THREADS>(twl, int(threadIdx.x), tables + tw_off,
-                                      typename P::radices{});
+    for (int e = 0; e < E; ++e) pr[e] = tables[prop_off + t0 + T * e];
+  }
+  fill_twiddles(tw_off);
 
   for (;;) {
     // thread coordinates laundered per iteration (addresses recomputed in
@@ -661,10 +672,21 @@ __global__ void __launch_bounds__(P::THREADS)
     // every wave has read the previous tile out of LDS (and the twiddles
     // are in place)
     __syncthreads();
-    fft_line_ltw<R, P, -1>(v, t, lds, twl);
+    if constexpr (QTW) {
+      fft_line_qtw<R, P, -1>(v, t, lds, twl);
+      // after the transform: not held through it (its wait also covers the
+      // next tile's loads, issued a transform earlier)
+#pragma unroll
+      for (int e = 0; e < E; ++e) pr[e] = tables[prop_off + t + T * e];
+    } else {
+      fft_line_ltw<R, P, -1>(v, t, lds, twl);
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = ADJ ? cmulc(v[e], pr[e]) : cmul(v[e], pr[e]);
-    fft_line_ltw<R, P, +1>(v, t, lds, twl);
+    if constexpr (QTW)
+      fft_line_qtw<R, P, +1>(v, t, lds, twl);
+    else
+      fft_line_ltw<R, P, +1>(v, t, lds, twl);
 #pragma unroll
     for (int e = 0; e < E; ++e) dst[base + toff + ESTRIDE * e] = v[e];
 
@@ -712,15 +734,16 @@ __global__ void __launch_bounds__(P::THREADS)
     const int64_t po = load_uniform(&a.inst[w.inst].prop_off);
     if (po != prop_off) {
       prop_off = po;
+      if constexpr (!QTW) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) pr[e] = tables[prop_off + t + T * e];
+        for (int e = 0; e < E; ++e) pr[e] = tables[prop_off + t + T * e];
+      }
     }
     const int64_t to = load_uniform(&a.inst[w.inst].tw_off);
     if (to != tw_off) {
       tw_off = to;
       __syncthreads();
-      fill_lds_twiddles<R, N, P::THREADS>(twl, int(threadIdx.x), tables + tw_off,
-                                          typename P::radices{});
+      fill_twiddles(tw_off);
     }
   }
 }

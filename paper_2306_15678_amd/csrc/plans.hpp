@@ -4,7 +4,8 @@
 // T, W, A, B, OPT, radices...).  OPT: 1 = late twiddles, 2 = late
 // propagator, plus 0x100 times the wavefronts per SIMD the compiler must
 // leave room for, 0x1000 = persistent pipelined passes (complex64),
-// 0x2000 = per-stage address computation (see Plan).  T
+// 0x2000 = per-stage address computation, 0x4000 = quarter twiddle table
+// and late propagator in pipelined columns (see Plan).  T
 // threads per line, LINES lines per workgroup (rows:
 // LINES consecutive rows; columns: W adjacent columns, read as
 // W * sizeof(complex) contiguous bytes per row), radix plan in stage order.
@@ -68,7 +69,7 @@ namespace ssfm {
   X(2048, 0, 128, 2, 16, 2, 0, 16, 16, 8) \
   X(2048, 1, 256, 2, 16, 2, 0, 8, 8, 8, 4) \
   X(2048, 2, 256, 2, 16, 2, 0x1000, 8, 8, 8, 4) \
-  X(2048, 3, 128, 8, 4, 2, 0x2403, 16, 16, 8) \
+  X(2048, 3, 128, 8, 4, 2, 0x7403, 16, 16, 8) \
   X(4096, 0, 256, 2, 16, 2, 0, 16, 16, 16) \
   X(4096, 1, 512, 2, 16, 2, 0, 8, 8, 8, 8) \
   X(4096, 2, 256, 2, 16, 2, 0x203, 16, 16, 16) \
@@ -77,18 +78,21 @@ namespace ssfm {
   X(4096, 5, 128, 4, 16, 2, 0x203, 16, 16, 16) \
   X(4096, 6, 512, 2, 16, 2, 0x1000, 8, 8, 8, 8) \
   X(4096, 7, 256, 2, 16, 2, 0x1000, 16, 16, 16) \
-  X(4096, 8, 256, 4, 8, 2, 0x2403, 16, 16, 16) \
-  X(4096, 9, 256, 4, 16, 2, 0x2403, 16, 16, 16)
+  X(4096, 8, 256, 4, 16, 2, 0x7403, 16, 16, 16) \
+  X(4096, 9, 256, 4, 8, 2, 0x7403, 16, 16, 16)
 
 // LDS of a pass workgroup (line tiles, plus the FP64 reduction scratch)
 // against the 160 KiB a gfx950 workgroup may allocate.
 constexpr size_t kMaxLdsBytes = 160 * 1024;
-// (pipelined plans also hold the twiddles of every stage, N - R0 entries)
+// (pipelined plans also hold the twiddles of every stage, N - R0 entries,
+// or a quarter table of N / 4)
 template <typename R, class P>
 constexpr size_t plan_lds_bytes(bool column) {
   const size_t tile = column ? size_t(LdsPointMajor<R, P::LINES, P::PA, P::PB>::size(P::N))
                              : size_t(P::LINES) * LdsLineMajor<R, P::N>::LINE;
-  const size_t tw = P::PIPE ? size_t(lds_tw_entries<P::N>(typename P::radices{})) : 0;
+  const size_t tw = !P::PIPE ? 0
+                    : P::QTW ? size_t(P::N / 4)
+                             : size_t(lds_tw_entries<P::N>(typename P::radices{}));
   return (tile + tw) * sizeof(cx<R>) + sizeof(double) * 8 * ((P::THREADS + 63) / 64);
 }
 // Pipelined (persistent) plans are built for complex64 only, rows with one
