@@ -408,6 +408,32 @@ def test_every_variant_adjoint_matches_oracle(adj_oracle):
         assert fmax < MAX_OVER_L2 * 1e-4, (r, c)
 
 
+def test_precise_math_forward_adjoint_matches_oracle(adj_oracle):
+    """ssfm_set_precise_math (library sine and cosine in the screens) with the
+    last row and column variants of the size (the persistent pipelined ones
+    at 2048^2, which hand such launches to the plain kernels): FP32 forward
+    + adjoint against the FP64 oracle gradient to the FP32 gradient
+    tolerance; the setting also applies to a march whose steps were already
+    captured in graphs (the captured steps are dropped)."""
+    from paper_2306_15678_amd.march import plan_variants
+    (inst, u0, target), (loss_o, g_u0, g_th) = adj_oracle
+    n = inst.n
+    n_row, n_col = plan_variants(n, 32)
+    p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=2)
+    p.gen_screens()
+    p.select_plan(n, n_row - 1, n_col - 1)
+    fast = _fwd_adj(p, inst, u0, target)
+    p.set_precise_math(True)
+    loss, gg, gt = _fwd_adj(p, inst, u0, target)
+    lerr = abs(loss / loss_o - 1)
+    ferr = M.rel_l2(gg, g_u0)
+    terr = float(np.max(np.abs(gt - g_th)) / np.max(np.abs(g_th)))
+    _report(f"precise math n={n} row={n_row - 1} col={n_col - 1}", loss=lerr, g_u0=ferr,
+            g_theta=terr, vs_fast=M.rel_l2(gg, fast[1]))
+    assert lerr < 1e-4 and ferr < 1e-4 and terr < 1e-4
+    assert not np.array_equal(gg, fast[1])
+
+
 def test_every_variant_adjoint_4096_agrees():
     """At 4096^2 (FP64 oracle too slow for every variant): each row variant's
     and each column variant's FP32 forward + adjoint against variants
