@@ -22,6 +22,7 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -756,11 +757,18 @@ __global__ void __launch_bounds__(P::THREADS)
 // runtime's occupancy for the kernel times the compute units), rounded down
 // to a multiple of 8, and no more than the items.
 inline int resident_grid(int per_cu, int items) {
+  // compute units of the current device, looked up once per device
+  constexpr int kMaxDevices = 64;
+  static std::atomic<int> cu_count[kMaxDevices] = {};
   int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      cus < 1)
-    cus = 1;
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices) cus = cu_count[dev];
+  if (cus < 1) {
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 1;
+    else if (dev >= 0 && dev < kMaxDevices)
+      cu_count[dev] = cus;
+  }
   const int g = std::max(8, per_cu * cus / 8 * 8);
   return std::min(g, items);
 }
