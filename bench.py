@@ -654,6 +654,13 @@ def main():
             "frac": march_gbps / HBM_PEAK_GBS,
             "note": "whole-march algorithmic bytes (forward 32, adjoint 40, 32 per recomputed "
                     "step, per grid point and z step) x grid-point.steps/s over the 8 TB/s spec",
+            "survey_basis": {
+                "bytes_per_gp_step": 112.0 + 8.0 / m,
+                "frac": head["fp32"]["value"] * (112.0 + 8.0 / m) / 1e9 / HBM_PEAK_GBS,
+                "note": "the same throughput on 112 + 8/M B per grid-point step (forward with "
+                        "checkpoints, every step recomputed with its pre-screen field stored, "
+                        "adjoint reading it)",
+            },
         },
         "passes_ms": head["passes"],
         "forward_only": {"value": head["fwd"]["value"],
