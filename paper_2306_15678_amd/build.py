@@ -2,8 +2,8 @@
 
     python -m paper_2306_15678_amd.build
 
-The pass kernels are compiled in four units (row / column x complex64 /
-complex128) in parallel with the pointwise kernels and the host code, then
+The pass kernels are compiled in five units (row / column x complex64 /
+complex128, and the half-exchange column passes) in parallel with the pointwise kernels and the host code, then
 linked with hipcc.
 """
 from __future__ import annotations
@@ -24,6 +24,9 @@ ARCH = os.environ.get("SSFM_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-fPIC", "-std=c++20", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 # packed FP32 instructions are disabled for all device code
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# device units (csrc/<unit>.hip), compiled in parallel
+UNITS = ["kernels", "diagnostics", "pass_row_f32", "pass_row_f64", "pass_col_f32",
+         "pass_col_f64", "pass_col_hx_f32"]
 
 
 def _hipcc() -> str:
@@ -47,8 +50,7 @@ def build(verbose: bool = False, force: bool = True) -> str:
             return LIB
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
-    units = ["kernels", "diagnostics", "pass_row_f32", "pass_row_f64", "pass_col_f32",
-             "pass_col_f64"]
+    units = UNITS
     jobs = [[hipcc, f"--offload-arch={ARCH}", *COMMON, *DEVICE, "-c",
              os.path.join(CSRC, u + ".hip"), "-o", os.path.join(BUILD, u + ".o")] for u in units]
     jobs.append([hipcc, f"--offload-arch={ARCH}", *COMMON, "-Wall", "-c",

@@ -268,6 +268,11 @@ __device__ __forceinline__ void dft(cx<R>* v) {
 template <int... Rs>
 struct Radices {};
 
+template <int R0, int... Rest>
+constexpr int first_radix() {
+  return R0;
+}
+
 // N points per line, T threads per line, LINES lines per workgroup; column
 // tiles pad their LDS by B slots every A points (see LdsPointMajor).  OPT:
 // bit 0 set loads each stage's twiddles just before that stage (fewer live
@@ -283,7 +288,8 @@ struct Radices {};
 // (fewer registers held through the transform, a few more instructions);
 // bit 14 gives a pipelined column pass its twiddles from a quarter table
 // in LDS and loads its propagator after the forward transform (for tiles
-// that leave no LDS room for the stage tables).
+// that leave no LDS room for the stage tables); bit 15 makes a column pass
+// exchange through half its tile (fft_line_hx), complex64 only.
 template <int N_, int T_, int LINES_, class Rad, int PA_ = 32, int PB_ = 0, int OPT_ = 0>
 struct Plan {
   static constexpr int N = N_;
@@ -300,6 +306,7 @@ struct Plan {
   static constexpr bool PIPE = (OPT_ & 0x1000) != 0;
   static constexpr bool LAUNDER = (OPT_ & 0x2000) != 0;
   static constexpr bool QTW = (OPT_ & 0x4000) != 0;
+  static constexpr bool HX = (OPT_ & 0x8000) != 0;
   using radices = Rad;
   static_assert(N_ % T_ == 0, "T must divide N");
 };
@@ -666,6 +673,134 @@ __device__ __forceinline__ void fft_line_qtw_impl(cx<R>* v, int t, const Lds& ld
 template <typename R, class P, int DIR, class Lds>
 __device__ __forceinline__ void fft_line_qtw(cx<R>* v, int t, const Lds& lds, const cx<R>* twq) {
   fft_line_qtw_impl<R, P::N, P::T, DIR>(v, t, lds, twq, typename P::radices{});
+}
+
+
+// ------------------------------------ exchanges through half an LDS tile
+// A tile that would fill the LDS can exchange through half of it, so that
+// two workgroups fit one compute unit.  In a stage of radix R and span NS
+// (not the last), butterfly j writes its outputs below N/2 exactly when
+// j < N/(2R) (given N/(NS R) even), i.e. for b < NB/2 of every thread; the
+// next stage (radix R') reads point t + T b' + r' N/R', below N/2 exactly
+// when r' < R'/2.  So each exchange runs in two rounds over the same N/2
+// slots: the lower outputs are written and the lower inputs read, then the
+// upper ones, with a barrier between every write and read (four per
+// exchange, the first guarding the previous exchange's last reads).  The
+// butterflies, twiddles (quarter table) and their order are those of
+// fft_line_qtw.
+template <typename R, int N, int T, int RAD, int NS, int DIR>
+__device__ __forceinline__ void hx_butterfly(cx<R> (&y)[RAD], int j, const cx<R>* twq) {
+  constexpr int TWS = N / (NS * RAD);
+  if constexpr (NS > 1) {
+    const int k = j % NS;
+#pragma unroll
+    for (int r = 1; r < RAD; ++r) {
+      const cx<R> ww = qtw<R, N>(twq, r * k * TWS);
+      y[r] = (DIR > 0) ? cmulc(y[r], ww) : cmul(y[r], ww);
+    }
+  }
+  dft<RAD, DIR>(y);
+}
+
+template <typename R, int N, int T, int RAD, int NS, int RB, class Lds>
+__device__ __forceinline__ void hx_exchange(cx<R> (&a)[N / T / RAD][RAD],
+                                            cx<R> (&nx)[N / T / RB][RB], int t, const Lds& lds) {
+  constexpr int NB = N / T / RAD, NB2 = N / T / RB, H = N / 2;
+  static_assert(NB % 2 == 0 && RB % 2 == 0 && (N / (NS * RAD)) % 2 == 0,
+                "half exchange: even butterfly count, next radix and remaining span");
+  asm volatile("" : "+v"(t));
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+#pragma unroll
+    for (int b = h * NB / 2; b < (h + 1) * NB / 2; ++b) {
+      const int j = t + T * b;
+      const int base = (j / NS) * NS * RAD + j % NS - h * H;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) lds.put(base + r * NS, a[b][r]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < NB2; ++b) {
+#pragma unroll
+      for (int r = h * RB / 2; r < (h + 1) * RB / 2; ++r)
+        nx[b][r] = lds.get(t + T * b + r * (N / RB) - h * H);
+    }
+  }
+}
+
+// The last stage hands each butterfly's outputs to sink(b, y) as soon as
+// they are formed: y[r] is point t + T (b + r NB), NB = E / R_last.
+template <typename R, int N, int T, int DIR, int NS, class Lds, class Sink, int RA, int... Rest>
+__device__ __forceinline__ void hx_stages(cx<R> (&a)[N / T / RA][RA], int t, const Lds& lds,
+                                          const cx<R>* twq, Sink&& sink) {
+  constexpr int NB = N / T / RA;
+  // the thread index made opaque per stage (addresses computed in the stage)
+  asm volatile("" : "+v"(t));
+  if constexpr (sizeof...(Rest) == 0) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      hx_butterfly<R, N, T, RA, NS, DIR>(a[b], t + T * b, twq);
+      sink(b, a[b]);
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) hx_butterfly<R, N, T, RA, NS, DIR>(a[b], t + T * b, twq);
+    constexpr int RB = first_radix<Rest...>();
+    cx<R> nx[N / T / RB][RB];
+    hx_exchange<R, N, T, RA, NS, RB>(a, nx, t, lds);
+    hx_stages<R, N, T, DIR, NS * RA, Lds, Sink, Rest...>(nx, t, lds, twq, static_cast<Sink&&>(sink));
+  }
+}
+
+template <int... Rs>
+constexpr int last_radix() {
+  int r = 0;
+  ((r = Rs), ...);
+  return r;
+}
+
+template <class P>
+struct LastRadix;
+template <int N, int T, int L, int... Rs, int A, int B, int O>
+struct LastRadix<Plan<N, T, L, Radices<Rs...>, A, B, O>> {
+  static constexpr int value = last_radix<Rs...>();
+};
+
+template <typename R, int N, int T, int DIR, class Lds, class Sink, int R0, int... Rest>
+__device__ __forceinline__ void fft_line_hx_impl(cx<R>* v, int t, const Lds& lds,
+                                                 const cx<R>* twq, Sink&& sink,
+                                                 Radices<R0, Rest...>) {
+  constexpr int NB = N / T / R0;
+  cx<R> a[NB][R0];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+#pragma unroll
+    for (int r = 0; r < R0; ++r) a[b][r] = v[b + r * NB];
+  }
+  hx_stages<R, N, T, DIR, 1, Lds, Sink, R0, Rest...>(a, t, lds, twq, static_cast<Sink&&>(sink));
+}
+
+// fft_line with half-tile exchanges and quarter-table twiddles (lds spans
+// N/2 points of each line); the outputs go to sink(b, y) butterfly by
+// butterfly of the last stage (y[r]: point t + T (b + r NB)).
+template <typename R, class P, int DIR, class Lds, class Sink>
+__device__ __forceinline__ void fft_line_hx(cx<R>* v, int t, const Lds& lds, const cx<R>* twq,
+                                            Sink&& sink) {
+  fft_line_hx_impl<R, P::N, P::T, DIR>(v, t, lds, twq, static_cast<Sink&&>(sink),
+                                       typename P::radices{});
+}
+
+// the same with the outputs in place (v[e] = point t + T e)
+template <typename R, class P, int DIR, class Lds>
+__device__ __forceinline__ void fft_line_hx(cx<R>* v, int t, const Lds& lds, const cx<R>* twq) {
+  [&]<int... Rs>(Radices<Rs...>) {
+    constexpr int NB = P::E / last_radix<Rs...>();
+    fft_line_hx<R, P, DIR>(v, t, lds, twq, [&](int b, const auto& y) {
+#pragma unroll
+      for (int r = 0; r < last_radix<Rs...>(); ++r) v[b + r * NB] = y[r];
+    });
+  }(typename P::radices{});
 }
 
 }  // namespace ssfm

@@ -773,10 +773,17 @@ inline int resident_grid(int per_cu, int items) {
   return std::min(g, items);
 }
 
+// Column passes of half-exchange plans (their kernels are compiled in a
+// unit of their own, pass_col_hx_f32.hip).
+template <typename R, class P, int KIND>
+hipError_t launch_hx(int n_blocks, const PassArgs<R>& a, hipStream_t s, const LaunchEv* ev);
+
 template <typename R, class P, int KIND>
 hipError_t launch_one(int n_blocks, const PassArgs<R>& a, hipStream_t s, const LaunchEv* ev) {
   if constexpr (!plan_fits<R, P>(is_col_kind(KIND))) {
     return hipErrorInvalidValue;
+  } else if constexpr (P::HX) {
+    return launch_hx<R, P, KIND>(n_blocks, a, s, ev);
   } else if constexpr (P::PIPE && (KIND == ROW_FWD || KIND == ROW_ADJ)) {
     if (a.precise) {
       if (ev)

@@ -5,7 +5,8 @@
 // propagator, plus 0x100 times the wavefronts per SIMD the compiler must
 // leave room for, 0x1000 = persistent pipelined passes (complex64),
 // 0x2000 = per-stage address computation, 0x4000 = quarter twiddle table
-// and late propagator in pipelined columns (see Plan).  T
+// and late propagator in pipelined columns, 0x8000 = column exchanges
+// through half the tile (two workgroups per compute unit; see Plan).  T
 // threads per line, LINES lines per workgroup (rows:
 // LINES consecutive rows; columns: W adjacent columns, read as
 // W * sizeof(complex) contiguous bytes per row), radix plan in stage order.
@@ -79,7 +80,8 @@ namespace ssfm {
   X(4096, 6, 512, 2, 16, 2, 0x1000, 8, 8, 8, 8) \
   X(4096, 7, 256, 2, 16, 2, 0x1000, 16, 16, 16) \
   X(4096, 8, 256, 4, 16, 2, 0x7403, 16, 16, 16) \
-  X(4096, 9, 256, 4, 8, 2, 0x7403, 16, 16, 16)
+  X(4096, 9, 256, 4, 8, 2, 0x7403, 16, 16, 16) \
+  X(4096, 10, 128, 4, 16, 2, 0x8400, 16, 16, 16)
 
 // LDS of a pass workgroup (line tiles, plus the FP64 reduction scratch)
 // against the 160 KiB a gfx950 workgroup may allocate.
@@ -88,19 +90,21 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 // or a quarter table of N / 4)
 template <typename R, class P>
 constexpr size_t plan_lds_bytes(bool column) {
-  const size_t tile = column ? size_t(LdsPointMajor<R, P::LINES, P::PA, P::PB>::size(P::N))
-                             : size_t(P::LINES) * LdsLineMajor<R, P::N>::LINE;
-  const size_t tw = !P::PIPE ? 0
-                    : P::QTW ? size_t(P::N / 4)
-                             : size_t(lds_tw_entries<P::N>(typename P::radices{}));
+  const size_t tile =
+      column ? size_t(LdsPointMajor<R, P::LINES, P::PA, P::PB>::size(P::HX ? P::N / 2 : P::N))
+             : size_t(P::LINES) * LdsLineMajor<R, P::N>::LINE;
+  const size_t tw = (P::QTW || P::HX) ? size_t(P::N / 4)
+                    : !P::PIPE        ? 0
+                                      : size_t(lds_tw_entries<P::N>(typename P::radices{}));
   return (tile + tw) * sizeof(cx<R>) + sizeof(double) * 8 * ((P::THREADS + 63) / 64);
 }
 // Pipelined (persistent) plans are built for complex64 only, rows with one
-// row per workgroup.
+// row per workgroup; half-exchange plans for complex64 columns only.
 template <typename R, class P>
 constexpr bool plan_fits(bool column) {
   return plan_lds_bytes<R, P>(column) <= kMaxLdsBytes &&
-         !(P::PIPE && (sizeof(R) != 4 || (!column && P::LINES != 1)));
+         !(P::PIPE && (sizeof(R) != 4 || (!column && P::LINES != 1))) &&
+         !(P::HX && (sizeof(R) != 4 || !column));
 }
 
 template <int N, int V>

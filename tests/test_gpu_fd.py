@@ -255,7 +255,20 @@ def test_largest_grid_conserves_power():
     moved = M.rel_l2(p.field(0), u0)
     print(f"fd fp64 4096^2: power drift {drift:.2e}, field moved {moved:.2e}", flush=True)
     assert drift < 1e-12 and moved > 1e-4
+    ref = p.field(0)
     p.close()
+    # complex64 with every column variant (their solve multiplies and
+    # transforms differ only in rounding) against the complex128 march
+    from paper_2306_15678_amd.march import plan_variants
+    q = _fd([inst], 32, 12)
+    for v in range(plan_variants(4096, 32)[1]):
+        q.select_plan(4096, 0, v)
+        q.set_field(0, u0)
+        q.propagate(3)
+        err = M.rel_l2(q.field(0), ref)
+        print(f"fd fp32 4096^2 column variant {v}: {err:.2e} from fp64", flush=True)
+        assert err < 1e-5, v
+    q.close()
 
 
 def test_fluence_mismatch_after_a_finite_difference_march():

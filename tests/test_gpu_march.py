@@ -864,13 +864,17 @@ def test_config5_first_screens_match_oracle():
     amp = T.kolmogorov_amplitude(inst.n, inst.length,
                                  T.fried_parameter(k0, inst.cn2, inst.screen_dz))
     re, im = T.screen_pair(inst.n, inst.length, amp, inst.seed, 0)
+    from paper_2306_15678_amd.march import plan_variants
     p = _prop([inst], 32)
-    p.gen_screens()
-    for s, want in ((0, re), (1, im)):
-        got = p.screen(0, s)
-        err = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
-        _report(f"c5 screen {s}", maxrel=err)
-        assert err < 2e-6
+    # the column inverse transform of every column variant
+    for v in range(plan_variants(inst.n, 32)[1]):
+        p.select_plan(inst.n, 0, v)
+        p.gen_screens()
+        for s, want in ((0, re), (1, im)):
+            got = p.screen(0, s)
+            err = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+            _report(f"c5 screen {s} column variant {v}", maxrel=err)
+            assert err < 2e-6, v
 
 
 def test_config5_gradient_prefix_matches_oracle():

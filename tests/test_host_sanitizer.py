@@ -14,11 +14,11 @@ import subprocess
 
 import pytest
 
+from paper_2306_15678_amd.build import UNITS
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PKG = os.path.join(ROOT, "paper_2306_15678_amd")
 BUILD = os.path.join(PKG, "_build")
-UNITS = ["kernels", "diagnostics", "pass_row_f32", "pass_row_f64", "pass_col_f32",
-         "pass_col_f64"]
 SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
        "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host",
        "-fno-omit-frame-pointer"]
