@@ -286,9 +286,10 @@ constexpr int first_radix() {
 // each workgroup loads its next row while it transforms the current one);
 // bit 13 recomputes each stage's LDS and twiddle addresses within the stage
 // (fewer registers held through the transform, a few more instructions);
-// bit 14 gives a pipelined column pass its twiddles from a quarter table
-// in LDS and loads its propagator after the forward transform (for tiles
-// that leave no LDS room for the stage tables); bit 15 makes a column pass
+// bit 14 gives a plain row pass or a pipelined column pass its twiddles
+// from a quarter table in LDS (a pipelined column pass also loads its
+// propagator after the forward transform: its tile leaves no LDS room for
+// the stage tables); bit 15 makes a column pass
 // exchange through half its tile (fft_line_hx), complex64 only.
 template <int N_, int T_, int LINES_, class Rad, int PA_ = 32, int PB_ = 0, int OPT_ = 0>
 struct Plan {

@@ -155,6 +155,17 @@ __device__ __forceinline__ void fd_generator(const ScreenConst<R>& s, R x, R& gr
   if (tm & T_MPA) gr -= s.cM * s.inv2k1 * xk1;
 }
 
+// A line transform of a row pass: twiddles from registers / the table, or
+// (QTW plans) from the quarter table in LDS.
+template <typename R, class P, int DIR, class Lds>
+__device__ __forceinline__ void row_fft(cx<R>* v, int t, const Lds& lds, const cx<R>* wt,
+                                        const cx<R>* __restrict__ tw, const cx<R>* twq) {
+  if constexpr (P::QTW)
+    fft_line_qtw<R, P, DIR>(v, t, lds, twq);
+  else
+    fft_line<R, P, DIR>(v, t, lds, wt, tw);
+}
+
 template <class P>
 constexpr int tw_regs() {
   return TwCount<P>::value > 0 ? TwCount<P>::value : 1;
@@ -167,6 +178,7 @@ __global__ void __launch_bounds__(P::THREADS)
   constexpr int N = P::N, T = P::T, E = P::E;
   using L = LdsLineMajor<R, N>;
   __shared__ cx<R> lds_mem[P::LINES * L::LINE];
+  __shared__ cx<R> twq[P::QTW ? N / 4 : 1];
   __shared__ double red[((P::THREADS + 63) / 64) * 8];
 
   const WorkItem w = a.work[blockIdx.x];
@@ -202,6 +214,9 @@ __global__ void __launch_bounds__(P::THREADS)
     for (int e = 0; e < E; ++e) pr[e] = prop[t + T * e];
   }
   load_twiddles<R, P>(wt, t, tw);
+  // quarter twiddle table (QTW plans); the first exchange's barrier orders
+  // it before the first twiddle is read
+  if constexpr (P::QTW) fill_qtw<R, N, P::THREADS>(twq, int(threadIdx.x), tw);
   cx<R> sv[KIND == ROW_ADJ ? E : 1];
   R ph[(KIND == ROW_ADJ || KIND == ROW_FWD) ? E : 1];
   const R* plane = nullptr;
@@ -240,7 +255,7 @@ __global__ void __launch_bounds__(P::THREADS)
     cx<R> un[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) un[e] = st[toff + uint32_t(T * e)];
-    if (a.flags & FD_SPECTRAL) fft_line<R, P, +1>(v, t, lds, wt, tw);
+    if (a.flags & FD_SPECTRAL) row_fft<R, P, +1>(v, t, lds, wt, tw, twq);
     if (a.flags & FD_FINISH) {
       // U+ = 2 Ubar - U, its power partials; it is the next step's U and
       // its first Ubar
@@ -276,7 +291,7 @@ __global__ void __launch_bounds__(P::THREADS)
       gi *= R(0.5);
       v[e] = {un[e].re + (gr * v[e].re - gi * v[e].im), un[e].im + (gr * v[e].im + gi * v[e].re)};
     }
-    fft_line<R, P, -1>(v, t, lds, wt, tw);
+    row_fft<R, P, -1>(v, t, lds, wt, tw, twq);
 #pragma unroll
     for (int e = 0; e < E; ++e) dst[toff + uint32_t(T * e)] = v[e];
     return;
@@ -287,9 +302,9 @@ __global__ void __launch_bounds__(P::THREADS)
   }
 
   if constexpr (KIND == ROW_INV) {
-    fft_line<R, P, +1>(v, t, lds, wt, tw);
+    row_fft<R, P, +1>(v, t, lds, wt, tw, twq);
   } else {
-    fft_line<R, P, -1>(v, t, lds, wt, tw);
+    row_fft<R, P, -1>(v, t, lds, wt, tw, twq);
     if constexpr (P::LATE_PROP) {
       // loaded after the forward FFT: not held in registers through it
 #pragma unroll
@@ -297,7 +312,7 @@ __global__ void __launch_bounds__(P::THREADS)
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = (KIND == ROW_ADJ) ? cmulc(v[e], pr[e]) : cmul(v[e], pr[e]);
-    fft_line<R, P, +1>(v, t, lds, wt, tw);
+    row_fft<R, P, +1>(v, t, lds, wt, tw, twq);
   }
 
   if constexpr (KIND == ROW_ADJ) {
@@ -308,6 +323,12 @@ __global__ void __launch_bounds__(P::THREADS)
       for (int c = 0; c < E; c += AC) {
         if constexpr (kLateScreenInputs) load_screen_inputs(c, c + AC);
         screen_adjoint_n<R, AC>(sc, sv + c, v + c, ph + c, plane != nullptr, g);
+        // the batch's cotangent is stored now, not held through the
+        // reduction (offset laundered: formed here, not kept from the loads)
+        uint32_t to = toff;
+        asm volatile("" : "+v"(to));
+#pragma unroll
+        for (int e = c; e < c + AC; ++e) dst[to + uint32_t(T * e)] = v[e];
       }
       if (in.terms & T_ANSATZ) {
         block_reduce<8, P::THREADS, false>(g, red);
@@ -317,6 +338,7 @@ __global__ void __launch_bounds__(P::THREADS)
           for (int p = 0; p < 8; ++p) acc[p] += g[p];
         }
       }
+      return;
     }
   }
 
@@ -435,6 +457,7 @@ __global__ void __launch_bounds__(P::THREADS)
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = ADJ ? cmulc(v[e], pr[e]) : cmul(v[e], pr[e]);
     fft_line_ltw<R, P, +1>(v, t, lds, twl);
+    bool stored = false;
     if constexpr (ADJ) {
       if (a.step >= 0) {
         double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -442,9 +465,14 @@ __global__ void __launch_bounds__(P::THREADS)
 #pragma unroll
         for (int c = 0; c < E; c += AC) {
           screen_adjoint_n<R, AC, true>(sc, sv + c, v + c, ph + c, plane != nullptr, g);
+          // the batch's cotangent is stored now, not held through the
+          // reduction
+#pragma unroll
+          for (int e = c; e < c + AC; ++e) dst[base + uint32_t(t + T * e)] = v[e];
           // one batch at a time: the scheduler does not interleave batches
           __builtin_amdgcn_sched_barrier(0);
         }
+        stored = true;
         if (in.terms & T_ANSATZ) {
           // the scratch's address from a laundered zero, so its per-wave
           // slot addresses are not held in registers across the loop
@@ -459,8 +487,10 @@ __global__ void __launch_bounds__(P::THREADS)
         }
       }
     }
+    if (!stored) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) dst[base + uint32_t(t + T * e)] = v[e];
+      for (int e = 0; e < E; ++e) dst[base + uint32_t(t + T * e)] = v[e];
+    }
     if (!more) break;
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = vn[e];

@@ -4,9 +4,10 @@
 // T, W, A, B, OPT, radices...).  OPT: 1 = late twiddles, 2 = late
 // propagator, plus 0x100 times the wavefronts per SIMD the compiler must
 // leave room for, 0x1000 = persistent pipelined passes (complex64),
-// 0x2000 = per-stage address computation, 0x4000 = quarter twiddle table
-// and late propagator in pipelined columns, 0x8000 = column exchanges
-// through half the tile (two workgroups per compute unit; see Plan).  T
+// 0x2000 = per-stage address computation, 0x4000 = twiddles from a quarter
+// table in LDS (plain row passes and pipelined columns; the latter also
+// load the propagator late), 0x8000 = column exchanges through half the
+// tile (two workgroups per compute unit; see Plan).  T
 // threads per line, LINES lines per workgroup (rows:
 // LINES consecutive rows; columns: W adjacent columns, read as
 // W * sizeof(complex) contiguous bytes per row), radix plan in stage order.
@@ -49,7 +50,8 @@ namespace ssfm {
   X(4096, 4, 256, 1, 0x323, 16, 16, 16)   \
   X(4096, 5, 256, 1, 0x303, 16, 16, 16)   \
   X(4096, 6, 512, 1, 0x1000, 8, 8, 8, 8)  \
-  X(4096, 7, 512, 1, 0x1010, 8, 8, 8, 8)
+  X(4096, 7, 512, 1, 0x1010, 8, 8, 8, 8)  \
+  X(4096, 8, 256, 1, 0x4303, 16, 16, 16)
 
 #define SSFM_COL_PLANS(X)              \
   X(128, 0, 8, 32, 1, 0, 0, 16, 8) \
