@@ -593,7 +593,11 @@ int fwd_step(ssfm_ctx* c, const void* src, void* dst, int64_t pending_step, doub
              const ssfm_ctx::PassSample* ts = nullptr) {
   // both passes transform whole lines, each read and written by one
   // workgroup, so the row pass can write straight into dst and the column
-  // pass finish there in place: two field streams per step instead of three
+  // pass finish there in place.  A step into a fresh slot of the stored
+  // trajectory goes through a work buffer instead (row pass into it, column
+  // pass out of it): the column pass then reads lines the cache holds from
+  // the row pass and only its stores touch the new slot, which measures
+  // faster than column reads and writes on freshly written memory.
   if (!work) work = dst;
   if (!st) st = c->stream;
   PassArgs<R> a = base_args<R>(c);
@@ -915,9 +919,11 @@ int enqueue_record(ssfm_ctx* c, int64_t n, int64_t step0, int64_t i0, int64_t i1
     const int slot = int((i - i0) % kDiagChunk);
     double* part = c->at<double>(c->L.diag_part) + size_t(slot) * 2 * c->L.n_widx_cols;
     const int64_t pend = rec_pending(c, step0, step0 + i);
-    if (int r = fwd_step<R>(c, rec_slot(c, g, i, n), rec_slot(c, g, i + 1, n), pend, part, nullptr,
-                            nullptr, ts))
-      return r;
+    // a step whose state is kept goes through the work buffer (see
+    // fwd_step); the others run in place in S
+    void* dsl = rec_slot(c, g, i + 1, n);
+    void* wk = dsl != c->field(c->L.S) ? c->field(c->L.Wk) : nullptr;
+    if (int r = fwd_step<R>(c, rec_slot(c, g, i, n), dsl, pend, part, wk, nullptr, ts)) return r;
     if (slot == kDiagChunk - 1 || i == i1 - 1) {
       if (int r = diag_flush<R>(c, slot + 1, chunk_start)) return r;
       chunk_start = step0 + i + 1;
@@ -950,7 +956,7 @@ int do_record(ssfm_ctx* c, int64_t n) {
 
 // Backward over the recorded march, segment by segment from the last.  A
 // segment the forward did not keep whole is recomputed from its checkpoint:
-// segment k-1 on the auxiliary stream (into the other bank, with its own
+// segment k-1 on the auxiliary stream (into the other bank, through the
 // work buffer) while the adjoint of segment k runs on the main stream; the
 // two chains join before the adjoint of segment k-1.
 template <typename R>
@@ -972,7 +978,10 @@ int enqueue_backward(ssfm_ctx* c) {
     for (int64_t i = 0; i + 1 < len; ++i) {
       const int64_t g = s0 + i;
       const int64_t pend = rec_pending(c, step0, step0 + g);
-      if (int r = fwd_step<R>(c, sv(k, i), slot(k, i), pend, nullptr, nullptr, st)) return r;
+      // through the work buffer, which nothing else uses during the backward
+      // sweep (the adjoint steps run in place on the cotangent)
+      if (int r = fwd_step<R>(c, sv(k, i), slot(k, i), pend, nullptr, c->field(c->L.Wk), st))
+        return r;
     }
     return SSFM_OK;
   };
