@@ -450,6 +450,15 @@ int ssfm_measure_distance(ssfm_ctx* ctx, int32_t inst, double w_p, int32_t perio
  * FP64 contexts. */
 int ssfm_set_precise_math(ssfm_ctx* ctx, int32_t enable);
 
+/* Backward sweep schedule (section Math and Equations, the adjoint of the
+ * march with checkpoints): each checkpointed segment is recomputed after
+ * the adjoint of the following segment on the context's stream (0,
+ * default), or on a second stream while that adjoint runs (1).  The
+ * gradients are the same bitwise; the second form overlaps the two kernel
+ * chains, which pays only where neither fills the GPU (the 4096^2 passes
+ * do).  Drops the context's captured steps. */
+int ssfm_set_recompute_overlap(ssfm_ctx* ctx, int32_t enable);
+
 /* Run march steps through captured HIP graphs (1, default) or plain
  * launches (0). */
 int ssfm_use_graphs(ssfm_ctx* ctx, int32_t enable);

@@ -82,6 +82,7 @@ _SIGS = {
     "ssfm_block_mean": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
     "ssfm_use_graphs": (c_int32, [c_void_p, c_int32]),
     "ssfm_set_precise_math": (c_int32, [c_void_p, c_int32]),
+    "ssfm_set_recompute_overlap": (c_int32, [c_void_p, c_int32]),
     "ssfm_plan_variants": (c_int32, [c_int32, c_int32, POINTER(c_int32), POINTER(c_int32)]),
     "ssfm_select_plan": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
     "ssfm_time_passes": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),

@@ -161,6 +161,9 @@ struct ssfm_ctx {
   // adjoint record
   int64_t rec_steps = 0, rec_step0 = 0;
   bool rec_valid = false, seeded = false, grads_valid = false;
+  // backward sweep: recompute of the next segment on the second stream
+  // beside the adjoint of the current one (else after it, on the stream)
+  bool overlap_recompute = false;
   std::vector<char> seeded_beam;  // per beam: cotangent set since the record
   bool use_graphs = true;
   std::map<std::tuple<int, int64_t, int64_t, int64_t, int64_t>, hipGraphExec_t> graphs;
@@ -955,10 +958,11 @@ int do_record(ssfm_ctx* c, int64_t n) {
 }
 
 // Backward over the recorded march, segment by segment from the last.  A
-// segment the forward did not keep whole is recomputed from its checkpoint:
-// segment k-1 on the auxiliary stream (into the other bank, through the
-// work buffer) while the adjoint of segment k runs on the main stream; the
-// two chains join before the adjoint of segment k-1.
+// segment the forward did not keep whole is recomputed from its checkpoint
+// (into the other bank, through the work buffer): segment k-1 after the
+// adjoint of segment k on the same stream, or (overlap_recompute) on the
+// auxiliary stream while the adjoint of segment k runs on the main stream,
+// the two chains joining before the adjoint of segment k-1.
 template <typename R>
 int enqueue_backward(ssfm_ctx* c) {
   const int64_t n = c->rec_steps, step0 = c->rec_step0;
@@ -994,7 +998,8 @@ int enqueue_backward(ssfm_ctx* c) {
     if (int r = recompute(n_seg - 1, c->stream)) return r;
   }
   for (int64_t k = n_seg - 1; k >= 0; --k) {
-    const bool overlap = k >= 1 && g.recomputed(k - 1);
+    const bool rec_prev = k >= 1 && g.recomputed(k - 1);
+    const bool overlap = rec_prev && c->overlap_recompute;
     if (overlap) {
       HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
       HIP_TRY(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
@@ -1012,7 +1017,11 @@ int enqueue_backward(ssfm_ctx* c) {
       if (int r = adj_step<R>(c, sv(k, i), pend, sample ? &ps : nullptr)) return r;
       if (sample) c->adj_samples.push_back(std::move(ps));
     }
-    if (overlap) HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    if (overlap) {
+      HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    } else if (rec_prev) {
+      if (int r = recompute(k - 1, c->stream)) return r;
+    }
   }
   // Strang: V_0 = L(dz/2) U_0, so dL/dU_0 = L(-dz/2) dL/dV_0
   if (c->strang)
@@ -2023,6 +2032,14 @@ int ssfm_block_mean(ssfm_ctx* c, const double* src, int32_t n, int32_t b, double
   if (!src || !dst) return fail(SSFM_EINVAL, "src/dst is NULL");
   if (n < 1 || b < 1 || n % b) return fail(SSFM_EINVAL, "block %d must divide n=%d", b, n);
   HIP_TRY(launch_block_mean(src, n, b, dst, c->stream));
+  return SSFM_OK;
+}
+
+int ssfm_set_recompute_overlap(ssfm_ctx* c, int32_t enable) {
+  if (int r = check_ctx(c)) return r;
+  c->overlap_recompute = enable != 0;
+  // captured backward sweeps hold the previous schedule
+  clear_graphs(c);
   return SSFM_OK;
 }
 

@@ -199,6 +199,12 @@ class Propagator:
     def set_precise_math(self, enable: bool) -> None:
         L.call("ssfm_set_precise_math", self.ctx, 1 if enable else 0)
 
+    def set_recompute_overlap(self, enable: bool) -> None:
+        """Recompute checkpointed segments on a second stream beside the
+        adjoint (True) or after it on the context's stream (False, default);
+        the gradients are the same bitwise."""
+        L.call("ssfm_set_recompute_overlap", self.ctx, 1 if enable else 0)
+
     def use_graphs(self, enable: bool) -> None:
         L.call("ssfm_use_graphs", self.ctx, 1 if enable else 0)
 

@@ -172,6 +172,7 @@ int main() {
   EXPECT(ssfm_measure_vector(nullptr, &x, 128, 1.0, 1.0, 0, th) == SSFM_EINVAL);
   EXPECT(ssfm_measure_distance(nullptr, 0, 1.0, 0, th, &y, th) == SSFM_EINVAL);
   EXPECT(ssfm_set_precise_math(nullptr, 1) == SSFM_EINVAL);
+  EXPECT(ssfm_set_recompute_overlap(nullptr, 1) == SSFM_EINVAL);
   EXPECT(ssfm_use_graphs(nullptr, 1) == SSFM_EINVAL);
   EXPECT(ssfm_select_plan(nullptr, 128, 0, 0) == SSFM_EINVAL);
   EXPECT(ssfm_select_adjoint_plan(nullptr, 128, 0, 0) == SSFM_EINVAL);

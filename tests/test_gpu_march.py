@@ -245,23 +245,28 @@ def test_gradient_matches_oracle(precision, ckpt, turb):
 
 @pytest.mark.parametrize("graphs", [True, False])
 def test_checkpointed_and_stored_adjoints_are_bitwise_equal(graphs):
-    """3 segments (recompute of the next segment overlapped with the adjoint
-    of the current one on a second stream) against all steps stored."""
+    """3 segments, each recomputed after the adjoint of the next one or
+    (overlap) on a second stream beside it, against all steps stored; the
+    overlap setting also switched on a context whose backward sweep was
+    already captured."""
     inst = _grad_case()
     u0 = W.initial_field(inst)
     target = W.synthetic_target(inst, 5)
     res = []
-    for ckpt in (3, 100):
+    for ckpt, overlap in ((3, False), (3, True), (100, False)):
         p = _prop([inst], 32, max_steps=inst.n_steps, ckpt_every=ckpt)
         p.use_graphs(graphs)
-        p.set_field(0, u0)
-        p.set_theta(0, inst.theta)
-        p.forward_record(inst.n_steps)
-        p.fluence_loss(0, target)
-        p.backward()
+        for ov in ((not overlap, overlap) if ckpt == 3 else (overlap,)):
+            p.set_recompute_overlap(ov)
+            p.set_field(0, u0)
+            p.set_theta(0, inst.theta)
+            p.forward_record(inst.n_steps)
+            p.fluence_loss(0, target)
+            p.backward()
         res.append((p.grad_field(0), p.grad_theta(0)))
-    assert np.array_equal(res[0][0], res[1][0])
-    assert np.array_equal(res[0][1], res[1][1])
+    for r in res[:2]:
+        assert np.array_equal(r[0], res[2][0])
+        assert np.array_equal(r[1], res[2][1])
 
 
 def test_external_cotangent_matches_loss_seed():
