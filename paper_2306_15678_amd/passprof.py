@@ -31,7 +31,8 @@ import sys
 # The sources the row and column pass kernels are compiled from.
 PASS_SOURCES = ("fft_core.hpp", "plans.hpp", "screen.hpp", "internal.hpp", "kernels.hpp",
                 "pass_kernels.hpp", "pass_row_f32.hip", "pass_row_f64.hip",
-                "pass_col_f32.hip", "pass_col_f64.hip")
+                "pass_col_f32.hip", "pass_col_f64.hip", "pass_col_hx.hpp",
+                "pass_col_hx_f32.hip")
 
 
 FD_ITERS = 4  # fixed-point iterations per finite-difference step
@@ -63,6 +64,8 @@ def kernel_kind(name: str):
         return "copy"
     if base in ("k_row_pipe", "k_col_pipe"):  # persistent forms of the same passes
         base = base[:-len("_pipe")]
+    if base == "k_col_hx":  # column passes exchanging through half the tile
+        base = "k_col"
     if base in ("k_row", "k_col"):
         tail = name.rsplit(",", 1)[-1]
         digits = "".join(ch for ch in tail if ch.isdigit())
