@@ -329,7 +329,12 @@ template <typename R, int W, int A, int B>
 struct LdsPointMajor {
   static constexpr int size(int n) { return n * W + (n / A) * B; }
   cx<R>* base;  // already offset by the column index
-  __device__ __forceinline__ int idx(int p) const { return p * W + (p / A) * B; }
+  // unsigned (p >= 0): the division is a shift, and constant offsets of p
+  // that are multiples of A fold into the instruction's offset
+  __device__ __forceinline__ int idx(int p) const {
+    const unsigned u = unsigned(p);
+    return int(u * W + (u / A) * B);
+  }
   __device__ __forceinline__ cx<R> get(int p) const { return base[idx(p)]; }
   __device__ __forceinline__ void put(int p, cx<R> v) const { base[idx(p)] = v; }
 };
@@ -542,8 +547,8 @@ __device__ __forceinline__ void fft_stage_ltw(cx<R>* v, int t, const Lds& lds,
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int j = t + T * b;
-    const int k = j % NS;
+    const unsigned j = unsigned(t + T * b);  // j >= 0: shifts and masks
+    const int k = int(j % NS);
     if constexpr (NS > 1) {
 #pragma unroll
       for (int r = 1; r < RAD; ++r) {
@@ -553,7 +558,7 @@ __device__ __forceinline__ void fft_stage_ltw(cx<R>* v, int t, const Lds& lds,
     }
     dft<RAD, DIR>(a[b]);
     if constexpr (!LAST) {
-      const int base = (j / NS) * NS * RAD + k;
+      const int base = int(j / NS) * NS * RAD + k;
 #pragma unroll
       for (int r = 0; r < RAD; ++r) lds.put(base + r * NS, a[b][r]);
     } else {
@@ -594,8 +599,9 @@ __device__ __forceinline__ void fft_line_ltw(cx<R>* v, int t, const Lds& lds, co
 // changes.  For tiles that fill the LDS (N/4 entries instead of N - R0).
 template <typename R, int N>
 __device__ __forceinline__ cx<R> qtw(const cx<R>* twq, int m) {
-  const cx<R> a = twq[m & (N / 4 - 1)];
-  const int q = (m / (N / 4)) & 3;
+  const unsigned u = unsigned(m);  // m >= 0
+  const cx<R> a = twq[u & (N / 4 - 1)];
+  const unsigned q = (u / (N / 4)) & 3;
   const cx<R> b = (q & 1) ? cx<R>{a.im, -a.re} : a;
   return (q & 2) ? cx<R>{-b.re, -b.im} : b;
 }
@@ -632,8 +638,8 @@ __device__ __forceinline__ void fft_stage_qtw(cx<R>* v, int t, const Lds& lds,
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int j = t + T * b;
-    const int k = j % NS;
+    const unsigned j = unsigned(t + T * b);  // j >= 0: shifts and masks
+    const int k = int(j % NS);
     if constexpr (NS > 1) {
 #pragma unroll
       for (int r = 1; r < RAD; ++r) {
@@ -643,7 +649,7 @@ __device__ __forceinline__ void fft_stage_qtw(cx<R>* v, int t, const Lds& lds,
     }
     dft<RAD, DIR>(a[b]);
     if constexpr (!LAST) {
-      const int base = (j / NS) * NS * RAD + k;
+      const int base = int(j / NS) * NS * RAD + k;
 #pragma unroll
       for (int r = 0; r < RAD; ++r) lds.put(base + r * NS, a[b][r]);
     } else {
@@ -693,7 +699,9 @@ template <typename R, int N, int T, int RAD, int NS, int DIR>
 __device__ __forceinline__ void hx_butterfly(cx<R> (&y)[RAD], int j, const cx<R>* twq) {
   constexpr int TWS = N / (NS * RAD);
   if constexpr (NS > 1) {
-    const int k = j % NS;
+    // unsigned (j >= 0): butterflies T apart share k when NS divides T,
+    // and the compiler sees it
+    const int k = int(unsigned(j) % unsigned(NS));
 #pragma unroll
     for (int r = 1; r < RAD; ++r) {
       const cx<R> ww = qtw<R, N>(twq, r * k * TWS);
@@ -715,8 +723,8 @@ __device__ __forceinline__ void hx_exchange(cx<R> (&a)[N / T / RAD][RAD],
     __syncthreads();
 #pragma unroll
     for (int b = h * NB / 2; b < (h + 1) * NB / 2; ++b) {
-      const int j = t + T * b;
-      const int base = (j / NS) * NS * RAD + j % NS - h * H;
+      const unsigned j = unsigned(t + T * b);
+      const int base = int((j / NS) * NS * RAD + j % NS) - h * H;
 #pragma unroll
       for (int r = 0; r < RAD; ++r) lds.put(base + r * NS, a[b][r]);
     }
