@@ -695,7 +695,26 @@ __device__ __forceinline__ void fft_line_qtw(cx<R>* v, int t, const Lds& lds, co
 // exchange, the first guarding the previous exchange's last reads).  The
 // butterflies, twiddles (quarter table) and their order are those of
 // fft_line_qtw.
-template <typename R, int N, int T, int RAD, int NS, int DIR>
+// Twiddles of the half-exchange transforms: the quarter table (N/4
+// entries), then the second stage's own table (span R0, radix R1: entry
+// (r - 1) R0 + k holds tw[r k N/(R0 R1)]), read without the quadrant
+// rotation and by consecutive k across a wave.
+template <int N, int R0, int R1, int... Rest>
+constexpr int hx_tw_entries(Radices<R0, R1, Rest...>) {
+  return N / 4 + (R1 - 1) * R0;
+}
+
+template <typename R, int N, int THREADS, int R0, int R1, int... Rest>
+__device__ __forceinline__ void fill_hx_twiddles(cx<R>* twl, int t, const cx<R>* __restrict__ tw,
+                                                 Radices<R0, R1, Rest...>) {
+  fill_qtw<R, N, THREADS>(twl, t, tw);
+  for (int i = t; i < (R1 - 1) * R0; i += THREADS) {
+    const int r = i / R0 + 1, k = i % R0;
+    twl[N / 4 + i] = tw[r * k * (N / (R0 * R1))];
+  }
+}
+
+template <typename R, int N, int T, int RAD, int NS, int R0, int DIR>
 __device__ __forceinline__ void hx_butterfly(cx<R> (&y)[RAD], int j, const cx<R>* twq) {
   constexpr int TWS = N / (NS * RAD);
   if constexpr (NS > 1) {
@@ -704,7 +723,11 @@ __device__ __forceinline__ void hx_butterfly(cx<R> (&y)[RAD], int j, const cx<R>
     const int k = int(unsigned(j) % unsigned(NS));
 #pragma unroll
     for (int r = 1; r < RAD; ++r) {
-      const cx<R> ww = qtw<R, N>(twq, r * k * TWS);
+      cx<R> ww;
+      if constexpr (NS == R0)
+        ww = twq[N / 4 + (r - 1) * NS + k];
+      else
+        ww = qtw<R, N>(twq, r * k * TWS);
       y[r] = (DIR > 0) ? cmulc(y[r], ww) : cmul(y[r], ww);
     }
   }
@@ -740,7 +763,8 @@ __device__ __forceinline__ void hx_exchange(cx<R> (&a)[N / T / RAD][RAD],
 
 // The last stage hands each butterfly's outputs to sink(b, y) as soon as
 // they are formed: y[r] is point t + T (b + r NB), NB = E / R_last.
-template <typename R, int N, int T, int DIR, int NS, class Lds, class Sink, int RA, int... Rest>
+template <typename R, int N, int T, int DIR, int NS, int R0, class Lds, class Sink, int RA,
+          int... Rest>
 __device__ __forceinline__ void hx_stages(cx<R> (&a)[N / T / RA][RA], int t, const Lds& lds,
                                           const cx<R>* twq, Sink&& sink) {
   constexpr int NB = N / T / RA;
@@ -749,16 +773,17 @@ __device__ __forceinline__ void hx_stages(cx<R> (&a)[N / T / RA][RA], int t, con
   if constexpr (sizeof...(Rest) == 0) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      hx_butterfly<R, N, T, RA, NS, DIR>(a[b], t + T * b, twq);
+      hx_butterfly<R, N, T, RA, NS, R0, DIR>(a[b], t + T * b, twq);
       sink(b, a[b]);
     }
   } else {
 #pragma unroll
-    for (int b = 0; b < NB; ++b) hx_butterfly<R, N, T, RA, NS, DIR>(a[b], t + T * b, twq);
+    for (int b = 0; b < NB; ++b) hx_butterfly<R, N, T, RA, NS, R0, DIR>(a[b], t + T * b, twq);
     constexpr int RB = first_radix<Rest...>();
     cx<R> nx[N / T / RB][RB];
     hx_exchange<R, N, T, RA, NS, RB>(a, nx, t, lds);
-    hx_stages<R, N, T, DIR, NS * RA, Lds, Sink, Rest...>(nx, t, lds, twq, static_cast<Sink&&>(sink));
+    hx_stages<R, N, T, DIR, NS * RA, R0, Lds, Sink, Rest...>(nx, t, lds, twq,
+                                                             static_cast<Sink&&>(sink));
   }
 }
 
@@ -787,12 +812,13 @@ __device__ __forceinline__ void fft_line_hx_impl(cx<R>* v, int t, const Lds& lds
 #pragma unroll
     for (int r = 0; r < R0; ++r) a[b][r] = v[b + r * NB];
   }
-  hx_stages<R, N, T, DIR, 1, Lds, Sink, R0, Rest...>(a, t, lds, twq, static_cast<Sink&&>(sink));
+  hx_stages<R, N, T, DIR, 1, R0, Lds, Sink, R0, Rest...>(a, t, lds, twq,
+                                                        static_cast<Sink&&>(sink));
 }
 
-// fft_line with half-tile exchanges and quarter-table twiddles (lds spans
-// N/2 points of each line); the outputs go to sink(b, y) butterfly by
-// butterfly of the last stage (y[r]: point t + T (b + r NB)).
+// fft_line with half-tile exchanges and the twiddles of fill_hx_twiddles
+// (lds spans N/2 points of each line); the outputs go to sink(b, y)
+// butterfly by butterfly of the last stage (y[r]: point t + T (b + r NB)).
 template <typename R, class P, int DIR, class Lds, class Sink>
 __device__ __forceinline__ void fft_line_hx(cx<R>* v, int t, const Lds& lds, const cx<R>* twq,
                                             Sink&& sink) {

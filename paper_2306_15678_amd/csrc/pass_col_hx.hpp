@@ -5,8 +5,9 @@
 // partials of the forward pass), for tiles of W adjacent columns whose
 // full LDS tile would leave room for one workgroup per compute unit only.
 // The transforms exchange through N/2 points of the tile (fft_line_hx) and
-// read their twiddles from a quarter table in LDS, so the workgroup needs a
-// little over half the LDS and two of them share a compute unit: the loads,
+// read their twiddles from a quarter table and the second stage's table in
+// LDS, so the workgroup needs a little under half the LDS and two of them
+// share a compute unit: the loads,
 // LDS exchanges and arithmetic of one overlap those of the other.  The
 // propagator is read after the forward transform; the inverse transform's
 // outputs are stored (and, forward, summed into the power partials) one
@@ -25,7 +26,7 @@ __global__ void __launch_bounds__(P::THREADS)
   constexpr int SB = 4;  // power-partial batch
   using L = LdsPointMajor<R, W, P::PA, P::PB>;
   __shared__ cx<R> lds_mem[L::size(N / 2)];
-  __shared__ cx<R> twq[N / 4];
+  __shared__ cx<R> twq[hx_tw_entries<N>(typename P::radices{})];
   __shared__ double red[((P::THREADS + 63) / 64) * 2];
 
   const WorkItem w = a.work[blockIdx.x];
@@ -47,8 +48,9 @@ __global__ void __launch_bounds__(P::THREADS)
   cx<R> v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = src[toff + ESTRIDE * e];
-  // quarter twiddle table; the first exchange's barrier orders it before use
-  fill_qtw<R, N, P::THREADS>(twq, int(threadIdx.x), tables + in.tw_off);
+  // twiddle tables; the first exchange's barrier orders them before use
+  fill_hx_twiddles<R, N, P::THREADS>(twq, int(threadIdx.x), tables + in.tw_off,
+                                     typename P::radices{});
 
   // the last transform's outputs go out butterfly by butterfly (point
   // t + T (b + r NBL) of the last stage's butterfly b), so that they need

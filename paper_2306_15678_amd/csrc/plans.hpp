@@ -95,7 +95,8 @@ constexpr size_t plan_lds_bytes(bool column) {
   const size_t tile =
       column ? size_t(LdsPointMajor<R, P::LINES, P::PA, P::PB>::size(P::HX ? P::N / 2 : P::N))
              : size_t(P::LINES) * LdsLineMajor<R, P::N>::LINE;
-  const size_t tw = (P::QTW || P::HX) ? size_t(P::N / 4)
+  const size_t tw = P::HX             ? size_t(hx_tw_entries<P::N>(typename P::radices{}))
+                    : P::QTW          ? size_t(P::N / 4)
                     : !P::PIPE        ? 0
                                       : size_t(lds_tw_entries<P::N>(typename P::radices{}));
   return (tile + tw) * sizeof(cx<R>) + sizeof(double) * 8 * ((P::THREADS + 63) / 64);
