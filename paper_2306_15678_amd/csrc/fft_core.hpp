@@ -611,7 +611,36 @@ __device__ __forceinline__ void fill_qtw(cx<R>* twq, int t, const cx<R>* __restr
   for (int i = t; i < N / 4; i += THREADS) twq[i] = tw[i];
 }
 
-template <typename R, int N, int T, int RAD, int NS, int DIR, bool FIRST, bool LAST, class Lds>
+// The quarter table (N/4 entries) followed by the second stage's own
+// table (span R0, radix R1: entry (r - 1) R0 + k holds tw[r k N/(R0 R1)]),
+// which that stage reads without the quadrant rotation and by consecutive
+// k across a wave.
+template <int N, int R0, int R1, int... Rest>
+constexpr int qtw_entries(Radices<R0, R1, Rest...>) {
+  return N / 4 + (R1 - 1) * R0;
+}
+
+template <typename R, int N, int THREADS, int R0, int R1, int... Rest>
+__device__ __forceinline__ void fill_qtw_tables(cx<R>* twl, int t, const cx<R>* __restrict__ tw,
+                                                Radices<R0, R1, Rest...>) {
+  fill_qtw<R, N, THREADS>(twl, t, tw);
+  for (int i = t; i < (R1 - 1) * R0; i += THREADS) {
+    const int r = i / R0 + 1, k = i % R0;
+    twl[N / 4 + i] = tw[r * k * (N / (R0 * R1))];
+  }
+}
+
+// A twiddle of stage (span NS, radix RAD) from the tables of fill_qtw_tables.
+template <typename R, int N, int RAD, int NS, int R0>
+__device__ __forceinline__ cx<R> qtw_stage(const cx<R>* twq, int r, int k) {
+  if constexpr (NS == R0)
+    return twq[N / 4 + (r - 1) * NS + k];
+  else
+    return qtw<R, N>(twq, r * k * (N / (NS * RAD)));
+}
+
+template <typename R, int N, int T, int RAD, int NS, int R0, int DIR, bool FIRST, bool LAST,
+          class Lds>
 __device__ __forceinline__ void fft_stage_qtw(cx<R>* v, int t, const Lds& lds,
                                               const cx<R>* twq) {
   // the thread index made opaque per stage (addresses computed in the stage)
@@ -643,7 +672,7 @@ __device__ __forceinline__ void fft_stage_qtw(cx<R>* v, int t, const Lds& lds,
     if constexpr (NS > 1) {
 #pragma unroll
       for (int r = 1; r < RAD; ++r) {
-        const cx<R> ww = qtw<R, N>(twq, r * k * TWS);
+        const cx<R> ww = qtw_stage<R, N, RAD, NS, R0>(twq, r, k);
         a[b][r] = (DIR > 0) ? cmulc(a[b][r], ww) : cmul(a[b][r], ww);
       }
     }
@@ -662,21 +691,23 @@ __device__ __forceinline__ void fft_stage_qtw(cx<R>* v, int t, const Lds& lds,
   }
 }
 
-template <typename R, int N, int T, int DIR, int NS, bool FIRST, class Lds, int RA, int... Rest>
+template <typename R, int N, int T, int DIR, int NS, int R0, bool FIRST, class Lds, int RA,
+          int... Rest>
 __device__ __forceinline__ void fft_stages_qtw(cx<R>* v, int t, const Lds& lds,
                                                const cx<R>* twq) {
   constexpr bool LAST = sizeof...(Rest) == 0;
-  fft_stage_qtw<R, N, T, RA, NS, DIR, FIRST, LAST>(v, t, lds, twq);
-  if constexpr (!LAST) fft_stages_qtw<R, N, T, DIR, NS * RA, false, Lds, Rest...>(v, t, lds, twq);
+  fft_stage_qtw<R, N, T, RA, NS, R0, DIR, FIRST, LAST>(v, t, lds, twq);
+  if constexpr (!LAST)
+    fft_stages_qtw<R, N, T, DIR, NS * RA, R0, false, Lds, Rest...>(v, t, lds, twq);
 }
 
-template <typename R, int N, int T, int DIR, class Lds, int... Rs>
+template <typename R, int N, int T, int DIR, class Lds, int R0, int... Rs>
 __device__ __forceinline__ void fft_line_qtw_impl(cx<R>* v, int t, const Lds& lds,
-                                                  const cx<R>* twq, Radices<Rs...>) {
-  fft_stages_qtw<R, N, T, DIR, 1, true, Lds, Rs...>(v, t, lds, twq);
+                                                  const cx<R>* twq, Radices<R0, Rs...>) {
+  fft_stages_qtw<R, N, T, DIR, 1, R0, true, Lds, R0, Rs...>(v, t, lds, twq);
 }
 
-// fft_line with the twiddles read from the quarter table made by fill_qtw.
+// fft_line with the twiddles read from the tables made by fill_qtw_tables.
 template <typename R, class P, int DIR, class Lds>
 __device__ __forceinline__ void fft_line_qtw(cx<R>* v, int t, const Lds& lds, const cx<R>* twq) {
   fft_line_qtw_impl<R, P::N, P::T, DIR>(v, t, lds, twq, typename P::radices{});
@@ -695,39 +726,15 @@ __device__ __forceinline__ void fft_line_qtw(cx<R>* v, int t, const Lds& lds, co
 // exchange, the first guarding the previous exchange's last reads).  The
 // butterflies, twiddles (quarter table) and their order are those of
 // fft_line_qtw.
-// Twiddles of the half-exchange transforms: the quarter table (N/4
-// entries), then the second stage's own table (span R0, radix R1: entry
-// (r - 1) R0 + k holds tw[r k N/(R0 R1)]), read without the quadrant
-// rotation and by consecutive k across a wave.
-template <int N, int R0, int R1, int... Rest>
-constexpr int hx_tw_entries(Radices<R0, R1, Rest...>) {
-  return N / 4 + (R1 - 1) * R0;
-}
-
-template <typename R, int N, int THREADS, int R0, int R1, int... Rest>
-__device__ __forceinline__ void fill_hx_twiddles(cx<R>* twl, int t, const cx<R>* __restrict__ tw,
-                                                 Radices<R0, R1, Rest...>) {
-  fill_qtw<R, N, THREADS>(twl, t, tw);
-  for (int i = t; i < (R1 - 1) * R0; i += THREADS) {
-    const int r = i / R0 + 1, k = i % R0;
-    twl[N / 4 + i] = tw[r * k * (N / (R0 * R1))];
-  }
-}
-
 template <typename R, int N, int T, int RAD, int NS, int R0, int DIR>
 __device__ __forceinline__ void hx_butterfly(cx<R> (&y)[RAD], int j, const cx<R>* twq) {
-  constexpr int TWS = N / (NS * RAD);
   if constexpr (NS > 1) {
     // unsigned (j >= 0): butterflies T apart share k when NS divides T,
     // and the compiler sees it
     const int k = int(unsigned(j) % unsigned(NS));
 #pragma unroll
     for (int r = 1; r < RAD; ++r) {
-      cx<R> ww;
-      if constexpr (NS == R0)
-        ww = twq[N / 4 + (r - 1) * NS + k];
-      else
-        ww = qtw<R, N>(twq, r * k * TWS);
+      const cx<R> ww = qtw_stage<R, N, RAD, NS, R0>(twq, r, k);
       y[r] = (DIR > 0) ? cmulc(y[r], ww) : cmul(y[r], ww);
     }
   }
@@ -816,7 +823,7 @@ __device__ __forceinline__ void fft_line_hx_impl(cx<R>* v, int t, const Lds& lds
                                                         static_cast<Sink&&>(sink));
 }
 
-// fft_line with half-tile exchanges and the twiddles of fill_hx_twiddles
+// fft_line with half-tile exchanges and the twiddles of fill_qtw_tables
 // (lds spans N/2 points of each line); the outputs go to sink(b, y)
 // butterfly by butterfly of the last stage (y[r]: point t + T (b + r NB)).
 template <typename R, class P, int DIR, class Lds, class Sink>

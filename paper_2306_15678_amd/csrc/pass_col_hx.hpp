@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(P::THREADS)
   constexpr int SB = 4;  // power-partial batch
   using L = LdsPointMajor<R, W, P::PA, P::PB>;
   __shared__ cx<R> lds_mem[L::size(N / 2)];
-  __shared__ cx<R> twq[hx_tw_entries<N>(typename P::radices{})];
+  __shared__ cx<R> twq[qtw_entries<N>(typename P::radices{})];
   __shared__ double red[((P::THREADS + 63) / 64) * 2];
 
   const WorkItem w = a.work[blockIdx.x];
@@ -49,8 +49,8 @@ __global__ void __launch_bounds__(P::THREADS)
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = src[toff + ESTRIDE * e];
   // twiddle tables; the first exchange's barrier orders them before use
-  fill_hx_twiddles<R, N, P::THREADS>(twq, int(threadIdx.x), tables + in.tw_off,
-                                     typename P::radices{});
+  fill_qtw_tables<R, N, P::THREADS>(twq, int(threadIdx.x), tables + in.tw_off,
+                                    typename P::radices{});
 
   // the last transform's outputs go out butterfly by butterfly (point
   // t + T (b + r NBL) of the last stage's butterfly b), so that they need

@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(P::THREADS)
   constexpr int N = P::N, T = P::T, E = P::E;
   using L = LdsLineMajor<R, N>;
   __shared__ cx<R> lds_mem[P::LINES * L::LINE];
-  __shared__ cx<R> twq[P::QTW ? N / 4 : 1];
+  __shared__ cx<R> twq[P::QTW ? qtw_entries<N>(typename P::radices{}) : 1];
   __shared__ double red[((P::THREADS + 63) / 64) * 8];
 
   const WorkItem w = a.work[blockIdx.x];
@@ -216,7 +216,8 @@ __global__ void __launch_bounds__(P::THREADS)
   load_twiddles<R, P>(wt, t, tw);
   // quarter twiddle table (QTW plans); the first exchange's barrier orders
   // it before the first twiddle is read
-  if constexpr (P::QTW) fill_qtw<R, N, P::THREADS>(twq, int(threadIdx.x), tw);
+  if constexpr (P::QTW)
+    fill_qtw_tables<R, N, P::THREADS>(twq, int(threadIdx.x), tw, typename P::radices{});
   cx<R> sv[KIND == ROW_ADJ ? E : 1];
   R ph[(KIND == ROW_ADJ || KIND == ROW_FWD) ? E : 1];
   const R* plane = nullptr;
@@ -646,7 +647,7 @@ __global__ void __launch_bounds__(P::THREADS)
   constexpr uint32_t ESTRIDE = uint32_t(T) * N;
   using L = LdsPointMajor<R, W, P::PA, P::PB>;
   __shared__ cx<R> lds_mem[L::size(N)];
-  __shared__ cx<R> twl[QTW ? N / 4 : lds_tw_entries<N>(typename P::radices{})];
+  __shared__ cx<R> twl[QTW ? qtw_entries<N>(typename P::radices{}) : lds_tw_entries<N>(typename P::radices{})];
   __shared__ double red[((P::THREADS + 63) / 64) * 2];
   const int nb = a.n_work, G = gridDim.x;
   auto next_item = [&](int i) {
@@ -663,7 +664,8 @@ __global__ void __launch_bounds__(P::THREADS)
   const uint32_t toff0 = uint32_t(t0) * N + uint32_t(c0);
   auto fill_twiddles = [&](int64_t off) {
     if constexpr (QTW)
-      fill_qtw<R, N, P::THREADS>(twl, int(threadIdx.x), tables + off);
+      fill_qtw_tables<R, N, P::THREADS>(twl, int(threadIdx.x), tables + off,
+                                        typename P::radices{});
     else
       fill_lds_twiddles<R, N, P::THREADS>(twl, int(threadIdx.x), tables + off,
                                           typename P::radices{});

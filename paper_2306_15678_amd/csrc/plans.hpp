@@ -89,16 +89,15 @@ namespace ssfm {
 // against the 160 KiB a gfx950 workgroup may allocate.
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 // (pipelined plans also hold the twiddles of every stage, N - R0 entries,
-// or a quarter table of N / 4)
+// or a quarter table of N / 4 and the second stage's (R1 - 1) R0 entries)
 template <typename R, class P>
 constexpr size_t plan_lds_bytes(bool column) {
   const size_t tile =
       column ? size_t(LdsPointMajor<R, P::LINES, P::PA, P::PB>::size(P::HX ? P::N / 2 : P::N))
              : size_t(P::LINES) * LdsLineMajor<R, P::N>::LINE;
-  const size_t tw = P::HX             ? size_t(hx_tw_entries<P::N>(typename P::radices{}))
-                    : P::QTW          ? size_t(P::N / 4)
-                    : !P::PIPE        ? 0
-                                      : size_t(lds_tw_entries<P::N>(typename P::radices{}));
+  const size_t tw = (P::HX || P::QTW) ? size_t(qtw_entries<P::N>(typename P::radices{}))
+                    : !P::PIPE         ? 0
+                                       : size_t(lds_tw_entries<P::N>(typename P::radices{}));
   return (tile + tw) * sizeof(cx<R>) + sizeof(double) * 8 * ((P::THREADS + 63) / 64);
 }
 // Pipelined (persistent) plans are built for complex64 only, rows with one
