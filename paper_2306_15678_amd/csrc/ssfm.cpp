@@ -590,17 +590,25 @@ void clear_graphs(ssfm_ctx* c) {
   c->graphs.clear();
 }
 
+// Whether steps into fresh slots of the stored trajectory go through the
+// work buffer (see fwd_step): for beams whose field spans at least 64 MiB
+// (4096^2 complex64 and up), where it measures faster; the 1024^2 march
+// measures faster with the column pass in place on the slot.
+bool fresh_via_work(const ssfm_ctx* c) {
+  return int64_t(c->L.max_n) * c->L.max_n * int64_t(c->el) >= (int64_t(64) << 20);
+}
+
 template <typename R>
 int fwd_step(ssfm_ctx* c, const void* src, void* dst, int64_t pending_step, double* part,
              void* work = nullptr, hipStream_t st = nullptr,
              const ssfm_ctx::PassSample* ts = nullptr) {
   // both passes transform whole lines, each read and written by one
   // workgroup, so the row pass can write straight into dst and the column
-  // pass finish there in place.  A step into a fresh slot of the stored
-  // trajectory goes through a work buffer instead (row pass into it, column
-  // pass out of it): the column pass then reads lines the cache holds from
-  // the row pass and only its stores touch the new slot, which measures
-  // faster than column reads and writes on freshly written memory.
+  // pass finish there in place.  For large beams a step into a fresh slot
+  // of the stored trajectory goes through a work buffer instead (row pass
+  // into it, column pass out of it): the column pass then reads a buffer
+  // every step uses and only its stores touch the new slot, which measures
+  // faster than column reads and writes on the freshly written slot there.
   if (!work) work = dst;
   if (!st) st = c->stream;
   PassArgs<R> a = base_args<R>(c);
@@ -922,10 +930,10 @@ int enqueue_record(ssfm_ctx* c, int64_t n, int64_t step0, int64_t i0, int64_t i1
     const int slot = int((i - i0) % kDiagChunk);
     double* part = c->at<double>(c->L.diag_part) + size_t(slot) * 2 * c->L.n_widx_cols;
     const int64_t pend = rec_pending(c, step0, step0 + i);
-    // a step whose state is kept goes through the work buffer (see
-    // fwd_step); the others run in place in S
+    // a step whose state is kept goes through the work buffer for large
+    // beams (see fwd_step); the others run in place
     void* dsl = rec_slot(c, g, i + 1, n);
-    void* wk = dsl != c->field(c->L.S) ? c->field(c->L.Wk) : nullptr;
+    void* wk = (fresh_via_work(c) && dsl != c->field(c->L.S)) ? c->field(c->L.Wk) : nullptr;
     if (int r = fwd_step<R>(c, rec_slot(c, g, i, n), dsl, pend, part, wk, nullptr, ts)) return r;
     if (slot == kDiagChunk - 1 || i == i1 - 1) {
       if (int r = diag_flush<R>(c, slot + 1, chunk_start)) return r;
@@ -982,10 +990,10 @@ int enqueue_backward(ssfm_ctx* c) {
     for (int64_t i = 0; i + 1 < len; ++i) {
       const int64_t g = s0 + i;
       const int64_t pend = rec_pending(c, step0, step0 + g);
-      // through the work buffer, which nothing else uses during the backward
-      // sweep (the adjoint steps run in place on the cotangent)
-      if (int r = fwd_step<R>(c, sv(k, i), slot(k, i), pend, nullptr, c->field(c->L.Wk), st))
-        return r;
+      // large beams through the work buffer, which nothing else uses during
+      // the backward sweep (the adjoint steps run in place on the cotangent)
+      void* wk = fresh_via_work(c) ? c->field(c->L.Wk) : nullptr;
+      if (int r = fwd_step<R>(c, sv(k, i), slot(k, i), pend, nullptr, wk, st)) return r;
     }
     return SSFM_OK;
   };
