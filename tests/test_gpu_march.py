@@ -504,6 +504,39 @@ def test_pipelined_rows_batch_equals_each_beam_alone():
         assert np.array_equal(pair.grad_theta(b), one.grad_theta(0)), b
 
 
+def test_headline_variants_batch_equals_each_beam_alone():
+    """Two 4096^2 beams with different z steps in one context with the
+    tile variants the tuner picks for the 4096^2 headline (row 8: twiddles
+    in LDS; column 10: exchange through half the tile; also as the adjoint
+    passes): each workgroup reads its own beam's tables, so forward +
+    adjoint of each beam equals that beam in a context of its own,
+    bitwise."""
+    base, u0, target = _adjoint_variant_case(4096)
+    other = dataclasses.replace(base, dz=base.dz * 0.7, seed=base.seed + 1)
+    u1 = W.initial_field(other)
+    pair = _prop([base, other], 32, max_steps=3, ckpt_every=2)
+    pair.gen_screens()
+    pair.select_plan(4096, 8, 10)
+    pair.select_adjoint_plan(4096, 8, 10)
+    for b, (inst, u) in enumerate(((base, u0), (other, u1))):
+        pair.set_field(b, u)
+        pair.set_theta(b, inst.theta)
+    pair.forward_record(3)
+    pair.fluence_loss(0, target)
+    pair.fluence_loss(1, target)
+    pair.backward()
+    for b, (inst, u) in enumerate(((base, u0), (other, u1))):
+        one = _prop([inst], 32, max_steps=3, ckpt_every=2)
+        one.gen_screens()
+        one.select_plan(4096, 8, 10)
+        one.select_adjoint_plan(4096, 8, 10)
+        _fwd_adj(one, inst, u, target)
+        assert np.array_equal(pair.grad_field(b), one.grad_field(0)), b
+        assert np.array_equal(pair.grad_theta(b), one.grad_theta(0)), b
+        one.close()
+    pair.close()
+
+
 # ---------------------------------------------------------- config 3
 # 64 uneven beams (n in {256, 512, 768, 1024}) with 20 Kolmogorov screens
 # each, marched together in one context.  Checked on one beam of each size
