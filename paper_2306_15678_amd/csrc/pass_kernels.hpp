@@ -320,9 +320,14 @@ __global__ void __launch_bounds__(P::THREADS)
     if (a.step >= 0) {
       double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       constexpr int AC = (E % P::ADJ_BATCH == 0) ? P::ADJ_BATCH : E;  // points per batch
+      // late inputs: each batch's stored field and phases are requested one
+      // batch ahead, so their latency overlaps the previous batch's screen
+      if constexpr (kLateScreenInputs) load_screen_inputs(0, AC);
 #pragma unroll
       for (int c = 0; c < E; c += AC) {
-        if constexpr (kLateScreenInputs) load_screen_inputs(c, c + AC);
+        if constexpr (kLateScreenInputs) {
+          if (c + AC < E) load_screen_inputs(c + AC, c + 2 * AC);
+        }
         screen_adjoint_n<R, AC>(sc, sv + c, v + c, ph + c, plane != nullptr, g);
         // the batch's cotangent is stored now, not held through the
         // reduction (offset laundered: formed here, not kept from the loads)
